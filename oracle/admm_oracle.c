@@ -1,0 +1,705 @@
+/*
+ * admm_oracle.c -- plain double-precision CPU oracle for one ADMM iteration of
+ * Zhou & Bhattacharya, "Accelerated computational micromechanics"
+ * (arXiv 2010.06697).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library; the product path never does. It is
+ * deliberately slow and literal: direct (not fast) Fourier sums, a scalar
+ * Newton solve per voxel, plain loops in voxel order. Nothing here is shared
+ * with the HIP library.
+ *
+ * What each function follows in the paper:
+ *   or_dft3        - the discrete Fourier transform of the periodic setting,
+ *                    Sec. 2.3, written as its defining sum along each axis.
+ *   or_gradient    - the central difference of Sec. 2.3 (the first-derivative
+ *                    symbol i sin(h xi)/h) plus the prescribed mean <F>.
+ *   or_project     - Step 2 of Sec. 2.1 (Helmholtz projection), solved in
+ *                    Fourier space as in Sec. 2.3 with central-difference
+ *                    symbols; the Laplacian is taken as D_h^T D_h (the sum of
+ *                    the squared first-difference symbols), which makes Step 2
+ *                    the exact minimiser over u of the discrete augmented
+ *                    Lagrangian and keeps the multiplier divergence-free.
+ *   or_prox        - Step 1 of Sec. 2.1 (local problem): the point-wise
+ *                    stationarity condition W_F(F) - Lambda - rho(grad u - F) = 0,
+ *                    solved as the minimiser of W + rho/2 |F - A|^2.
+ *   or_admm_run    - Steps 1-4 of Sec. 2.1 in order, the multiplier update
+ *                    of Step 3, the primal/dual residuals of Step 4, and the
+ *                    adaptive penalty rule of Sec. 2.1 ("Penalty parameter").
+ *   or_mean_stress - the homogenised (average) stress of Sec. 2.3.
+ */
+#include "admm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define TWO_PI 6.283185307179586476925286766559
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3x3 helpers (row-major, A[3*i+j])                                        */
+/* ------------------------------------------------------------------------ */
+
+static double det3(const double *A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* cofactor matrix: C_ij = (-1)^(i+j) minor_ij, so that A^{-T} = C / det A */
+static void cof3(const double *A, double *C) {
+  C[0] = A[4] * A[8] - A[5] * A[7];
+  C[1] = A[5] * A[6] - A[3] * A[8];
+  C[2] = A[3] * A[7] - A[4] * A[6];
+  C[3] = A[2] * A[7] - A[1] * A[8];
+  C[4] = A[0] * A[8] - A[2] * A[6];
+  C[5] = A[1] * A[6] - A[0] * A[7];
+  C[6] = A[1] * A[5] - A[2] * A[4];
+  C[7] = A[2] * A[3] - A[0] * A[5];
+  C[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+static double dot9(const double *a, const double *b) {
+  double s = 0.0;
+  for (int k = 0; k < 9; ++k) s += a[k] * b[k];
+  return s;
+}
+
+static double norm9(const double *a) { return sqrt(dot9(a, a)); }
+
+/* ------------------------------------------------------------------------ */
+/* Constitutive models                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* |F^T n|^2 */
+static double ftn2(const double *F, const double *n, double *Ftn) {
+  double s = 0.0;
+  for (int L = 0; L < 3; ++L) {
+    double v = 0.0;
+    for (int k = 0; k < 3; ++k) v += F[3 * k + L] * n[k];
+    if (Ftn) Ftn[L] = v;
+    s += v * v;
+  }
+  return s;
+}
+
+double or_energy(const or_material *m, const double F[9], const double n[3]) {
+  double J = det3(F);
+  if (!(J > 0.0)) return INFINITY;
+  double f2 = dot9(F, F);
+  if (m->model == OR_NEOHOOKE) {
+    double lj = log(J);
+    return 0.5 * m->mu * (f2 - 3.0) - m->mu * lj + 0.5 * m->lambda * lj * lj;
+  }
+  /* OR_LCE */
+  double a13 = cbrt(m->a);
+  double t = ftn2(F, n, NULL);
+  return 0.5 * m->mu * (a13 * (f2 + (1.0 / m->a - 1.0) * t) - 3.0) +
+         0.5 * m->kappa * (J - 1.0) * (J - 1.0);
+}
+
+int or_stress(const or_material *m, const double F[9], const double n[3],
+              double P[9]) {
+  double J = det3(F);
+  if (!(J > 0.0)) return OR_EDOMAIN;
+  double C[9], G[9];
+  cof3(F, C);
+  for (int k = 0; k < 9; ++k) G[k] = C[k] / J; /* F^{-T} */
+  if (m->model == OR_NEOHOOKE) {
+    /* P = mu (F - F^{-T}) + lambda ln J F^{-T} */
+    double lj = log(J);
+    for (int k = 0; k < 9; ++k)
+      P[k] = m->mu * (F[k] - G[k]) + m->lambda * lj * G[k];
+    return OR_OK;
+  }
+  /* P = mu a^{1/3} (F + (1/a - 1) n (F^T n)) + kappa (J - 1) J F^{-T} */
+  double a13 = cbrt(m->a), Ftn[3];
+  ftn2(F, n, Ftn);
+  for (int i = 0; i < 3; ++i)
+    for (int L = 0; L < 3; ++L)
+      P[3 * i + L] = m->mu * a13 * (F[3 * i + L] + (1.0 / m->a - 1.0) * n[i] * Ftn[L]) +
+                     m->kappa * (J - 1.0) * J * G[3 * i + L];
+  return OR_OK;
+}
+
+int or_tangent(const or_material *m, const double F[9], const double n[3],
+               double Cm[81]) {
+  double J = det3(F);
+  if (!(J > 0.0)) return OR_EDOMAIN;
+  double C[9], Fi[9]; /* Fi[3*J+k] = (F^{-1})_Jk = C_kJ / det */
+  cof3(F, C);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Fi[3 * a + b] = C[3 * b + a] / J;
+  for (int i = 0; i < 3; ++i)
+    for (int Jx = 0; Jx < 3; ++Jx)
+      for (int k = 0; k < 3; ++k)
+        for (int L = 0; L < 3; ++L) {
+          double d_ik = (i == k), d_JL = (Jx == L);
+          double v;
+          if (m->model == OR_NEOHOOKE) {
+            /* mu d_ik d_JL + (mu - lambda ln J) Fi_Jk Fi_Li + lambda Fi_Ji Fi_Lk */
+            double lj = log(J);
+            v = m->mu * d_ik * d_JL +
+                (m->mu - m->lambda * lj) * Fi[3 * Jx + k] * Fi[3 * L + i] +
+                m->lambda * Fi[3 * Jx + i] * Fi[3 * L + k];
+          } else {
+            /* mu a^{1/3} (d_ik + (1/a - 1) n_i n_k) d_JL
+               + kappa [(2J - 1) J Fi_Ji Fi_Lk - (J - 1) J Fi_Jk Fi_Li] */
+            double a13 = cbrt(m->a);
+            v = m->mu * a13 * (d_ik + (1.0 / m->a - 1.0) * n[i] * n[k]) * d_JL +
+                m->kappa * ((2.0 * J - 1.0) * J * Fi[3 * Jx + i] * Fi[3 * L + k] -
+                            (J - 1.0) * J * Fi[3 * Jx + k] * Fi[3 * L + i]);
+          }
+          Cm[(3 * i + Jx) * 9 + (3 * k + L)] = v;
+        }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Director: top eigenvector of F F^T (cyclic Jacobi on a 3x3 matrix)       */
+/* ------------------------------------------------------------------------ */
+
+static void jacobi3(double B[9], double Vv[9], double w[3]) {
+  for (int k = 0; k < 9; ++k) Vv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = B[1] * B[1] + B[2] * B[2] + B[5] * B[5];
+    double dia = B[0] * B[0] + B[4] * B[4] + B[8] * B[8];
+    if (off <= 1e-34 * dia || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        double bpq = B[3 * p + q];
+        if (bpq == 0.0) continue;
+        /* rotation that zeroes B_pq */
+        double theta = (B[3 * q + q] - B[3 * p + p]) / (2.0 * bpq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        /* B <- R^T B R with R = I + (c-1)(e_p e_p + e_q e_q) + s(e_p e_q - e_q e_p) */
+        for (int k = 0; k < 3; ++k) { /* columns p, q */
+          double bkp = B[3 * k + p], bkq = B[3 * k + q];
+          B[3 * k + p] = c * bkp - s * bkq;
+          B[3 * k + q] = s * bkp + c * bkq;
+        }
+        for (int k = 0; k < 3; ++k) { /* rows p, q */
+          double bpk = B[3 * p + k], bqk = B[3 * q + k];
+          B[3 * p + k] = c * bpk - s * bqk;
+          B[3 * q + k] = s * bpk + c * bqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          double vkp = Vv[3 * k + p], vkq = Vv[3 * k + q];
+          Vv[3 * k + p] = c * vkp - s * vkq;
+          Vv[3 * k + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  w[0] = B[0];
+  w[1] = B[4];
+  w[2] = B[8];
+}
+
+int or_director(const double F[9], const double n_prev[3], double n[3]) {
+  double B[9], Vv[9], w[3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += F[3 * i + k] * F[3 * j + k];
+      B[3 * i + j] = s;
+    }
+  jacobi3(B, Vv, w);
+  int order[3] = {0, 1, 2};
+  for (int a = 0; a < 3; ++a) /* sort eigenvalues descending */
+    for (int b = a + 1; b < 3; ++b)
+      if (w[order[b]] > w[order[a]]) {
+        int t = order[a];
+        order[a] = order[b];
+        order[b] = t;
+      }
+  double top = w[order[0]];
+  double tie = 1e-12 * fabs(top);
+  double out[3];
+  int ncl = 1;
+  while (ncl < 3 && top - w[order[ncl]] <= tie) ++ncl;
+  if (ncl == 1) {
+    for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + order[0]];
+  } else {
+    /* degenerate top eigenvalue: any unit vector of the top eigenspace is a
+       minimiser; keep the previous director's projection onto it */
+    for (int k = 0; k < 3; ++k) out[k] = 0.0;
+    for (int e = 0; e < ncl; ++e) {
+      double c = 0.0;
+      for (int k = 0; k < 3; ++k) c += Vv[3 * k + order[e]] * n_prev[k];
+      for (int k = 0; k < 3; ++k) out[k] += c * Vv[3 * k + order[e]];
+    }
+    double nn = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+    if (nn < 1e-8)
+      for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + order[0]];
+  }
+  double s = out[0] * n_prev[0] + out[1] * n_prev[1] + out[2] * n_prev[2];
+  if (s < 0.0)
+    for (int k = 0; k < 3; ++k) out[k] = -out[k];
+  double nn = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+  for (int k = 0; k < 3; ++k) n[k] = out[k] / nn;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 1: the local problem at one point                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Cholesky factorisation of a 9x9 symmetric matrix in place (lower part);
+   returns 0 when a pivot is not positive. */
+static int chol9(double *K) {
+  for (int j = 0; j < 9; ++j) {
+    double d = K[9 * j + j];
+    for (int k = 0; k < j; ++k) d -= K[9 * j + k] * K[9 * j + k];
+    if (!(d > 0.0)) return 0;
+    d = sqrt(d);
+    K[9 * j + j] = d;
+    for (int i = j + 1; i < 9; ++i) {
+      double v = K[9 * i + j];
+      for (int k = 0; k < j; ++k) v -= K[9 * i + k] * K[9 * j + k];
+      K[9 * i + j] = v / d;
+    }
+  }
+  return 1;
+}
+
+static void chol9_solve(const double *L, const double *b, double *x) {
+  double y[9];
+  for (int i = 0; i < 9; ++i) {
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= L[9 * i + k] * y[k];
+    y[i] = v / L[9 * i + i];
+  }
+  for (int i = 8; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 9; ++k) v -= L[9 * k + i] * x[k];
+    x[i] = v / L[9 * i + i];
+  }
+}
+
+static double prox_objective(const or_material *m, double rho, const double *A,
+                             const double *F, const double *n) {
+  double W = or_energy(m, F, n);
+  double d2 = 0.0;
+  for (int k = 0; k < 9; ++k) d2 += (F[k] - A[k]) * (F[k] - A[k]);
+  return W + 0.5 * rho * d2;
+}
+
+static double moduli_sum(const or_material *m) {
+  return m->model == OR_NEOHOOKE ? m->mu + m->lambda : m->mu * cbrt(m->a) + m->kappa;
+}
+
+/* Newton's method with Armijo backtracking on phi(F) = W(F,n) + rho/2|F-A|^2
+   at fixed n. Returns OR_OK, OR_NOT_CONVERGED or OR_EDOMAIN; *it = iterations. */
+static int newton_fixed_n(const or_material *m, double rho, const double *A,
+                          const or_newton *opt, double *F, const double *n, int *it) {
+  double P[9], g[9], K[81], d[9], Ft[9];
+  double scale_mod = moduli_sum(m) + rho;
+  for (int iter = 0; iter < opt->max_iter; ++iter) {
+    if (or_stress(m, F, n, P) != OR_OK) {
+      *it = iter;
+      return OR_EDOMAIN;
+    }
+    for (int k = 0; k < 9; ++k) g[k] = P[k] + rho * (F[k] - A[k]);
+    double scale = scale_mod * (1.0 + norm9(F) + norm9(A));
+    if (norm9(g) <= opt->gtol * scale) {
+      *it = iter;
+      return OR_OK;
+    }
+    or_tangent(m, F, n, K);
+    for (int k = 0; k < 9; ++k) K[10 * k] += rho;
+    int pd = chol9(K);
+    if (pd) {
+      double mg[9];
+      for (int k = 0; k < 9; ++k) mg[k] = -g[k];
+      chol9_solve(K, mg, d);
+    } else {
+      for (int k = 0; k < 9; ++k) d[k] = -g[k];
+    }
+    double slope = dot9(g, d);
+    double phi0 = prox_objective(m, rho, A, F, n);
+    /* Armijo backtracking on phi. Once the predicted decrease falls below the
+       rounding floor of phi itself, the energy test is noise; the step is then
+       accepted on a decrease of the gradient norm instead. */
+    double fn0 = norm9(F);
+    double floor_phi = 1e-12 * scale_mod * (1.0 + fn0 * fn0);
+    int small = -slope <= floor_phi;
+    double gn = norm9(g);
+    double t = 1.0;
+    int accepted = 0;
+    for (int ls = 0; ls < 60; ++ls) {
+      for (int k = 0; k < 9; ++k) Ft[k] = F[k] + t * d[k];
+      if (det3(Ft) > 0.0) {
+        if (!small) {
+          double phit = prox_objective(m, rho, A, Ft, n);
+          if (phit <= phi0 + 1e-4 * t * slope) {
+            accepted = 1;
+            break;
+          }
+        } else {
+          double Pt[9], gt[9];
+          or_stress(m, Ft, n, Pt);
+          for (int k = 0; k < 9; ++k) gt[k] = Pt[k] + rho * (Ft[k] - A[k]);
+          if (norm9(gt) <= (1.0 - 1e-4 * t) * gn) {
+            accepted = 1;
+            break;
+          }
+        }
+      }
+      t *= 0.5;
+    }
+    if (!accepted) {
+      *it = iter + 1;
+      return OR_NOT_CONVERGED;
+    }
+    memcpy(F, Ft, sizeof(Ft));
+    double fn = norm9(F);
+    if (pd && t == 1.0 && norm9(d) <= opt->step_tol * (fn > 1.0 ? fn : 1.0)) {
+      *it = iter + 1;
+      return OR_OK;
+    }
+  }
+  *it = opt->max_iter;
+  return OR_NOT_CONVERGED;
+}
+
+int or_prox(const or_material *m, double rho, const double A[9],
+            const or_newton *opt, double F[9], double n[3], int *iters) {
+  if (!m || !A || !opt || !F || !(rho > 0.0)) return OR_EINVAL;
+  int it = 0, rc;
+  if (m->model == OR_NEOHOOKE) {
+    rc = newton_fixed_n(m, rho, A, opt, F, n, &it);
+    if (iters) *iters = it;
+    return rc;
+  }
+  if (!n) return OR_EINVAL;
+  /* LCE: alternate the F-minimisation at fixed n and the exact n-minimisation
+     at fixed F (top eigenvector of F F^T) until the director stops moving. */
+  int total = 0;
+  rc = OR_NOT_CONVERGED;
+  for (int outer = 0; outer < opt->dir_max; ++outer) {
+    int r = newton_fixed_n(m, rho, A, opt, F, n, &it);
+    total += it;
+    if (r == OR_EDOMAIN) {
+      rc = r;
+      break;
+    }
+    double nn[3];
+    or_director(F, n, nn);
+    double dn = sqrt((nn[0] - n[0]) * (nn[0] - n[0]) + (nn[1] - n[1]) * (nn[1] - n[1]) +
+                     (nn[2] - n[2]) * (nn[2] - n[2]));
+    memcpy(n, nn, sizeof(nn));
+    if (dn <= 1e-13) {
+      rc = r;
+      break;
+    }
+  }
+  if (iters) *iters = total;
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Periodic grid: DFT, gradient, Step 2                                     */
+/* ------------------------------------------------------------------------ */
+
+static int valid_dims(int n1, int n2, int n3) { return n1 >= 1 && n2 >= 1 && n3 >= 1; }
+
+/* direct DFT of every line along one axis, in place on (re, im) */
+static void dft_axis(int n1, int n2, int n3, int axis, double *re, double *im, int inverse) {
+  int N = axis == 0 ? n1 : (axis == 1 ? n2 : n3);
+  if (N == 1) return;
+  size_t V = (size_t)n1 * n2 * n3;
+  size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)n1 : (size_t)n1 * n2);
+  size_t nlines = V / (size_t)N;
+  double *c = (double *)malloc(sizeof(double) * N * N);
+  double *s = (double *)malloc(sizeof(double) * N * N);
+  double sg = inverse ? 1.0 : -1.0;
+  for (int m = 0; m < N; ++m)
+    for (int k = 0; k < N; ++k) {
+      long t = ((long)m * k) % N;
+      double ang = TWO_PI * (double)t / (double)N;
+      c[m * N + k] = cos(ang);
+      s[m * N + k] = sg * sin(ang);
+    }
+#pragma omp parallel
+  {
+    double *lr = (double *)malloc(sizeof(double) * N);
+    double *li = (double *)malloc(sizeof(double) * N);
+#pragma omp for schedule(static)
+    for (size_t line = 0; line < nlines; ++line) {
+      size_t base;
+      if (axis == 0)
+        base = line * (size_t)n1;
+      else if (axis == 1)
+        base = (line / n1) * (size_t)n1 * n2 + (line % n1);
+      else
+        base = line;
+      for (int k = 0; k < N; ++k) {
+        lr[k] = re[base + k * stride];
+        li[k] = im[base + k * stride];
+      }
+      for (int m = 0; m < N; ++m) {
+        const double *cm = c + (size_t)m * N, *sm = s + (size_t)m * N;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < N; ++k) {
+          sr += lr[k] * cm[k] - li[k] * sm[k];
+          si += lr[k] * sm[k] + li[k] * cm[k];
+        }
+        re[base + m * stride] = sr;
+        im[base + m * stride] = si;
+      }
+    }
+    free(lr);
+    free(li);
+  }
+  free(c);
+  free(s);
+}
+
+int or_dft3(int n1, int n2, int n3, const double *re, const double *im,
+            double *out_re, double *out_im, int inverse) {
+  if (!valid_dims(n1, n2, n3) || !re || !out_re || !out_im) return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  memcpy(out_re, re, V * sizeof(double));
+  if (im)
+    memcpy(out_im, im, V * sizeof(double));
+  else
+    memset(out_im, 0, V * sizeof(double));
+  dft_axis(n1, n2, n3, 0, out_re, out_im, inverse);
+  dft_axis(n1, n2, n3, 1, out_re, out_im, inverse);
+  dft_axis(n1, n2, n3, 2, out_re, out_im, inverse);
+  if (inverse) {
+    double sc = 1.0 / (double)V;
+    for (size_t x = 0; x < V; ++x) {
+      out_re[x] *= sc;
+      out_im[x] *= sc;
+    }
+  }
+  return OR_OK;
+}
+
+int or_gradient(int n1, int n2, int n3, const double *u, const double Fbar[9], double *G) {
+  if (!valid_dims(n1, n2, n3) || !u || !Fbar || !G) return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  int nn[3] = {n1, n2, n3};
+#pragma omp parallel for schedule(static)
+  for (long k3 = 0; k3 < n3; ++k3)
+    for (int k2 = 0; k2 < n2; ++k2)
+      for (int k1 = 0; k1 < n1; ++k1) {
+        int kk[3] = {k1, k2, (int)k3};
+        size_t x = ((size_t)k3 * n2 + k2) * n1 + k1;
+        for (int j = 0; j < 3; ++j) {
+          int kp[3] = {kk[0], kk[1], kk[2]}, km[3] = {kk[0], kk[1], kk[2]};
+          kp[j] = (kk[j] + 1) % nn[j];
+          km[j] = (kk[j] - 1 + nn[j]) % nn[j];
+          size_t xp = ((size_t)kp[2] * n2 + kp[1]) * n1 + kp[0];
+          size_t xm = ((size_t)km[2] * n2 + km[1]) * n1 + km[0];
+          for (int i = 0; i < 3; ++i)
+            G[(size_t)(3 * i + j) * V + x] =
+                Fbar[3 * i + j] + 0.5 * (u[(size_t)i * V + xp] - u[(size_t)i * V + xm]);
+        }
+      }
+  return OR_OK;
+}
+
+/* modified wavenumber sin(2 pi m / N) of the central difference, exactly zero
+   at m = 0 and m = N/2 */
+static double kmod(int m, int N) {
+  int t = ((m % N) + N) % N;
+  if (t == 0 || 2 * t == N) return 0.0;
+  return sin(TWO_PI * (double)t / (double)N);
+}
+
+static int null_mode(int m, int N) {
+  int t = ((m % N) + N) % N;
+  return t == 0 || 2 * t == N;
+}
+
+int or_project(int n1, int n2, int n3, const double *H, double *u, double *max_imag) {
+  if (!valid_dims(n1, n2, n3) || !H || !u) return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  double *ur = (double *)calloc(3 * V, sizeof(double)); /* 3 accumulators, Re */
+  double *ui = (double *)calloc(3 * V, sizeof(double)); /* Im */
+  double *hr = (double *)malloc(V * sizeof(double));
+  double *hi = (double *)malloc(V * sizeof(double));
+  double *tr = (double *)malloc(V * sizeof(double));
+  double *ti = (double *)malloc(V * sizeof(double));
+  if (!ur || !ui || !hr || !hi || !tr || !ti) {
+    free(ur); free(ui); free(hr); free(hi); free(tr); free(ti);
+    return OR_EINVAL;
+  }
+  /* u_hat_i = -i sum_j K_j H_hat_ij / |K|^2, accumulated one component at a time */
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      or_dft3(n1, n2, n3, H + (size_t)(3 * i + j) * V, NULL, hr, hi, 0);
+      for (int m3 = 0; m3 < n3; ++m3)
+        for (int m2 = 0; m2 < n2; ++m2)
+          for (int m1 = 0; m1 < n1; ++m1) {
+            size_t x = ((size_t)m3 * n2 + m2) * n1 + m1;
+            if (null_mode(m1, n1) && null_mode(m2, n2) && null_mode(m3, n3)) continue;
+            double K[3] = {kmod(m1, n1), kmod(m2, n2), kmod(m3, n3)};
+            double k2 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
+            double w = K[j] / k2;
+            /* -i * w * (hr + i hi) = w*hi - i*w*hr */
+            ur[(size_t)i * V + x] += w * hi[x];
+            ui[(size_t)i * V + x] -= w * hr[x];
+          }
+    }
+  double mi = 0.0, mr = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    or_dft3(n1, n2, n3, ur + (size_t)i * V, ui + (size_t)i * V, tr, ti, 1);
+    for (size_t x = 0; x < V; ++x) {
+      u[(size_t)i * V + x] = tr[x];
+      if (fabs(tr[x]) > mr) mr = fabs(tr[x]);
+      if (fabs(ti[x]) > mi) mi = fabs(ti[x]);
+    }
+  }
+  if (max_imag) *max_imag = mr > 0.0 ? mi / mr : mi;
+  free(ur); free(ui); free(hr); free(hi); free(tr); free(ti);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Steps 1-4                                                                */
+/* ------------------------------------------------------------------------ */
+
+double or_rho_update(double rho, double r_p, double r_d, const or_params *p) {
+  /* rho <- kappa rho           if r_p / r_d > tau
+     rho <- max(rho/kappa, min) if r_d / r_p > tau
+     then clamped to rho_max */
+  double out = rho;
+  if (r_p > p->tau * r_d)
+    out = p->kappa_rho * rho;
+  else if (r_d > p->tau * r_p)
+    out = fmax(rho / p->kappa_rho, p->rho_min);
+  if (out > p->rho_max) out = p->rho_max;
+  return out;
+}
+
+int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
+                const or_material *mats, int n_mat, const double Fbar[9],
+                const or_params *p, double *u, double *F, double *Lambda,
+                double *director, double *rho, double *hist_rp, double *hist_rd,
+                double *hist_rho, int *iters, int *newton_fail) {
+  if (!valid_dims(n1, n2, n3) || !phase || !mats || n_mat < 1 || !Fbar || !p || !u ||
+      !F || !Lambda || !rho || !(*rho > 0.0) || p->max_iter < 0)
+    return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  for (size_t x = 0; x < V; ++x)
+    if (phase[x] >= n_mat) return OR_EINVAL;
+  for (int q = 0; q < n_mat; ++q)
+    if (mats[q].model == OR_LCE && !director) return OR_EINVAL;
+
+  double *Gold = (double *)malloc(9 * V * sizeof(double));
+  double *Gnew = (double *)malloc(9 * V * sizeof(double));
+  double *H = (double *)malloc(9 * V * sizeof(double));
+  if (!Gold || !Gnew || !H) {
+    free(Gold); free(Gnew); free(H);
+    return OR_EINVAL;
+  }
+  or_gradient(n1, n2, n3, u, Fbar, Gold); /* grad u_0 = Fbar + D_h u_0 */
+
+  int rc = p->fixed_iters ? OR_OK : OR_NOT_CONVERGED;
+  int done = 0, fails = 0, dom = 0;
+  for (int it = 0; it < p->max_iter; ++it) {
+    double r = *rho;
+    /* Step 1: F_{i+1} = argmin W(F) + rho/2 |F - (grad u_i + Lambda_i / rho)|^2 */
+#pragma omp parallel for schedule(static) reduction(+ : fails, dom)
+    for (long xl = 0; xl < (long)V; ++xl) {
+      size_t x = (size_t)xl;
+      double A[9], Fx[9], nx[3] = {0.0, 0.0, 1.0};
+      for (int c = 0; c < 9; ++c) {
+        A[c] = Gold[c * V + x] + Lambda[c * V + x] / r;
+        Fx[c] = F[c * V + x];
+      }
+      if (director)
+        for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
+      int its = 0;
+      int pr = or_prox(&mats[phase[x]], r, A, &p->newton, Fx, nx, &its);
+      if (pr == OR_NOT_CONVERGED) fails += 1;
+      if (pr == OR_EDOMAIN) dom += 1;
+      for (int c = 0; c < 9; ++c) F[c * V + x] = Fx[c];
+      if (director)
+        for (int c = 0; c < 3; ++c) director[c * V + x] = nx[c];
+    }
+    if (dom) {
+      rc = OR_EDOMAIN;
+      done = it;
+      break;
+    }
+    /* Step 2: -Lap u_{i+1} = div(-F_{i+1} + Lambda_i / rho) */
+    for (size_t k = 0; k < 9 * V; ++k) H[k] = F[k] - Lambda[k] / r;
+    or_project(n1, n2, n3, H, u, NULL);
+    /* Step 3: Lambda_{i+1} = Lambda_i + rho (grad u_{i+1} - F_{i+1}) */
+    or_gradient(n1, n2, n3, u, Fbar, Gnew);
+    for (size_t k = 0; k < 9 * V; ++k) Lambda[k] += r * (Gnew[k] - F[k]);
+    /* Step 4: r_p = |grad u_{i+1} - F_{i+1}|, r_d = rho/mu |grad u_{i+1} - grad u_i| */
+    double sp = 0.0, sd = 0.0;
+    for (size_t x = 0; x < V; ++x)
+      for (int c = 0; c < 9; ++c) {
+        double e = Gnew[c * V + x] - F[c * V + x];
+        double dd = Gnew[c * V + x] - Gold[c * V + x];
+        sp += e * e;
+        sd += dd * dd;
+      }
+    double rp = sqrt(sp / (double)V);
+    double rd = r / p->mu_ref * sqrt(sd / (double)V);
+    if (hist_rp) hist_rp[it] = rp;
+    if (hist_rd) hist_rd[it] = rd;
+    if (hist_rho) hist_rho[it] = r;
+    double *t = Gold;
+    Gold = Gnew;
+    Gnew = t;
+    done = it + 1;
+    if (!(rp == rp) || !(rd == rd)) {
+      rc = OR_EDOMAIN;
+      break;
+    }
+    if (!p->fixed_iters && rp <= p->tol_p && rd <= p->tol_d) {
+      rc = OR_OK;
+      break;
+    }
+    if (p->adapt_rho) *rho = or_rho_update(r, rp, rd, p);
+  }
+  if (iters) *iters = done;
+  if (newton_fail) *newton_fail = fails;
+  free(Gold);
+  free(Gnew);
+  free(H);
+  return rc;
+}
+
+int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
+                   const or_material *mats, int n_mat, const double *F,
+                   const double *director, const double *Lambda, double P_mean[9],
+                   double Lambda_mean[9]) {
+  if (!valid_dims(n1, n2, n3) || !phase || !mats || !F) return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  double sP[9] = {0}, sL[9] = {0};
+  for (size_t x = 0; x < V; ++x) {
+    if (phase[x] >= n_mat) return OR_EINVAL;
+    double Fx[9], P[9], nx[3] = {0.0, 0.0, 1.0};
+    for (int c = 0; c < 9; ++c) Fx[c] = F[c * V + x];
+    if (director)
+      for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
+    if (or_stress(&mats[phase[x]], Fx, nx, P) != OR_OK) return OR_EDOMAIN;
+    for (int c = 0; c < 9; ++c) sP[c] += P[c];
+    if (Lambda)
+      for (int c = 0; c < 9; ++c) sL[c] += Lambda[c * V + x];
+  }
+  for (int c = 0; c < 9; ++c) {
+    if (P_mean) P_mean[c] = sP[c] / (double)V;
+    if (Lambda_mean) Lambda_mean[c] = sL[c] / (double)V;
+  }
+  return OR_OK;
+}

@@ -1,0 +1,136 @@
+/*
+ * admm_oracle.h -- plain double-precision CPU oracle for the ADMM iteration of
+ * Zhou & Bhattacharya, "Accelerated computational micromechanics"
+ * (arXiv 2010.06697).
+ *
+ * TEST INFRASTRUCTURE. This library exists only to check the GPU path: the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product path never does. It shares no code, header, table or helper with
+ * the HIP library.
+ *
+ * Conventions (chosen here, independent of the GPU library's header):
+ *   - grid n1 x n2 x n3, voxel (k1,k2,k3) at linear index (k3*n2 + k2)*n1 + k1,
+ *     spacing h = 1 (voxel units);
+ *   - fields are component-major: a 3-vector field holds 3*V doubles,
+ *     component i at [i*V + idx]; a 3x3 tensor field holds 9*V doubles,
+ *     component (i,J) at [(3*i+J)*V + idx] (row-major F_iJ);
+ *   - the deformation gradient is stored as F itself (not F - I);
+ *   - the DFT is unnormalised forward, exp(-2*pi*i m.k/N), inverse exp(+...)/V.
+ */
+#ifndef ADMM_ORACLE_H
+#define ADMM_ORACLE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OR_OK = 0,
+  OR_NOT_CONVERGED = 1, /* ADMM hit max_iter, or a local Newton hit its cap */
+  OR_EINVAL = -1,       /* bad argument */
+  OR_EDOMAIN = -5       /* det F <= 0 or NaN met */
+};
+
+enum { OR_NEOHOOKE = 0, OR_LCE = 1 };
+
+/* Material of one phase.
+ *   OR_NEOHOOKE: W = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 (ln J)^2
+ *   OR_LCE:      W = mu/2 [ a^(1/3) (|F|^2 + (1/a - 1) |F^T n|^2) - 3 ]
+ *                    + kappa/2 (J - 1)^2
+ *                (neo-classical energy with step length tensor
+ *                 L(n) = a^(-1/3) (I + (a-1) n n), plus a volumetric penalty) */
+typedef struct {
+  int model;
+  double mu, lambda; /* neo-Hookean */
+  double a, kappa;   /* LCE */
+} or_material;
+
+/* Options of the per-voxel Newton solve of the local problem. */
+typedef struct {
+  int max_iter;     /* Newton iteration cap (100) */
+  double gtol;      /* stop when |grad| <= gtol * scale before a step (1e-15) */
+  double step_tol;  /* stop after a full PD Newton step with |d| <= step_tol*max(1,|F|) */
+  int dir_max;      /* LCE: cap on alternations between F and n (200) */
+} or_newton;
+
+/* ADMM parameters. */
+typedef struct {
+  double rho_min, rho_max; /* clamp of the adaptive penalty */
+  double kappa_rho, tau;   /* adaptive-penalty factor and ratio threshold */
+  int adapt_rho;           /* 0: fixed rho, 1: adaptive rule after each test */
+  double tol_p, tol_d;     /* primal / dual tolerances */
+  double mu_ref;           /* representative modulus in r_d */
+  int max_iter;            /* iteration cap */
+  int fixed_iters;         /* 1: run exactly max_iter iterations, no test */
+  or_newton newton;
+} or_params;
+
+/* ---- small pieces, exposed so that tests can pin each one ---- */
+
+/* 3D DFT of a complex field (re, im: V doubles each), separable direct sums.
+ * inverse = 0: forward unnormalised; inverse = 1: conjugate kernel and 1/V. */
+int or_dft3(int n1, int n2, int n3, const double *re, const double *im,
+            double *out_re, double *out_im, int inverse);
+
+/* Gradient of the displacement: G_iJ = Fbar_iJ + (u_i(x+e_J) - u_i(x-e_J))/2. */
+int or_gradient(int n1, int n2, int n3, const double *u, const double Fbar[9],
+                double *G);
+
+/* Step 2 (Helmholtz projection): u = argmin_u sum_x |D_h u - H|^2 with zero
+ * mean and no null-mode content. H: 9*V, u: 3*V. max_imag (may be NULL)
+ * receives max |Im| of the inverse transform relative to max |Re|. */
+int or_project(int n1, int n2, int n3, const double *H, double *u,
+               double *max_imag);
+
+/* Energy, first Piola stress and tangent dP_iJ/dF_kL (81 doubles, row
+ * (3i+J), column (3k+L)) of one material point; n is read by OR_LCE only. */
+double or_energy(const or_material *m, const double F[9], const double n[3]);
+int or_stress(const or_material *m, const double F[9], const double n[3],
+              double P[9]);
+int or_tangent(const or_material *m, const double F[9], const double n[3],
+               double C[81]);
+
+/* Top eigenvector of F F^T with the sign / tie rules of the director update.
+ * n_prev: previous director (unit). Writes unit n. */
+int or_director(const double F[9], const double n_prev[3], double n[3]);
+
+/* Step 1 (local problem) at one point: F = argmin W(F,n) + rho/2 |F - A|^2.
+ * F holds the warm start on entry and the minimiser on exit; n (LCE) likewise.
+ * iters (may be NULL) receives the Newton iteration count. */
+int or_prox(const or_material *m, double rho, const double A[9],
+            const or_newton *opt, double F[9], double n[3], int *iters);
+
+/* Adaptive penalty rule applied after the convergence test. */
+double or_rho_update(double rho, double r_p, double r_d, const or_params *p);
+
+/* ---- the whole iteration ---- */
+
+/* Runs ADMM iterations on one periodic cell.
+ *   phase: V bytes indexing mats; Fbar: macroscopic gradient (row-major);
+ *   u (3V), F (9V), Lambda (9V): state, updated in place; director (3V) or NULL;
+ *   rho: in/out penalty; hist_* (max_iter doubles each, may be NULL) receive
+ *   r_p, r_d and the rho used at each iteration; iters: iterations done.
+ * Returns OR_OK (converged or fixed count done), OR_NOT_CONVERGED, or an error. */
+int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
+                const or_material *mats, int n_mat, const double Fbar[9],
+                const or_params *p, double *u, double *F, double *Lambda,
+                double *director, double *rho, double *hist_rp,
+                double *hist_rd, double *hist_rho, int *iters,
+                int *newton_fail);
+
+/* Homogenised first Piola stress <P> = (1/V) sum_x P(F(x)) (plain summation in
+ * voxel order), and the mean multiplier <Lambda>. Either output may be NULL. */
+int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
+                   const or_material *mats, int n_mat, const double *F,
+                   const double *director, const double *Lambda,
+                   double P_mean[9], double Lambda_mean[9]);
+
+/* Number of OpenMP threads the oracle uses (1 without OpenMP). */
+int or_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
