@@ -1,0 +1,288 @@
+"""Throughput of the ADMM hot path on one MI355X.
+
+Workload (N = 1): the 256^3 periodic fibre composite (fibres along x3, radius 8,
+area fraction 0.3, gap >= 2, fibre mu=50 lambda=500, matrix mu=1 lambda=10),
+first increment of the simple-shear path (Fbar = I + 0.01 e1 x e2), rho0 = 10
+adapted in [1, 50], float fields with double reductions. A step is one ADMM
+iteration (Steps 1-4 and the penalty rule) over the whole cell; the timed
+region is `--steps` iterations plus one homogenised-stress evaluation, with
+every field resident in HBM before it starts.
+
+Also reported on the same line: the all-double form at 256^3, the 128-cell
+batch (edges 32..96, one load step each to tol 1e-6) as cell solves/s, the
+per-kernel times from hipEvents on the library's stream, the roofline of the
+dominant kernel, and the CPU oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-ADMM-iterations/s at 256³, FP32+FP64-reduce vs FP64; RVE solves/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes_per_voxel(s, c):
+    """Algorithmic HBM bytes per voxel of each kernel (every operand read or
+    written once; s = scalar bytes, c = (n1/2+1)/n1 half-spectrum fraction)."""
+    return {
+        "local_fwdx": (30 + 18 * c) * s + 1,
+        "fft_y_fwd": 36 * c * s,
+        "green_z": 24 * c * s,
+        "fft_y_inv": 12 * c * s,
+        "inv_x": (6 * c + 3) * s,
+        "update": 33 * s,
+        "finalize": 0.0,
+        "mean_stress": 18 * s + 1,
+    }
+
+
+def iteration_bytes_alg(s, c):
+    """Minimum bytes per voxel-iteration of the method (state once in and out,
+    one round trip of the forward and inverse spectra)."""
+    return s * (45 + 48 * c) + 1
+
+
+def run_single(case, precision, steps, warmup, profile=True):
+    import torch
+    from paper_2010_06697_amd import admm
+
+    n3, n2, n1 = case["phase"].shape
+    V = n1 * n2 * n3
+    p = admm.default_params(rho0=case["rho0"], rho_min=case["rho_min"], rho_max=case["rho_max"],
+                            adapt_rho=1, mu_ref=case["mu_ref"],
+                            tol_p=case["tol_fp32" if precision == "fp32" else "tol_fp64"],
+                            tol_d=case["tol_fp32" if precision == "fp32" else "tol_fp64"],
+                            newton_step_tol=1e-7 if precision == "fp32" else 1e-10)
+    s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
+                    precision=precision)
+    log(f"[bench] {precision}: warmup {warmup} iterations")
+    if warmup:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    if profile:
+        s.profile(True)
+    log(f"[bench] {precision}: timing {steps} iterations")
+    t0 = time.perf_counter()
+    rc, rp, rd, rho = s.step(steps)
+    P, _ = s.homogenized_stress(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read() if profile else {}
+    it, status, nfail = s.info(0)
+    s.profile(False)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    dt = t1 - t0
+    out = {
+        "value": V * steps / dt,
+        "ms_per_step": 1e3 * dt / steps,
+        "r_p": float(rp[0]), "r_d": float(rd[0]), "rho": float(rho[0]),
+        "newton_fail": int(nfail),
+        "P_mean": [float(x) for x in P],
+        "kernels_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()},
+        "kernels_launches": {k: v[1] for k, v in prof.items()},
+    }
+    log(f"[bench] {precision}: {out['value']:.3e} voxel-it/s, {out['ms_per_step']:.3f} ms/it")
+    return out
+
+
+def run_batch(count, steps_warm=2):
+    import torch
+    from paper_2010_06697_amd import admm, microstructure as M
+
+    log(f"[bench] batch: generating {count} cells")
+    cells = M.rve_batch(count)
+    mats = M.rve_batch_materials()
+    p = admm.default_params(rho0=10.0, rho_min=1.0, rho_max=50.0, adapt_rho=1, mu_ref=5.0,
+                            tol_p=1e-6, tol_d=1e-6, max_iter=2000, check_every=20,
+                            newton_step_tol=1e-7)
+    s = admm.Solver([c["phase"] for c in cells], mats, [c["Fbar"] for c in cells], p,
+                    precision="fp32")
+    s.step(steps_warm)  # loads the kernels; the state is reset below
+    for k, c in enumerate(s.cells):
+        for f in ("u", "u_prev", "F", "Lambda"):
+            c[f].zero_()
+    torch.cuda.synchronize()
+    for k, c in enumerate(cells):
+        s.set_load(k, c["Fbar"])
+    s.set_rho(10.0)
+    torch.cuda.synchronize()
+    log("[bench] batch: timing one load step of every cell")
+    t0 = time.perf_counter()
+    rc, iters, status = s.solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    vox = np.array([c["n"] ** 3 for c in cells], dtype=np.float64)
+    dt = t1 - t0
+    out = {
+        "cells": count,
+        "rve_solves_per_s": float(np.sum(status == admm.OK)) / dt,
+        "seconds": dt,
+        "converged": int(np.sum(status == admm.OK)),
+        "voxels": int(vox.sum()),
+        "iterations_mean": float(iters.mean()),
+        "iterations_max": int(iters.max()),
+        "voxel_iterations_per_s": float(np.sum(vox * iters)) / dt,
+    }
+    log(f"[bench] batch: {out['rve_solves_per_s']:.2f} cell solves/s, "
+        f"{out['voxel_iterations_per_s']:.3e} voxel-it/s")
+    return out
+
+
+def cpu_baseline(case):
+    """The oracle (plain C, all host threads) on one ADMM iteration of the same
+    256^3 cell from the same start."""
+    import oracle as O
+
+    n3, n2, n1 = case["phase"].shape
+    mats = [O.material(m["model"], mu=m["mu"], lam=m["lam"]) for m in case["materials"]]
+    u, F, L = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=1, fixed_iters=True, mu_ref=case["mu_ref"])
+    log(f"[bench] cpu baseline: oracle, 1 iteration at {n1}x{n2}x{n3}, {O.num_threads()} threads")
+    t0 = time.perf_counter()
+    O.admm_run(case["phase"], mats, case["loads"][0].ravel(), p, u, F, L, case["rho0"])
+    dt = time.perf_counter() - t0
+    log(f"[bench] cpu baseline: {dt:.1f} s")
+    return {"value": n1 * n2 * n3 / dt, "unit": "voxel-iterations/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one ADMM iteration of the {n1}x{n2}x{n3} fibre cell from the zero "
+                      f"state (FP64, direct DFT), {dt:.1f} s"}
+
+
+def traffic_for(kernel, workload):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, or
+    None when absent or when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != sources_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2010_06697_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied by a plain device copy before the timed region "
+                         "(reference kernel for the HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): this build runs the "
+              "single-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_06697_amd import admm, microstructure as M
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    admm.lib()
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("[bench] generating the 256^3 fibre cell")
+    case = M.fibres256_case()
+    n3, n2, n1 = case["phase"].shape
+    V = n1 * n2 * n3
+    c = (n1 // 2 + 1) / n1
+
+    f32 = run_single(case, "fp32", args.steps, args.warmup)
+    f64 = None if args.no_fp64 else run_single(case, "fp64", args.steps, args.warmup)
+    batch = None if args.no_batch else run_batch(128)
+
+    # roofline of the dominant kernel (by total time in the timed region)
+    kb = kernel_bytes_per_voxel(4, c)
+    tot = {k: f32["kernels_ms"][k] * f32["kernels_launches"][k] for k in f32["kernels_ms"]}
+    dom = max(tot, key=tot.get)
+    avg_ms = f32["kernels_ms"][dom]
+    bytes_launch = kb[dom] * V
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = traffic_for(dom, "fibres256_fp32")
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": bytes_launch, "avg_ms": avg_ms}
+    b_it = iteration_bytes_alg(4, c)
+    it_roof = {"bytes_per_voxel_iteration": b_it,
+               "achieved_GBs": b_it * f32["value"] / 1e9,
+               "frac": b_it * f32["value"] / (HBM_PEAK_GBS * 1e9)}
+    per_kernel = {k: {"avg_ms": f32["kernels_ms"][k],
+                      "GBs": (kb[k] * V / (f32["kernels_ms"][k] * 1e-3) / 1e9
+                              if f32["kernels_ms"][k] > 0 and kb[k] > 0 else None)}
+                  for k in f32["kernels_ms"] if f32["kernels_launches"][k]}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(case)
+
+    line = {
+        "metric": METRIC,
+        "value": f32["value"],
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fibres256: 256^3 periodic fibre composite (fibres along x3, "
+                               "r=8, area fraction 0.3, gap>=2; fibre mu=50 lambda=500, matrix "
+                               "mu=1 lambda=10), simple shear Fbar = I + 0.01 e1(x)e2, rho0=10 "
+                               "adaptive in [1,50], float fields with double reductions",
+                   "grid": [n1, n2, n3], "voxels": V},
+        "fp64": None if f64 is None else {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                                          "dtype": "f64",
+                                          "kernels_ms": f64["kernels_ms"]},
+        "fp32_over_fp64": None if f64 is None else f32["value"] / f64["value"],
+        "rve_batch": batch,
+        "roofline": roof,
+        "iteration_roofline": it_roof,
+        "kernels": per_kernel,
+        "residuals_after_timed_steps": {"r_p": f32["r_p"], "r_d": f32["r_d"], "rho": f32["rho"],
+                                        "newton_fail": f32["newton_fail"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

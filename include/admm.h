@@ -1,0 +1,214 @@
+/*
+ * admm.h -- C ABI of the MI355X (gfx950) ADMM micromechanics library.
+ *
+ * The library runs the operator-splitting method of Zhou & Bhattacharya,
+ * "Accelerated computational micromechanics" (arXiv 2010.06697), on periodic
+ * voxel grids: the incremental variational problem written with an augmented
+ * Lagrangian (Sec. 2.1) and solved by ADMM, one iteration being
+ *   Step 1  local problem      F <- argmin W(F) + rho/2 |F - grad u - Lambda/rho|^2
+ *   Step 2  Helmholtz projection of F - Lambda/rho onto gradients, by FFT with
+ *           central-difference symbols (Sec. 2.3)
+ *   Step 3  multiplier update  Lambda <- Lambda + rho (grad u - F)
+ *   Step 4  primal / dual residuals r_p, r_d and the convergence test,
+ *           then the adaptive penalty rule (Sec. 2.1, "Penalty parameter").
+ * Every step runs in the library's HIP kernels; the host only launches them.
+ *
+ * Conventions
+ *   - Grid n1 x n2 x n3 (each even, 4..256, of the form 2^a 3^b), spacing 1.
+ *     Voxel (k1,k2,k3) has linear index (k3*n2 + k2)*n1 + k1 (x1 fastest);
+ *     V = n1*n2*n3.
+ *   - Fields are structure-of-arrays, component-major: a 3-vector field is
+ *     3*V scalars, component i at [i*V + idx]; a 3x3 tensor field is 9*V
+ *     scalars, component (i,J) at [(3*i+J)*V + idx] (row-major F_iJ).
+ *   - Scalar type: double in ADMM_FP64, float in ADMM_FP32_FP64RED.
+ *   - u is the periodic displacement fluctuation (grad u = Fbar + D_h u).
+ *   - The deformation-gradient field stores E = F - I (both precisions).
+ *   - All field pointers are DEVICE pointers owned by the caller; the library
+ *     never frees them. The context owns only its own metadata and the small
+ *     device tables it allocates in admm_init.
+ *   - Functions never throw; they return an admm_status code. On an error
+ *     return (< 0) the state is left as it was, except ADMM_EDOMAIN, which
+ *     leaves the last iterate and marks the offending cell.
+ *   - A context is bound to one HIP stream and is not thread safe. Work is
+ *     enqueued on that stream; calls returning host scalars synchronise it.
+ */
+#ifndef ADMM_H
+#define ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADMM_OK = 0,
+  ADMM_NOT_CONVERGED = 1, /* result valid; iteration cap reached */
+  ADMM_EINVAL = -1,       /* invalid argument */
+  ADMM_EUNSUPPORTED = -2, /* grid size or model not supported */
+  ADMM_EHIP = -3,         /* HIP runtime error */
+  ADMM_ENOMEM = -4,       /* workspace too small / allocation failed */
+  ADMM_EDOMAIN = -5,      /* det F <= 0 or NaN met in a cell */
+  ADMM_ENOGPU = -7        /* no HIP device */
+} admm_status;
+
+typedef enum {
+  ADMM_FP64 = 0,         /* everything in double precision */
+  ADMM_FP32_FP64RED = 1  /* float fields, FFT and Newton; double det F / ln J,
+                            residual norms, averages and convergence test */
+} admm_precision;
+
+typedef enum {
+  ADMM_NEOHOOKE = 0, /* W = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 (ln J)^2 */
+  ADMM_LCE = 1       /* W = mu/2 [a^(1/3)(|F|^2 + (1/a - 1)|F^T n|^2) - 3]
+                            + kappa/2 (J - 1)^2, director n per voxel
+                        (neo-classical energy of Sec. 5.1 with step-length
+                        tensor a^(-1/3)(I + (a-1) n n) and a volumetric
+                        penalty); not supported yet: ADMM_EUNSUPPORTED */
+} admm_model;
+
+/* One phase of the material table. */
+typedef struct {
+  int32_t model; /* admm_model */
+  int32_t reserved;
+  double mu, lambda; /* neo-Hookean moduli */
+  double a, kappa;   /* LCE: step-length ratio, volumetric penalty */
+} admm_material;
+
+/* One periodic cell (representative volume element). Pointers: device. */
+typedef struct {
+  int32_t n[3];          /* n1, n2, n3 */
+  int32_t reserved;
+  const uint8_t *phase;  /* V bytes, index into the material table */
+  void *u;               /* 3V: displacement fluctuation (in/out) */
+  void *u_prev;          /* 3V: second buffer the library iterates into */
+  void *F;               /* 9V: F - I (in/out) */
+  void *Lambda;          /* 9V: multiplier (in/out) */
+  void *director;        /* 3V unit director (LCE) or NULL */
+  double Fbar[9];        /* macroscopic gradient <F>, row-major, det > 0 */
+} admm_rve;
+
+/* Iteration parameters (Sec. 2.1; defaults in parentheses). */
+typedef struct {
+  double rho0;          /* initial penalty (10) */
+  double rho_min;       /* lower clamp of the adaptive rule (1) */
+  double rho_max;       /* upper clamp (50) */
+  double kappa_rho;     /* adaptive factor kappa (1.3) */
+  double tau;           /* adaptive ratio threshold tau (10) */
+  double tol_p, tol_d;  /* primal / dual tolerances */
+  double mu_ref;        /* representative modulus in r_d */
+  double newton_gtol;   /* local Newton: gradient test, relative (1e-15) */
+  double newton_step_tol; /* local Newton: step test, relative (1e-10) */
+  int32_t adapt_rho;    /* 1: adaptive penalty after each test */
+  int32_t max_iter;     /* iteration cap of admm_solve */
+  int32_t check_every;  /* admm_solve: iterations between host checks (10) */
+  int32_t newton_max;   /* local Newton iteration cap (100) */
+} admm_params;
+
+typedef struct admm_ctx admm_ctx;
+
+/* Validates one grid (host only, no GPU needed): ADMM_OK, ADMM_EINVAL
+ * (non-positive) or ADMM_EUNSUPPORTED (odd, outside 4..256, not 2^a 3^b). */
+int admm_check_grid(int32_t n1, int32_t n2, int32_t n3);
+
+/* Device workspace the library needs for these cells and precision (bytes):
+ * the half-spectrum buffers of Step 2 (9 components per cell) and the
+ * reduction partials. Host only. Returns 0 on invalid input. */
+size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precision);
+
+/* Creates a context for n_rve cells sharing one material table.
+ *   rves, mats, params: host arrays, copied (the field pointers inside rves
+ *   are kept and must stay valid for the context's life).
+ *   workspace: device buffer of at least admm_workspace_bytes(), or NULL to
+ *   let the library allocate (and free) its own.
+ *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * The penalty of every cell starts at params->rho0, the iteration count at 0.
+ * The fields are used as given (the caller zeroes u, F - I and Lambda for a
+ * fresh start). Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOGPU. */
+int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve,
+              const admm_material *mats, int32_t n_mat, const admm_params *params,
+              int32_t precision, void *workspace, size_t workspace_bytes,
+              void *hip_stream);
+
+/* Starts a new load step of cell `rve` (Algorithm 1, outer loop): sets its
+ * macroscopic gradient, resets its iteration count and convergence flag and
+ * keeps u, F, Lambda and rho as warm start. Errors: EINVAL (det Fbar <= 0). */
+int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]);
+
+/* Sets the penalty of one cell (rve >= 0) or of all cells (rve < 0). */
+int admm_set_rho(admm_ctx *ctx, int32_t rve, double rho);
+
+/* Runs exactly n_iter ADMM iterations (Steps 1-4 and the penalty rule) on
+ * every cell, ignoring the tolerances. Host arrays of n_rve doubles receive
+ * the last r_p, r_d and the penalty for the next iteration (each may be
+ * NULL). Synchronises the stream. Errors: EINVAL, EDOMAIN, EHIP. */
+int admm_step(admm_ctx *ctx, int32_t n_iter, double *r_p, double *r_d, double *rho);
+
+/* Iterates every cell until r_p <= tol_p and r_d <= tol_d or max_iter
+ * iterations of the current load step; converged cells are skipped on the
+ * device. iters_out / status_out (n_rve entries each, may be NULL) receive the
+ * iteration count and ADMM_OK / ADMM_NOT_CONVERGED / ADMM_EDOMAIN per cell.
+ * Returns ADMM_OK if all converged, ADMM_NOT_CONVERGED if some did not, or an
+ * error. Synchronises the stream. */
+int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out);
+
+/* The three parts of one iteration, for testing each on its own:
+ *   admm_local_step    Step 1 on every cell (F from u, Lambda, rho);
+ *   admm_project_step  Step 2 on every cell (u from F - Lambda/rho);
+ *   admm_update_step   Step 3 and Step 4 (Lambda, r_p, r_d, the penalty
+ *                      rule) against the u held before admm_project_step.
+ * admm_step(ctx, 1, ...) equals the three in this order. */
+int admm_local_step(admm_ctx *ctx);
+int admm_project_step(admm_ctx *ctx);
+int admm_update_step(admm_ctx *ctx);
+
+/* Homogenised stress <P> = (1/V) sum_x W_F(F(x)) and <Lambda> of one cell
+ * (Sec. 2.3; Lambda converges to the stress, Sec. 2.1), accumulated in
+ * double precision on the device. Host outputs of 9 doubles (Lambda_out may
+ * be NULL). Synchronises the stream. */
+int admm_homogenized_stress(admm_ctx *ctx, int32_t rve, double P_out[9],
+                            double Lambda_out[9]);
+
+/* Residual history of the current load step of one cell: up to max_n entries
+ * of r_p, r_d and the penalty used (host arrays, each may be NULL); n_out
+ * receives the number of iterations recorded. */
+int admm_history(admm_ctx *ctx, int32_t rve, int32_t max_n, double *r_p,
+                 double *r_d, double *rho, int32_t *n_out);
+
+/* Iteration count, status, Newton-failure count of one cell. */
+int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
+                   int32_t *newton_fail);
+
+/* Kernels timed by the profiling interface, in launch order. */
+typedef enum {
+  ADMM_KERNEL_LOCAL = 0,    /* Step 1 + H = F - Lambda/rho + forward FFT along x1 */
+  ADMM_KERNEL_FFT_Y_FWD = 1, /* forward FFT along x2, 9 components */
+  ADMM_KERNEL_GREEN_Z = 2,  /* FFT along x3, Fourier-space solve, inverse along x3 */
+  ADMM_KERNEL_FFT_Y_INV = 3, /* inverse FFT along x2, 3 components */
+  ADMM_KERNEL_INV_X = 4,    /* inverse FFT along x1 into u */
+  ADMM_KERNEL_UPDATE = 5,   /* Step 3 + residual partial sums */
+  ADMM_KERNEL_FINALIZE = 6, /* Step 4 reductions, test, penalty rule */
+  ADMM_KERNEL_MEAN = 7,     /* homogenised stress reductions */
+  ADMM_KERNEL_COUNT = 8
+} admm_kernel;
+
+/* Profiling (for measurement, not part of the method): when on, every kernel
+ * launch of the context is bracketed by a pair of hipEvents on the context's
+ * stream. Enabling clears the accumulated totals. */
+int admm_profile_enable(admm_ctx *ctx, int32_t on);
+
+/* Sum of the measured durations (ms) and number of launches of one kernel
+ * since profiling was enabled. Synchronises the stream. */
+int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *launches);
+
+/* Static description of an error code. */
+const char *admm_strerror(int code);
+
+/* Releases the context (not the caller's buffers). NULL is a no-op. */
+void admm_destroy(admm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADMM_H */

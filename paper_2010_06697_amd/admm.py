@@ -1,0 +1,380 @@
+"""ctypes binding of the C ABI in ``include/admm.h`` (``libadmm.so``).
+
+Argument marshalling only: every step of the ADMM iteration runs in the HIP
+kernels of the library. PyTorch provides device memory and the stream. The
+functions ``admm_*`` mirror the C entry points one to one; ``Solver`` owns the
+device buffers of a batch of cells and wraps them.
+
+Importing this module does not load the library; the first call does, and
+raises ``RuntimeError`` if ``libadmm.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadmm.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, EUNSUPPORTED, EHIP, ENOMEM, EDOMAIN, ENOGPU = -1, -2, -3, -4, -5, -7
+FP64, FP32_FP64RED = 0, 1
+NEOHOOKE, LCE = 0, 1
+
+# entry points declared in include/admm.h, in order
+ENTRY_POINTS = (
+    "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_rho",
+    "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
+    "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
+    "admm_profile_read", "admm_strerror", "admm_destroy",
+)
+
+KERNELS = ("local_fwdx", "fft_y_fwd", "green_z", "fft_y_inv", "inv_x", "update", "finalize",
+           "mean_stress")
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("lam", ctypes.c_double),
+                ("a", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+class Rve(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+                ("phase", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("u_prev", ctypes.c_void_p), ("F", ctypes.c_void_p),
+                ("Lambda", ctypes.c_void_p), ("director", ctypes.c_void_p),
+                ("Fbar", ctypes.c_double * 9)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("kappa_rho", ctypes.c_double),
+                ("tau", ctypes.c_double), ("tol_p", ctypes.c_double),
+                ("tol_d", ctypes.c_double), ("mu_ref", ctypes.c_double),
+                ("newton_gtol", ctypes.c_double), ("newton_step_tol", ctypes.c_double),
+                ("adapt_rho", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+        i32 = ctypes.c_int32
+        L.admm_check_grid.argtypes = [i32, i32, i32]
+        L.admm_workspace_bytes.argtypes = [ctypes.POINTER(Rve), i32, i32]
+        L.admm_workspace_bytes.restype = ctypes.c_size_t
+        L.admm_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Rve), i32,
+                                ctypes.POINTER(Material), i32, ctypes.POINTER(Params), i32,
+                                vp, ctypes.c_size_t, vp]
+        L.admm_set_load.argtypes = [vp, i32, dp]
+        L.admm_set_rho.argtypes = [vp, i32, ctypes.c_double]
+        L.admm_step.argtypes = [vp, i32, dp, dp, dp]
+        L.admm_solve.argtypes = [vp, ip, ip]
+        L.admm_local_step.argtypes = [vp]
+        L.admm_project_step.argtypes = [vp]
+        L.admm_update_step.argtypes = [vp]
+        L.admm_homogenized_stress.argtypes = [vp, i32, dp, dp]
+        L.admm_history.argtypes = [vp, i32, i32, dp, dp, dp, ip]
+        L.admm_cell_info.argtypes = [vp, i32, ip, ip, ip]
+        L.admm_profile_enable.argtypes = [vp, i32]
+        L.admm_profile_read.argtypes = [vp, i32, dp, ip]
+        L.admm_strerror.argtypes = [ctypes.c_int]
+        L.admm_strerror.restype = ctypes.c_char_p
+        L.admm_destroy.argtypes = [vp]
+        L.admm_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class AdmmError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {admm_strerror(code)} ({code})")
+        self.code = code
+
+
+def _check(code, where, allow=(OK,)):
+    if code not in allow:
+        raise AdmmError(code, where)
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+# ---- one-to-one wrappers of the C entry points -----------------------------
+
+def admm_strerror(code: int) -> str:
+    return lib().admm_strerror(int(code)).decode()
+
+
+def admm_check_grid(n1: int, n2: int, n3: int) -> int:
+    return lib().admm_check_grid(n1, n2, n3)
+
+
+def admm_workspace_bytes(rves, precision: int) -> int:
+    arr = (Rve * len(rves))(*rves)
+    return lib().admm_workspace_bytes(arr, len(rves), precision)
+
+
+def admm_init(rves, mats, params: Params, precision: int, workspace_ptr=None,
+              workspace_bytes=0, stream_ptr=None):
+    ctx = ctypes.c_void_p()
+    ra = (Rve * len(rves))(*rves)
+    ma = (Material * len(mats))(*mats)
+    rc = lib().admm_init(ctypes.byref(ctx), ra, len(rves), ma, len(mats), ctypes.byref(params),
+                         precision, workspace_ptr, workspace_bytes, stream_ptr)
+    _check(rc, "admm_init")
+    return ctx
+
+
+def admm_set_load(ctx, rve: int, Fbar) -> int:
+    F = np.ascontiguousarray(np.asarray(Fbar, np.float64).reshape(9))
+    return _check(lib().admm_set_load(ctx, rve, _dptr(F)), "admm_set_load")
+
+
+def admm_set_rho(ctx, rve: int, rho: float) -> int:
+    return _check(lib().admm_set_rho(ctx, rve, float(rho)), "admm_set_rho")
+
+
+def admm_step(ctx, n_iter: int, n_rve: int):
+    rp, rd, rho = np.zeros(n_rve), np.zeros(n_rve), np.zeros(n_rve)
+    rc = lib().admm_step(ctx, n_iter, _dptr(rp), _dptr(rd), _dptr(rho))
+    _check(rc, "admm_step", allow=(OK, EDOMAIN))
+    return rc, rp, rd, rho
+
+
+def admm_solve(ctx, n_rve: int):
+    it = np.zeros(n_rve, np.int32)
+    st = np.zeros(n_rve, np.int32)
+    rc = lib().admm_solve(ctx, _iptr(it), _iptr(st))
+    _check(rc, "admm_solve", allow=(OK, NOT_CONVERGED, EDOMAIN))
+    return rc, it, st
+
+
+def admm_local_step(ctx) -> int:
+    return _check(lib().admm_local_step(ctx), "admm_local_step", allow=(OK, EDOMAIN))
+
+
+def admm_project_step(ctx) -> int:
+    return _check(lib().admm_project_step(ctx), "admm_project_step")
+
+
+def admm_update_step(ctx) -> int:
+    return _check(lib().admm_update_step(ctx), "admm_update_step", allow=(OK, EDOMAIN))
+
+
+def admm_homogenized_stress(ctx, rve: int):
+    P, L = np.zeros(9), np.zeros(9)
+    rc = lib().admm_homogenized_stress(ctx, rve, _dptr(P), _dptr(L))
+    _check(rc, "admm_homogenized_stress", allow=(OK, EDOMAIN))
+    return P, L
+
+
+def admm_history(ctx, rve: int, max_n: int):
+    rp, rd, rho = np.zeros(max(max_n, 1)), np.zeros(max(max_n, 1)), np.zeros(max(max_n, 1))
+    n = ctypes.c_int32(0)
+    _check(lib().admm_history(ctx, rve, max_n, _dptr(rp), _dptr(rd), _dptr(rho),
+                              ctypes.byref(n)), "admm_history")
+    k = n.value
+    return rp[:k], rd[:k], rho[:k]
+
+
+def admm_cell_info(ctx, rve: int):
+    it, st, nf = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().admm_cell_info(ctx, rve, ctypes.byref(it), ctypes.byref(st), ctypes.byref(nf)),
+           "admm_cell_info")
+    return it.value, st.value, nf.value
+
+
+def admm_profile_enable(ctx, on: bool) -> int:
+    return _check(lib().admm_profile_enable(ctx, int(bool(on))), "admm_profile_enable")
+
+
+def admm_profile_read(ctx):
+    """{kernel name: (total ms, launches)} since profiling was enabled."""
+    out = {}
+    for k, name in enumerate(KERNELS):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int32(0)
+        _check(lib().admm_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n)),
+               "admm_profile_read")
+        out[name] = (ms.value, n.value)
+    return out
+
+
+def admm_destroy(ctx) -> None:
+    lib().admm_destroy(ctx)
+
+
+# ---- convenience: device buffers of a batch of cells -----------------------
+
+def default_params(**kw) -> Params:
+    p = Params()
+    p.rho0, p.rho_min, p.rho_max, p.kappa_rho, p.tau = 10.0, 1.0, 50.0, 1.3, 10.0
+    p.tol_p, p.tol_d, p.mu_ref = 1e-8, 1e-8, 1.0
+    p.newton_gtol, p.newton_step_tol = 1e-15, 1e-10
+    p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0) -> Material:
+    m = Material()
+    m.model = NEOHOOKE if model == "neohooke" else LCE
+    m.mu, m.lam, m.a, m.kappa = float(mu), float(lam), float(a), float(kappa)
+    return m
+
+
+class Solver:
+    """A batch of periodic cells on one GPU, each with its own grid, phase map
+    and macroscopic gradient, sharing one material table and parameters.
+
+    Buffers are torch tensors on ``device``: per cell ``u``/``u_prev``
+    (3, n3, n2, n1), ``F`` (9, n3, n2, n1) holding F - I, ``Lambda`` (9, ...),
+    ``phase`` (n3, n2, n1) uint8. They start from the zero state (u = 0,
+    F = I, Lambda = 0) unless overwritten with ``set_state``.
+    """
+
+    def __init__(self, phases, materials, Fbars, params: Params | None = None,
+                 precision: str = "fp64", device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = FP64 if precision == "fp64" else FP32_FP64RED
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self.params = params if params is not None else default_params()
+        mats = [m if isinstance(m, Material) else material(**m) for m in materials]
+        self.cells = []
+        rves = []
+        for ph, Fb in zip(phases, Fbars):
+            ph = np.ascontiguousarray(ph, np.uint8)
+            n3, n2, n1 = ph.shape
+            if admm_check_grid(n1, n2, n3) != OK:
+                raise AdmmError(admm_check_grid(n1, n2, n3), f"grid {ph.shape}")
+            cell = {
+                "shape": (n3, n2, n1),
+                "phase": torch.from_numpy(ph).to(self.device),
+                "u": torch.zeros((3, n3, n2, n1), dtype=self.dtype, device=self.device),
+                "u_prev": torch.zeros((3, n3, n2, n1), dtype=self.dtype, device=self.device),
+                "F": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
+                "Lambda": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
+            }
+            self.cells.append(cell)
+            r = Rve()
+            r.n[0], r.n[1], r.n[2] = n1, n2, n3
+            r.phase = cell["phase"].data_ptr()
+            r.u = cell["u"].data_ptr()
+            r.u_prev = cell["u_prev"].data_ptr()
+            r.F = cell["F"].data_ptr()
+            r.Lambda = cell["Lambda"].data_ptr()
+            r.director = None
+            for k, v in enumerate(np.asarray(Fb, np.float64).reshape(9)):
+                r.Fbar[k] = v
+            rves.append(r)
+        self.n = len(rves)
+        nbytes = admm_workspace_bytes(rves, self.precision)
+        if nbytes == 0:
+            raise AdmmError(EINVAL, "admm_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        torch.cuda.synchronize(self.device)
+        self.ctx = admm_init(rves, mats, self.params, self.precision,
+                             self.workspace.data_ptr() + off, nbytes, self.stream.cuda_stream)
+
+    # -- iteration --
+    def set_load(self, rve, Fbar):
+        admm_set_load(self.ctx, rve, Fbar)
+
+    def set_rho(self, rho, rve=-1):
+        admm_set_rho(self.ctx, rve, rho)
+
+    def step(self, n_iter):
+        return admm_step(self.ctx, n_iter, self.n)
+
+    def solve(self):
+        return admm_solve(self.ctx, self.n)
+
+    def local_step(self):
+        return admm_local_step(self.ctx)
+
+    def project_step(self):
+        return admm_project_step(self.ctx)
+
+    def update_step(self):
+        return admm_update_step(self.ctx)
+
+    def homogenized_stress(self, rve=0):
+        return admm_homogenized_stress(self.ctx, rve)
+
+    def history(self, rve=0, max_n=100000):
+        return admm_history(self.ctx, rve, max_n)
+
+    def info(self, rve=0):
+        return admm_cell_info(self.ctx, rve)
+
+    def profile(self, on=True):
+        admm_profile_enable(self.ctx, on)
+
+    def profile_read(self):
+        return admm_profile_read(self.ctx)
+
+    # -- state as float64 numpy (F as F itself) --
+    def state(self, rve=0):
+        c = self.cells[rve]
+        self.torch.cuda.synchronize(self.device)
+        F = c["F"].double().cpu().numpy().copy()
+        F[0] += 1.0
+        F[4] += 1.0
+        F[8] += 1.0
+        return {"u": c["u"].double().cpu().numpy(), "u_prev": c["u_prev"].double().cpu().numpy(),
+                "F": F, "Lambda": c["Lambda"].double().cpu().numpy()}
+
+    def set_state(self, rve=0, u=None, F=None, Lambda=None):
+        """Overwrites the fields of one cell (F given as F itself)."""
+        c = self.cells[rve]
+        t = self.torch
+        if u is not None:
+            c["u"].copy_(t.from_numpy(np.ascontiguousarray(u, np.float64)).to(self.device, self.dtype))
+        if F is not None:
+            E = np.array(F, np.float64, copy=True)
+            E[0] -= 1.0
+            E[4] -= 1.0
+            E[8] -= 1.0
+            c["F"].copy_(t.from_numpy(E).to(self.device, self.dtype))
+        if Lambda is not None:
+            c["Lambda"].copy_(t.from_numpy(np.ascontiguousarray(Lambda, np.float64))
+                              .to(self.device, self.dtype))
+        t.cuda.synchronize(self.device)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            admm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,737 @@
+// admm_api.cpp -- host side of the C ABI declared in include/admm.h: argument
+// validation, radix plans and twiddle tables, the per-cell descriptors, and
+// the launch sequence of Algorithm 1 (inner loop on the device, convergence
+// state read back once per check interval).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/admm.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace admm;
+
+namespace {
+
+enum { ST_RUNNING = 0, ST_CAP = 1, ST_CONVERGED = 2, ST_DOMAIN = -5 };
+
+bool is_2a3b(int n) {
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// radices for length n: 8s first, 4 4 instead of 8 2, then 2, then 3s
+Plan1D make_plan(int n) {
+  Plan1D p{};
+  p.n = n;
+  int m = n, twos = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++twos;
+  }
+  std::vector<int> r;
+  int e8 = twos / 3, rest = twos % 3;
+  if (rest == 1 && e8 > 0) {
+    --e8;
+    rest = 4;  // 2^4 = 4 * 4
+  }
+  for (int k = 0; k < e8; ++k) r.push_back(8);
+  if (rest == 4) {
+    r.push_back(4);
+    r.push_back(4);
+  } else if (rest == 2) {
+    r.push_back(4);
+  } else if (rest == 1) {
+    r.push_back(2);
+  }
+  while (m % 3 == 0) {
+    m /= 3;
+    r.push_back(3);
+  }
+  p.nst = (int)r.size();
+  for (int k = 0; k < p.nst; ++k) p.rad[k] = r[k];
+  return p;
+}
+
+// exp(-2 pi i t/n), t = 0..n-1: long double evaluation rounded once, exact at
+// the quarter points, and exactly Hermitian (w[n-t] = conj w[t]).
+void twiddles(int n, std::vector<double> &re, std::vector<double> &im) {
+  re.assign(n, 0.0);
+  im.assign(n, 0.0);
+  const long double tp = 6.283185307179586476925286766559005768L;
+  for (int t = 0; t <= n / 2; ++t) {
+    double c, s;
+    if ((4 * t) % n == 0) {
+      const int q = (4 * t) / n;  // 0, 1, 2
+      c = q == 0 ? 1.0 : (q == 1 ? 0.0 : -1.0);
+      s = q == 1 ? 1.0 : 0.0;
+    } else {
+      const long double ang = tp * (long double)t / (long double)n;
+      c = (double)cosl(ang);
+      s = (double)sinl(ang);
+    }
+    re[t] = c;
+    im[t] = -s;
+    if (t > 0 && t < n - t) {
+      re[n - t] = c;
+      im[n - t] = s;
+    }
+  }
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
+  const size_t S = (size_t)n3 * n2 * (n1 / 2 + 1);
+  return align_up(9 * S * (fp64 ? 16 : 8), 256);
+}
+
+int rows_per_block(int n1) { return std::max(1, kThreads / n1); }
+
+}  // namespace
+
+// hipEvent pairs around every launch on the context's stream; elapsed times
+// are summed per kernel when read
+class EventTimer : public KernelTimer {
+ public:
+  explicit EventTimer(hipStream_t s) : stream_(s) {}
+  ~EventTimer() override {
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+  }
+  void begin(int kid) override {
+    pending_kid_ = kid;
+    pending_ = take();
+    if (pending_) (void)hipEventRecord(pending_, stream_);
+  }
+  void end(int kid) override {
+    hipEvent_t e1 = take();
+    if (pending_ && e1 && kid == pending_kid_) {
+      (void)hipEventRecord(e1, stream_);
+      recs_.push_back({kid, pending_, e1});
+    }
+    pending_ = nullptr;
+  }
+  // folds recorded pairs into the totals; the stream must be synchronised
+  void collect() {
+    for (const Rec &r : recs_) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+        total_ms_[r.kid] += ms;
+        count_[r.kid] += 1;
+      }
+    }
+    recs_.clear();
+    used_ = 0;
+  }
+  void reset() {
+    recs_.clear();
+    used_ = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+      total_ms_[k] = 0.0;
+      count_[k] = 0;
+    }
+  }
+  double total_ms(int k) const { return total_ms_[k]; }
+  int count(int k) const { return count_[k]; }
+
+ private:
+  struct Rec {
+    int kid;
+    hipEvent_t e0, e1;
+  };
+  hipEvent_t take() {
+    if (used_ == pool_.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool_.push_back(e);
+    }
+    return pool_[used_++];
+  }
+  hipStream_t stream_;
+  std::vector<hipEvent_t> pool_;
+  size_t used_ = 0;
+  std::vector<Rec> recs_;
+  hipEvent_t pending_ = nullptr;
+  int pending_kid_ = -1;
+  double total_ms_[K_COUNT] = {};
+  int count_[K_COUNT] = {};
+};
+
+struct admm_ctx {
+  int n_rve = 0, n_mat = 0;
+  bool fp64 = true;
+  hipStream_t stream = nullptr;
+  admm_params params{};
+  std::vector<admm_rve> rves;
+  std::vector<RveDesc> desc_h;
+  std::vector<RveState> state_h;
+  int hist_cap = 0;
+  // device
+  RveDesc *desc_d = nullptr;
+  RveState *state_d = nullptr;
+  int *blk_d = nullptr;
+  Material *mats_d = nullptr;
+  void *tw_d = nullptr;
+  double2 *partials_d = nullptr;
+  double *partials18_d = nullptr;
+  double *mean_d = nullptr;
+  double *hist_d = nullptr;
+  void *workspace = nullptr;
+  bool own_workspace = false;
+  LaunchCfg L{};
+  KernelArgs A{};
+  EventTimer *timer = nullptr;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return ADMM_EHIP;   \
+  } while (0)
+
+int upload_states(admm_ctx *c) {
+  HIP_TRY(hipMemcpyAsync(c->state_d, c->state_h.data(), sizeof(RveState) * c->n_rve,
+                         hipMemcpyHostToDevice, c->stream));
+  return ADMM_OK;
+}
+
+int download_states(admm_ctx *c) {
+  HIP_TRY(hipMemcpyAsync(c->state_h.data(), c->state_d, sizeof(RveState) * c->n_rve,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->timer) c->timer->collect();
+  return ADMM_OK;
+}
+
+// after a launch sequence: read the state back and make `u` the current
+// fluctuation buffer of every cell again
+int settle(admm_ctx *c) {
+  int rc = download_states(c);
+  if (rc != ADMM_OK) return rc;
+  bool moved = false;
+  const size_t s = c->fp64 ? 8 : 4;
+  for (int r = 0; r < c->n_rve; ++r) {
+    if (c->state_h[r].cur == 1) {
+      const RveDesc &D = c->desc_h[r];
+      HIP_TRY(hipMemcpyAsync(D.u[0], D.u[1], 3 * (size_t)D.V * s, hipMemcpyDeviceToDevice,
+                             c->stream));
+      c->state_h[r].cur = 0;
+      moved = true;
+    }
+  }
+  if (moved) {
+    rc = upload_states(c);
+    if (rc != ADMM_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return ADMM_OK;
+}
+
+IterParams iter_params(const admm_ctx *c, int test_conv) {
+  const admm_params &p = c->params;
+  IterParams ip{};
+  ip.rho_min = p.rho_min;
+  ip.rho_max = p.rho_max;
+  ip.kappa_rho = p.kappa_rho;
+  ip.tau = p.tau;
+  ip.tol_p = p.tol_p;
+  ip.tol_d = p.tol_d;
+  ip.mu_ref = p.mu_ref;
+  ip.gtol = p.newton_gtol;
+  ip.step_tol = p.newton_step_tol;
+  ip.adapt = p.adapt_rho;
+  ip.max_iter = p.max_iter;
+  ip.newton_max = p.newton_max;
+  ip.test_conv = test_conv;
+  ip.hist_cap = c->hist_cap;
+  ip.n_rve = c->n_rve;
+  ip.n_mat = c->n_mat;
+  return ip;
+}
+
+int launch(admm_ctx *c, Part part, const IterParams &ip) {
+  hipError_t e = launch_part(c->L, c->A, ip, part, c->fp64);
+  return e == hipSuccess ? ADMM_OK : ADMM_EHIP;
+}
+
+int one_iteration(admm_ctx *c, const IterParams &ip) {
+  int rc = launch(c, Part::Local, ip);
+  if (rc == ADMM_OK) rc = launch(c, Part::ProjectRest, ip);
+  if (rc == ADMM_OK) rc = launch(c, Part::Update, ip);
+  return rc;
+}
+
+bool valid_fbar(const double *F) {
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(F[k])) return false;
+  const double d = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                   F[2] * (F[3] * F[7] - F[4] * F[6]);
+  return d > 0.0;
+}
+
+void free_ctx(admm_ctx *c) {
+  if (!c) return;
+  (void)hipFree(c->desc_d);
+  (void)hipFree(c->state_d);
+  (void)hipFree(c->blk_d);
+  (void)hipFree(c->mats_d);
+  (void)hipFree(c->tw_d);
+  (void)hipFree(c->partials_d);
+  (void)hipFree(c->partials18_d);
+  (void)hipFree(c->mean_d);
+  (void)hipFree(c->hist_d);
+  if (c->own_workspace) (void)hipFree(c->workspace);
+  delete c->timer;
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int admm_check_grid(int32_t n1, int32_t n2, int32_t n3) {
+  const int n[3] = {n1, n2, n3};
+  for (int k = 0; k < 3; ++k) {
+    if (n[k] <= 0) return ADMM_EINVAL;
+    if (n[k] % 2 != 0 || n[k] < 4 || n[k] > kMaxN || !is_2a3b(n[k])) return ADMM_EUNSUPPORTED;
+  }
+  return ADMM_OK;
+}
+
+size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precision) {
+  if (!rves || n_rve <= 0 || (precision != ADMM_FP64 && precision != ADMM_FP32_FP64RED)) return 0;
+  size_t total = 0;
+  for (int r = 0; r < n_rve; ++r) {
+    if (admm_check_grid(rves[r].n[0], rves[r].n[1], rves[r].n[2]) != ADMM_OK) return 0;
+    total += spec_bytes(rves[r].n[0], rves[r].n[1], rves[r].n[2], precision == ADMM_FP64);
+  }
+  return total;
+}
+
+const char *admm_strerror(int code) {
+  switch (code) {
+    case ADMM_OK: return "ok";
+    case ADMM_NOT_CONVERGED: return "not converged within the iteration cap";
+    case ADMM_EINVAL: return "invalid argument";
+    case ADMM_EUNSUPPORTED: return "unsupported grid size or model";
+    case ADMM_EHIP: return "HIP runtime error";
+    case ADMM_ENOMEM: return "workspace too small or allocation failed";
+    case ADMM_EDOMAIN: return "det F <= 0 or NaN met";
+    case ADMM_ENOGPU: return "no HIP device";
+    default: return "unknown status";
+  }
+}
+
+int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_material *mats,
+              int32_t n_mat, const admm_params *params, int32_t precision, void *workspace,
+              size_t workspace_bytes, void *hip_stream) {
+  if (!out) return ADMM_EINVAL;
+  *out = nullptr;
+  if (!rves || n_rve <= 0 || !mats || n_mat <= 0 || n_mat > 256 || !params) return ADMM_EINVAL;
+  if (precision != ADMM_FP64 && precision != ADMM_FP32_FP64RED) return ADMM_EINVAL;
+  for (int q = 0; q < n_mat; ++q) {
+    if (mats[q].model == ADMM_LCE) return ADMM_EUNSUPPORTED;
+    if (mats[q].model != ADMM_NEOHOOKE) return ADMM_EINVAL;
+    if (!(mats[q].mu > 0.0) || !(mats[q].lambda >= 0.0)) return ADMM_EINVAL;
+  }
+  const admm_params &p = *params;
+  if (!(p.rho0 > 0.0) || !(p.rho_min > 0.0) || !(p.rho_max >= p.rho_min) || !(p.kappa_rho > 1.0) ||
+      !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
+      p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0))
+    return ADMM_EINVAL;
+  for (int r = 0; r < n_rve; ++r) {
+    const admm_rve &R = rves[r];
+    int g = admm_check_grid(R.n[0], R.n[1], R.n[2]);
+    if (g != ADMM_OK) return g;
+    if (!R.phase || !R.u || !R.u_prev || !R.F || !R.Lambda || R.u == R.u_prev) return ADMM_EINVAL;
+    if (!valid_fbar(R.Fbar)) return ADMM_EINVAL;
+  }
+  const bool fp64 = precision == ADMM_FP64;
+  const size_t need = admm_workspace_bytes(rves, n_rve, precision);
+  if (workspace && workspace_bytes < need) return ADMM_ENOMEM;
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) % 256) != 0) return ADMM_EINVAL;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ADMM_ENOGPU;
+
+  admm_ctx *c = new (std::nothrow) admm_ctx();
+  if (!c) return ADMM_ENOMEM;
+  c->n_rve = n_rve;
+  c->n_mat = n_mat;
+  c->fp64 = fp64;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->params = p;
+  c->params.check_every = p.check_every > 0 ? p.check_every : 10;
+  c->rves.assign(rves, rves + n_rve);
+  c->hist_cap = std::min(std::max(p.max_iter, 64), 1 << 16);
+
+#define INIT_TRY(expr)        \
+  do {                        \
+    if ((expr) != hipSuccess) { \
+      free_ctx(c);            \
+      return ADMM_EHIP;       \
+    }                         \
+  } while (0)
+
+  // workspace
+  if (workspace) {
+    c->workspace = workspace;
+  } else {
+    if (hipMalloc(&c->workspace, need) != hipSuccess) {
+      free_ctx(c);
+      return ADMM_ENOMEM;
+    }
+    c->own_workspace = true;
+  }
+
+  // twiddle pool: one table per distinct length
+  std::map<int, int> tw_off;
+  std::vector<double> pool_re, pool_im;
+  for (int r = 0; r < n_rve; ++r)
+    for (int k = 0; k < 3; ++k) {
+      const int n = rves[r].n[k];
+      if (tw_off.count(n)) continue;
+      tw_off[n] = (int)pool_re.size();
+      std::vector<double> re, im;
+      twiddles(n, re, im);
+      pool_re.insert(pool_re.end(), re.begin(), re.end());
+      pool_im.insert(pool_im.end(), im.begin(), im.end());
+    }
+  const size_t ntw = pool_re.size();
+  if (fp64) {
+    std::vector<double2> h(ntw);
+    for (size_t k = 0; k < ntw; ++k) h[k] = double2{pool_re[k], pool_im[k]};
+    INIT_TRY(hipMalloc(&c->tw_d, ntw * sizeof(double2)));
+    INIT_TRY(hipMemcpy(c->tw_d, h.data(), ntw * sizeof(double2), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float2> h(ntw);
+    for (size_t k = 0; k < ntw; ++k) h[k] = float2{(float)pool_re[k], (float)pool_im[k]};
+    INIT_TRY(hipMalloc(&c->tw_d, ntw * sizeof(float2)));
+    INIT_TRY(hipMemcpy(c->tw_d, h.data(), ntw * sizeof(float2), hipMemcpyHostToDevice));
+  }
+
+  // descriptors and workgroup prefix tables
+  const int B = tile_b(fp64);
+  c->desc_h.resize(n_rve);
+  std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1);
+  bx[0] = by[0] = bz[0] = bu[0] = 0;
+  size_t spec_off = 0;
+  int n2max = 0, n3max = 0, lds_fwd = 0, lds_inv = 0;
+  for (int r = 0; r < n_rve; ++r) {
+    const admm_rve &R = rves[r];
+    RveDesc &D = c->desc_h[r];
+    std::memset(&D, 0, sizeof(D));
+    D.n1 = R.n[0];
+    D.n2 = R.n[1];
+    D.n3 = R.n[2];
+    D.m1 = D.n1 / 2 + 1;
+    D.V = (long long)D.n1 * D.n2 * D.n3;
+    D.S = (long long)D.n3 * D.n2 * D.m1;
+    D.rows = rows_per_block(D.n1);
+    D.p1 = make_plan(D.n1);
+    D.p2 = make_plan(D.n2);
+    D.p3 = make_plan(D.n3);
+    D.p1.tw = tw_off[D.n1];
+    D.p2.tw = tw_off[D.n2];
+    D.p3.tw = tw_off[D.n3];
+    D.phase = R.phase;
+    D.u[0] = R.u;
+    D.u[1] = R.u_prev;
+    D.E = R.F;
+    D.Lam = R.Lambda;
+    D.dir = R.director;
+    D.spec = static_cast<char *>(c->workspace) + spec_off;
+    spec_off += spec_bytes(D.n1, D.n2, D.n3, fp64);
+    for (int k = 0; k < 9; ++k) D.Ebar[k] = R.Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+    const int nrows = D.n2 * D.n3;
+    bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
+    by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
+    bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
+    bu[r + 1] = bu[r] + (int)((D.V + kThreads - 1) / kThreads);
+    n2max = std::max(n2max, D.n2);
+    n3max = std::max(n3max, D.n3);
+    lds_fwd = std::max(lds_fwd, 2 * ((9 * D.rows + 1) / 2) * D.n1);
+    lds_inv = std::max(lds_inv, 2 * ((3 * D.rows + 1) / 2) * D.n1);
+  }
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  c->L.timer = nullptr;
+  c->L.stream = c->stream;
+  c->L.nblk_x = bx[n_rve];
+  c->L.nblk_y = by[n_rve];
+  c->L.nblk_z = bz[n_rve];
+  c->L.nblk_u = bu[n_rve];
+  c->L.n2max = n2max;
+  c->L.n3max = n3max;
+  c->L.lds_x_fwd = (size_t)lds_fwd * csz;
+  c->L.lds_x_inv = (size_t)lds_inv * csz;
+
+  INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
+  INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
+  INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 4 * (n_rve + 1)));
+  std::vector<int> blk_h;
+  blk_h.insert(blk_h.end(), bx.begin(), bx.end());
+  blk_h.insert(blk_h.end(), by.begin(), by.end());
+  blk_h.insert(blk_h.end(), bz.begin(), bz.end());
+  blk_h.insert(blk_h.end(), bu.begin(), bu.end());
+  INIT_TRY(hipMemcpy(c->blk_d, blk_h.data(), sizeof(int) * blk_h.size(), hipMemcpyHostToDevice));
+
+  std::vector<Material> mh(n_mat);
+  for (int q = 0; q < n_mat; ++q) {
+    mh[q] = Material{mats[q].model, 0, mats[q].mu, mats[q].lambda, mats[q].a, mats[q].kappa};
+  }
+  INIT_TRY(hipMalloc(&c->mats_d, sizeof(Material) * n_mat));
+  INIT_TRY(hipMemcpy(c->mats_d, mh.data(), sizeof(Material) * n_mat, hipMemcpyHostToDevice));
+
+  INIT_TRY(hipMalloc(&c->partials_d, sizeof(double2) * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMalloc(&c->partials18_d, sizeof(double) * 18 * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
+  INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
+
+  c->state_h.assign(n_rve, RveState{});
+  for (int r = 0; r < n_rve; ++r) {
+    RveState &s = c->state_h[r];
+    s.rho = p.rho0;
+    s.rho_used = p.rho0;
+    s.active = 1;
+    s.status = ST_RUNNING;
+  }
+  INIT_TRY(hipMalloc(&c->state_d, sizeof(RveState) * n_rve));
+  INIT_TRY(hipMemcpy(c->state_d, c->state_h.data(), sizeof(RveState) * n_rve, hipMemcpyHostToDevice));
+
+  KernelArgs &A = c->A;
+  A.desc = c->desc_d;
+  A.state = c->state_d;
+  A.blk_x = c->blk_d;
+  A.blk_y = c->blk_d + (n_rve + 1);
+  A.blk_z = c->blk_d + 2 * (n_rve + 1);
+  A.blk_u = c->blk_d + 3 * (n_rve + 1);
+  A.mats = c->mats_d;
+  A.tw = c->tw_d;
+  A.partials = c->partials_d;
+  A.partials18 = c->partials18_d;
+  A.mean_out = c->mean_d;
+  A.hist = c->hist_d;
+  A.n_rve = n_rve;
+  A.n_mat = n_mat;
+#undef INIT_TRY
+  *out = c;
+  return ADMM_OK;
+}
+
+void admm_destroy(admm_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+}
+
+int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
+  if (!ctx || !Fbar || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
+  if (!valid_fbar(Fbar)) return ADMM_EINVAL;
+  RveDesc &D = ctx->desc_h[rve];
+  for (int k = 0; k < 9; ++k) {
+    ctx->rves[rve].Fbar[k] = Fbar[k];
+    D.Ebar[k] = Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->desc_d + rve, &D, sizeof(RveDesc), hipMemcpyHostToDevice, ctx->stream));
+  RveState &s = ctx->state_h[rve];
+  s.iter = 0;
+  s.active = 1;
+  s.status = ST_RUNNING;
+  s.newton_fail = 0;
+  s.domain_err = 0;
+  int rc = upload_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ADMM_OK;
+}
+
+int admm_set_rho(admm_ctx *ctx, int32_t rve, double rho) {
+  if (!ctx || !(rho > 0.0) || rve >= ctx->n_rve) return ADMM_EINVAL;
+  for (int r = 0; r < ctx->n_rve; ++r)
+    if (rve < 0 || r == rve) ctx->state_h[r].rho = rho;
+  int rc = upload_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ADMM_OK;
+}
+
+// admm_step and the single-part entry points run every cell that has not
+// failed, whatever its convergence state
+static int activate_all(admm_ctx *ctx) {
+  for (auto &s : ctx->state_h) {
+    s.active = s.status == ST_DOMAIN ? 0 : 1;
+    if (s.status != ST_DOMAIN) s.status = ST_RUNNING;
+  }
+  return upload_states(ctx);
+}
+
+static int any_domain(const admm_ctx *ctx) {
+  for (const auto &s : ctx->state_h)
+    if (s.status == ST_DOMAIN || s.domain_err) return 1;
+  return 0;
+}
+
+int admm_step(admm_ctx *ctx, int32_t n_iter, double *r_p, double *r_d, double *rho) {
+  if (!ctx || n_iter < 0) return ADMM_EINVAL;
+  int rc = activate_all(ctx);
+  if (rc != ADMM_OK) return rc;
+  const IterParams ip = iter_params(ctx, 0);
+  for (int it = 0; it < n_iter && rc == ADMM_OK; ++it) rc = one_iteration(ctx, ip);
+  if (rc != ADMM_OK) return rc;
+  rc = settle(ctx);
+  if (rc != ADMM_OK) return rc;
+  for (int r = 0; r < ctx->n_rve; ++r) {
+    if (r_p) r_p[r] = ctx->state_h[r].rp;
+    if (r_d) r_d[r] = ctx->state_h[r].rd;
+    if (rho) rho[r] = ctx->state_h[r].rho;
+  }
+  return any_domain(ctx) ? ADMM_EDOMAIN : ADMM_OK;
+}
+
+int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out) {
+  if (!ctx) return ADMM_EINVAL;
+  for (auto &s : ctx->state_h) s.active = (s.status == ST_RUNNING) ? 1 : 0;
+  int rc = upload_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  const IterParams ip = iter_params(ctx, 1);
+  const int every = ctx->params.check_every;
+  for (;;) {
+    bool any = false;
+    for (const auto &s : ctx->state_h) any = any || s.active;
+    if (!any) break;
+    for (int k = 0; k < every && rc == ADMM_OK; ++k) rc = one_iteration(ctx, ip);
+    if (rc != ADMM_OK) return rc;
+    rc = download_states(ctx);
+    if (rc != ADMM_OK) return rc;
+  }
+  rc = settle(ctx);
+  if (rc != ADMM_OK) return rc;
+  int all = ADMM_OK;
+  for (int r = 0; r < ctx->n_rve; ++r) {
+    const RveState &s = ctx->state_h[r];
+    int st = s.status == ST_CONVERGED ? ADMM_OK
+             : s.status == ST_DOMAIN  ? ADMM_EDOMAIN
+                                      : ADMM_NOT_CONVERGED;
+    if (iters_out) iters_out[r] = s.iter;
+    if (status_out) status_out[r] = st;
+    if (st == ADMM_EDOMAIN) all = ADMM_EDOMAIN;
+    else if (st == ADMM_NOT_CONVERGED && all == ADMM_OK) all = ADMM_NOT_CONVERGED;
+  }
+  return all;
+}
+
+int admm_local_step(admm_ctx *ctx) {
+  if (!ctx) return ADMM_EINVAL;
+  int rc = activate_all(ctx);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::Local, iter_params(ctx, 0));
+  if (rc == ADMM_OK) rc = download_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  return any_domain(ctx) ? ADMM_EDOMAIN : ADMM_OK;
+}
+
+int admm_project_step(admm_ctx *ctx) {
+  if (!ctx) return ADMM_EINVAL;
+  int rc = activate_all(ctx);
+  const IterParams ip = iter_params(ctx, 0);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::FormH, ip);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::ProjectRest, ip);
+  if (rc == ADMM_OK) rc = download_states(ctx);
+  return rc;
+}
+
+int admm_update_step(admm_ctx *ctx) {
+  if (!ctx) return ADMM_EINVAL;
+  int rc = activate_all(ctx);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::Update, iter_params(ctx, 0));
+  if (rc == ADMM_OK) rc = settle(ctx);
+  if (rc != ADMM_OK) return rc;
+  return any_domain(ctx) ? ADMM_EDOMAIN : ADMM_OK;
+}
+
+int admm_homogenized_stress(admm_ctx *ctx, int32_t rve, double P_out[9], double Lambda_out[9]) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve || !P_out) return ADMM_EINVAL;
+  int rc = launch(ctx, Part::MeanStress, iter_params(ctx, 0));
+  if (rc != ADMM_OK) return rc;
+  double h[18];
+  HIP_TRY(hipMemcpyAsync(h, ctx->mean_d + 18 * rve, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  rc = download_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  for (int k = 0; k < 9; ++k) {
+    P_out[k] = h[k];
+    if (Lambda_out) Lambda_out[k] = h[9 + k];
+  }
+  return ctx->state_h[rve].domain_err ? ADMM_EDOMAIN : ADMM_OK;
+}
+
+int admm_history(admm_ctx *ctx, int32_t rve, int32_t max_n, double *r_p, double *r_d, double *rho,
+                 int32_t *n_out) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve || max_n < 0) return ADMM_EINVAL;
+  const int n = std::min(std::min(ctx->state_h[rve].iter, ctx->hist_cap), (int)max_n);
+  std::vector<double> h(3 * (size_t)std::max(n, 1));
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->hist_d + (size_t)rve * ctx->hist_cap * 3,
+                           sizeof(double) * 3 * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  for (int k = 0; k < n; ++k) {
+    if (r_p) r_p[k] = h[3 * k];
+    if (r_d) r_d[k] = h[3 * k + 1];
+    if (rho) rho[k] = h[3 * k + 2];
+  }
+  if (n_out) *n_out = n;
+  return ADMM_OK;
+}
+
+int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
+                   int32_t *newton_fail) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
+  const RveState &s = ctx->state_h[rve];
+  if (iters) *iters = s.iter;
+  if (status)
+    *status = s.status == ST_CONVERGED ? ADMM_OK
+              : s.status == ST_DOMAIN  ? ADMM_EDOMAIN
+              : s.status == ST_CAP     ? ADMM_NOT_CONVERGED
+                                       : ADMM_OK;
+  if (newton_fail) *newton_fail = s.newton_fail;
+  return ADMM_OK;
+}
+
+int admm_profile_enable(admm_ctx *ctx, int32_t on) {
+  if (!ctx) return ADMM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (on) {
+    if (!ctx->timer) ctx->timer = new (std::nothrow) EventTimer(ctx->stream);
+    if (!ctx->timer) return ADMM_ENOMEM;
+    ctx->timer->reset();
+    ctx->L.timer = ctx->timer;
+  } else {
+    ctx->L.timer = nullptr;
+  }
+  return ADMM_OK;
+}
+
+int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *launches) {
+  if (!ctx || kernel < 0 || kernel >= K_COUNT) return ADMM_EINVAL;
+  if (!ctx->timer) {
+    if (total_ms) *total_ms = 0.0;
+    if (launches) *launches = 0;
+    return ADMM_OK;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->timer->collect();
+  if (total_ms) *total_ms = ctx->timer->total_ms(kernel);
+  if (launches) *launches = ctx->timer->count(kernel);
+  return ADMM_OK;
+}
+
+}  // extern "C"

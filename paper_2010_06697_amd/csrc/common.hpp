@@ -1,0 +1,100 @@
+// common.hpp -- device-side data structures shared by the ADMM kernels and the
+// host launcher (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace admm {
+
+constexpr int kThreads = 256;   // threads per workgroup of every kernel
+constexpr int kMaxStages = 8;   // radix stages of one 1D transform
+constexpr int kMaxN = 256;      // largest supported edge
+
+// radix plan of one 1D transform of length n; tw: offset of its twiddle table
+// exp(-2 pi i t / n), t = 0..n-1, in the twiddle pool
+struct Plan1D {
+  int n;
+  int nst;
+  int rad[kMaxStages];
+  int tw;
+};
+
+// one periodic cell, as the kernels see it
+struct RveDesc {
+  int n1, n2, n3, m1;       // m1 = n1/2 + 1 (half spectrum along x1)
+  long long V;              // voxels
+  long long S;              // complex entries of one spectral component
+  int rows;                 // x1-rows per workgroup of the x-pass kernels
+  int pad0;
+  Plan1D p1, p2, p3;
+  const uint8_t *phase;
+  void *u[2];               // displacement fluctuation, ping-pong
+  void *E;                  // F - I
+  void *Lam;                // multiplier
+  void *dir;                // director (LCE) or null
+  void *spec;               // 9 spectral components, layout [c][x3][x2][m1]
+  double Ebar[9];           // Fbar - I
+};
+
+// per-cell iteration state, updated on the device
+struct RveState {
+  double rho;        // penalty of the next iteration
+  double rho_used;   // penalty of the last iteration
+  double rp, rd;     // residuals of the last iteration
+  int iter;          // iterations of the current load step
+  int cur;           // which u buffer holds u_i
+  int active;        // 1 while the cell iterates
+  int status;        // 0 running, 1 iteration cap, 2 converged, -5 domain error
+  int newton_fail;   // local solves that hit the Newton cap
+  int domain_err;    // set when det F <= 0 or NaN met
+  int pad0, pad1;
+};
+
+struct Material {
+  int model;
+  int pad;
+  double mu, lam, a, kappa;
+};
+
+// scalar parameters of one launch sequence (passed by value: kernel arguments
+// live in the constant/scalar path of the hardware)
+struct IterParams {
+  double rho_min, rho_max, kappa_rho, tau;
+  double tol_p, tol_d, mu_ref;
+  double gtol, step_tol;
+  int adapt;
+  int max_iter;
+  int newton_max;
+  int test_conv;     // 1: convergence test and iteration cap (admm_solve)
+  int hist_cap;
+  int n_rve;
+  int n_mat;
+  int pad;
+};
+
+template <typename T> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup i -> XCD i % 8).
+// Remap so that each XCD receives a contiguous range of logical tiles: tiles
+// that share halo rows then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int nx = 8;
+  int x = bid % nx, k = bid / nx;
+  int per = nblk / nx, rem = nblk % nx;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// cell owning logical workgroup `blk`, given the prefix table blk0[0..n]
+__device__ __forceinline__ int find_rve(const int *__restrict__ blk0, int n, int blk) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (blk0[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace admm

@@ -1,0 +1,153 @@
+// fft.hpp -- mixed-radix (2, 3, 4, 8) self-sorting Stockham FFT on lines held
+// in LDS, cooperatively by all threads of a workgroup.
+//
+// A transform of length N = prod R_s runs one stage per radix. At a stage with
+// radix R, after Ns = R_1 ... R_{s-1}, butterfly j (0 <= j < N/R) reads
+// x[j + r N/R], multiplies element r by w^{(j mod Ns) r N/(Ns R)} with
+// w = exp(-2 pi i / N), takes the length-R DFT and writes element r to
+// (j - j mod Ns) R + (j mod Ns) + r Ns of the other buffer (the Stockham
+// autosort formulation, so no bit reversal is needed). Forward transforms use
+// exp(-2 pi i m k / N), inverse ones exp(+...), both unnormalised.
+#pragma once
+
+#include "common.hpp"
+
+namespace admm {
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C rot90(C a) {
+  return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft2(C *v) {
+  C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft3(C *v) {
+  using T = decltype(v[0].x);
+  const T h = (T)0.86602540378443864676372317075294;  // sqrt(3)/2
+  C a = v[0], b = v[1], c = v[2];
+  C t1 = cadd(b, c);
+  C t2 = C{a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y};
+  C d = csub(b, c);
+  C t3 = rot90<INV>(C{h * d.x, h * d.y});
+  v[0] = cadd(a, t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C *v) {
+  C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  C t2 = cadd(v[1], v[3]), t3 = rot90<INV>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft8(C *v) {
+  using T = decltype(v[0].x);
+  const T c = (T)0.70710678118654752440084436210485;  // sqrt(2)/2
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  // o_k *= w8^k, w8 = exp(-+ 2 pi i / 8)
+  C o1 = o[1], o3 = o[3];
+  if (!INV) {
+    o[1] = C{c * (o1.x + o1.y), c * (o1.y - o1.x)};
+    o[3] = C{c * (o3.y - o3.x), -c * (o3.x + o3.y)};
+  } else {
+    o[1] = C{c * (o1.x - o1.y), c * (o1.x + o1.y)};
+    o[3] = C{-c * (o3.x + o3.y), c * (o3.x - o3.y)};
+  }
+  o[2] = rot90<INV>(o[2]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, bool INV, typename C> __device__ __forceinline__ void dftR(C *v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else dft8<INV>(v);
+}
+
+// One radix-R stage over `nlines` lines. Element k of line l lives at
+// buf[l*ls + k*es]. lfast: consecutive threads take consecutive lines (for the
+// [k][line] layouts) instead of consecutive butterflies of one line.
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void fft_stage(const C *__restrict__ src, C *__restrict__ dst, int N,
+                                          int Ns, int nlines, int ls, int es, bool lfast,
+                                          const C *__restrict__ tw, int tid, int nthr) {
+  const int nb = N / R;
+  const int total = nb * nlines;
+  const int twstep = N / (Ns * R);
+  for (int w = tid; w < total; w += nthr) {
+    int l, j;
+    if (lfast) {
+      l = w % nlines;
+      j = w / nlines;
+    } else {
+      j = w % nb;
+      l = w / nb;
+    }
+    const C *s = src + l * ls;
+    C *d = dst + l * ls;
+    const int jm = j % Ns;
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[(j + r * nb) * es];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C t = tw[jm * r * twstep];
+        v[r] = INV ? cmulc(v[r], t) : cmul(v[r], t);
+      }
+    }
+    dftR<R, INV>(v);
+    const int o = (j - jm) * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[(o + r * Ns) * es] = v[r];
+  }
+}
+
+// Transforms every line; a and b are two LDS buffers of the same shape, a
+// holds the input. Returns the buffer holding the result. Ends with a barrier.
+template <bool INV, typename C>
+__device__ C *fft_lines(C *a, C *b, const Plan1D &p, const C *__restrict__ twpool, int nlines,
+                        int ls, int es, bool lfast, int tid, int nthr) {
+  const C *tw = twpool + p.tw;
+  int Ns = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int R = p.rad[s];
+    switch (R) {
+      case 2: fft_stage<2, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
+      case 3: fft_stage<3, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
+      case 4: fft_stage<4, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
+      default: fft_stage<8, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
+    }
+    __syncthreads();
+    C *t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+}  // namespace admm

@@ -1,0 +1,607 @@
+// kernels.hip -- the HIP kernels of one ADMM iteration (gfx950) and their
+// host launchers.
+//
+// Per iteration, over every active cell of the batch, in this order:
+//   k_local_fwdx   Step 1 (local Newton per voxel) fused with forming
+//                  H = F - Lambda/rho and the forward real-to-complex FFT
+//                  along x1 (two real rows per complex transform)
+//   k_fft_y        forward FFT along x2 of the 9 half-spectrum components
+//   k_green_z      forward FFT along x3, the Fourier-space solve of Step 2
+//                  (u_i = -i sum_j K_j H_ij / |K|^2, K_j = sin(2 pi m_j/n_j),
+//                  zero on the eight null modes, scaled by 1/V) and the
+//                  inverse FFT along x3 of the 3 displacement components
+//   k_fft_y        inverse FFT along x2 of the 3 components
+//   k_inv_x        inverse complex-to-real FFT along x1 into u_{i+1}
+//   k_update       Step 3 (Lambda += rho (grad u_{i+1} - F)) and the
+//                  per-workgroup partial sums of Step 4
+//   k_finalize     fixed-order reduction of the partials, r_p, r_d, the
+//                  convergence test and the adaptive penalty (Sec. 2.1)
+// All scalar iteration state (rho, residuals, which u buffer is current,
+// activity) lives in device memory, so the host only launches.
+#include "common.hpp"
+#include "fft.hpp"
+#include "launch.hpp"
+#include "material.hpp"
+
+namespace admm {
+
+// ----------------------------------------------------------------------------
+// helpers
+// ----------------------------------------------------------------------------
+
+// periodic central difference (u(x+e_j) - u(x-e_j))/2 of the three
+// components of u at voxel (x1,x2,x3); out[3i+j]
+template <typename T>
+__device__ __forceinline__ void grad_u(const T *__restrict__ u, long long V, int n1, int n2, int n3,
+                                       int x1, int x2, int x3, double *out) {
+  const int x1p = x1 + 1 == n1 ? 0 : x1 + 1, x1m = x1 == 0 ? n1 - 1 : x1 - 1;
+  const int x2p = x2 + 1 == n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
+  const int x3p = x3 + 1 == n3 ? 0 : x3 + 1, x3m = x3 == 0 ? n3 - 1 : x3 - 1;
+  const long long row = ((long long)x3 * n2 + x2) * n1;
+  const long long o[6] = {row + x1p, row + x1m,
+                          ((long long)x3 * n2 + x2p) * n1 + x1, ((long long)x3 * n2 + x2m) * n1 + x1,
+                          ((long long)x3p * n2 + x2) * n1 + x1, ((long long)x3m * n2 + x2) * n1 + x1};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T *ui = u + i * V;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      out[3 * i + j] = 0.5 * ((double)ui[o[2 * j]] - (double)ui[o[2 * j + 1]]);
+  }
+}
+
+// deterministic sum of NV doubles over the workgroup; result valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwaves */) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * nw + wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[k * nw + w];
+      v[k] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Step 1 + H + forward FFT along x1
+// ----------------------------------------------------------------------------
+
+template <typename T, bool DO_LOCAL>
+__global__ __launch_bounds__(kThreads) void k_local_fwdx(KernelArgs a, IterParams ip) {
+  using C = typename cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  RveState *st = a.state + r;
+  if (!st->active) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int nrows = n2 * n3;
+  const int row0 = b * R;
+  const int ncl = (9 * R + 1) / 2;
+  const long long V = D.V, S = D.S;
+  C *za = reinterpret_cast<C *>(smem);
+  C *zb = za + ncl * n1;
+  const int t = threadIdx.x;
+  const double rho = st->rho;
+  const double irho = 1.0 / rho;
+
+  for (int w = t; w < ncl * n1; w += blockDim.x) za[w] = C{(T)0, (T)0};
+  __syncthreads();
+
+  const int row = t / n1, x1 = t - row * n1;
+  const int grow = row0 + row;
+  if (row < R && grow < nrows) {
+    const int x2 = grow % n2, x3 = grow / n2;
+    const long long idx = (long long)grow * n1 + x1;
+    const T *u = static_cast<const T *>(D.u[st->cur]);
+    T *Eg = static_cast<T *>(D.E);
+    const T *Lg = static_cast<const T *>(D.Lam);
+    double Du[9], E[9], Lm[9], A[9];
+    grad_u(u, V, n1, n2, n3, x1, x2, x3, Du);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      E[c] = (double)Eg[c * V + idx];
+      Lm[c] = (double)Lg[c * V + idx];
+      A[c] = D.Ebar[c] + Du[c] + Lm[c] * irho;
+    }
+    const int ph = D.phase[idx];
+    if (ph >= a.n_mat) atomicOr(&st->domain_err, 2);  // invalid phase index
+    if (DO_LOCAL && ph < a.n_mat) {
+      const Material m = a.mats[ph];
+      const int rc = nh_newton<T>(E, A, rho, m.mu, m.lam, ip.newton_max, ip.gtol, ip.step_tol);
+      if (rc == -1) atomicAdd(&st->newton_fail, 1);
+      if (rc == -2) atomicOr(&st->domain_err, 1);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Eg[c * V + idx] = (T)E[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const int ell = c * R + row;
+      C *z = za + (ell >> 1) * n1 + x1;
+      // in the reduced mode E is rounded to storage precision first, so that
+      // the projected field is the one Step 3 sees
+      const T h = (T)((double)(T)E[c] - Lm[c] * irho);
+      if (ell & 1) z->y = h; else z->x = h;
+    }
+  }
+  __syncthreads();
+  const C *tw = static_cast<const C *>(a.tw);
+  C *res = fft_lines<false>(za, zb, D.p1, tw, ncl, n1, 1, false, t, (int)blockDim.x);
+
+  C *spec = static_cast<C *>(D.spec);
+  for (int w = t; w < ncl * m1; w += blockDim.x) {
+    const int p = w / m1, m = w - p * m1;
+    const C Zm = res[p * n1 + m];
+    const C Zn = res[p * n1 + (m == 0 ? 0 : n1 - m)];
+    const C Av = C{(T)0.5 * (Zm.x + Zn.x), (T)0.5 * (Zm.y - Zn.y)};
+    const C Bv = C{(T)0.5 * (Zm.y + Zn.y), (T)(-0.5) * (Zm.x - Zn.x)};
+    const int la = 2 * p, lb = 2 * p + 1;
+    {
+      const int c = la / R, rw = la - c * R;
+      if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Av;
+    }
+    if (lb < 9 * R) {
+      const int c = lb / R, rw = lb - c * R;
+      if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Bv;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// FFT along x2 of ncomp spectral components (blockIdx.y = component)
+// ----------------------------------------------------------------------------
+
+template <typename T, int B, bool INV>
+__global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
+  using C = typename cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_y, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  if (!a.state[r].active) return;
+  const int b = blk - a.blk_y[r];
+  const int n2 = D.n2, m1 = D.m1;
+  const int nty = (m1 + B - 1) / B;
+  const int x3 = b / nty, m0 = (b - x3 * nty) * B;
+  C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + (long long)x3 * n2 * m1;
+  C *za = reinterpret_cast<C *>(smem);
+  C *zb = za + n2 * B;
+  const int t = threadIdx.x;
+  for (int w = t; w < n2 * B; w += blockDim.x) {
+    const int x2 = w / B, bb = w - x2 * B;
+    za[w] = (m0 + bb < m1) ? base[(long long)x2 * m1 + m0 + bb] : C{(T)0, (T)0};
+  }
+  __syncthreads();
+  const C *tw = static_cast<const C *>(a.tw);
+  C *res = fft_lines<INV>(za, zb, D.p2, tw, B, 1, B, true, t, (int)blockDim.x);
+  for (int w = t; w < n2 * B; w += blockDim.x) {
+    const int x2 = w / B, bb = w - x2 * B;
+    if (m0 + bb < m1) base[(long long)x2 * m1 + m0 + bb] = res[w];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// FFT along x3 + Fourier-space solve of Step 2 + inverse FFT along x3
+// ----------------------------------------------------------------------------
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void k_green_z(KernelArgs a) {
+  using C = typename cplx<T>::type;
+  constexpr int PMAX = (kMaxN * B) / kThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_z, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  if (!a.state[r].active) return;
+  const int b = blk - a.blk_z[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, m1 = D.m1;
+  const long long plane = (long long)n2 * m1;  // stride between x3 planes
+  const int nq = n2 * m1;
+  const int q0 = b * B;
+  const int npts = n3 * B;
+  C *spec = static_cast<C *>(D.spec);
+  const C *tw = static_cast<const C *>(a.tw);
+  C *za = reinterpret_cast<C *>(smem);
+  C *zb = za + n3 * B;
+  const int t = threadIdx.x, nthr = blockDim.x;
+
+  C acc[3][PMAX];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) acc[i][k] = C{(T)0, (T)0};
+
+  // the row index i of H_ij selects the accumulator: unrolled, so that the
+  // accumulators stay in registers
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+  for (int j = 0; j < 3; ++j) {
+    const int c = 3 * i + j;
+    const C *src = spec + c * D.S + q0;
+    for (int w = t; w < npts; w += nthr) {
+      const int x3 = w / B, bb = w - x3 * B;
+      za[w] = (q0 + bb < nq) ? src[x3 * plane + bb] : C{(T)0, (T)0};
+    }
+    __syncthreads();
+    C *res = fft_lines<false>(za, zb, D.p3, tw, B, 1, B, true, t, nthr);
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int p = t + k * nthr;
+      if (p < npts) {
+        const int m3 = p / B, bb = p - m3 * B;
+        const int q = q0 + bb;
+        const int m2 = q / m1, mm1 = q - m2 * m1;
+        T K;
+        if (j == 0) K = -tw[D.p1.tw + mm1].y;
+        else if (j == 1) K = -tw[D.p2.tw + (m2 < n2 ? m2 : 0)].y;
+        else K = -tw[D.p3.tw + m3].y;
+        const C h = res[p];
+        acc[i][k].x += K * h.x;
+        acc[i][k].y += K * h.y;
+      }
+    }
+    __syncthreads();
+  }
+
+  const double iV = 1.0 / (double)D.V;
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int p = t + k * nthr;
+    if (p < npts) {
+      const int m3 = p / B, bb = p - m3 * B;
+      const int q = q0 + bb;
+      const int m2 = q / m1, mm1 = q - m2 * m1;
+      const double K1 = -(double)tw[D.p1.tw + mm1].y;
+      const double K2 = -(double)tw[D.p2.tw + (m2 < n2 ? m2 : 0)].y;
+      const double K3 = -(double)tw[D.p3.tw + m3].y;
+      const bool null = (mm1 == 0 || 2 * mm1 == n1) && (m2 == 0 || 2 * m2 == n2) &&
+                        (m3 == 0 || 2 * m3 == n3);
+      const double k2 = K1 * K1 + K2 * K2 + K3 * K3;
+      const T s = null ? (T)0 : (T)(iV / k2);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {  // -i * acc * s
+        const C v = acc[i][k];
+        acc[i][k] = C{v.y * s, -v.x * s};
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      const int p = t + k * nthr;
+      if (p < npts) za[p] = acc[i][k];
+    }
+    __syncthreads();
+    C *res = fft_lines<true>(za, zb, D.p3, tw, B, 1, B, true, t, nthr);
+    C *dst = spec + i * D.S + q0;
+    for (int w = t; w < npts; w += nthr) {
+      const int x3 = w / B, bb = w - x3 * B;
+      if (q0 + bb < nq) dst[x3 * plane + bb] = res[w];
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// inverse complex-to-real FFT along x1 into u_{i+1}
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
+  using C = typename cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  if (!st->active) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int nrows = n2 * n3;
+  const int row0 = b * R;
+  const int ncl = (3 * R + 1) / 2;
+  const long long V = D.V, S = D.S;
+  const C *spec = static_cast<const C *>(D.spec);
+  C *za = reinterpret_cast<C *>(smem);
+  C *zb = za + ncl * n1;
+  const int t = threadIdx.x, nthr = blockDim.x;
+  const int h = n1 / 2;
+
+  // Z[k] = A[k] + i B[k] over the full length from the half spectra of the
+  // two real lines (A, B Hermitian; DC and Nyquist taken as real)
+  for (int w = t; w < ncl * n1; w += nthr) {
+    const int p = w / n1, k = w - p * n1;
+    const int kk = k <= h ? k : n1 - k;
+    C Av = C{(T)0, (T)0}, Bv = C{(T)0, (T)0};
+    const int la = 2 * p, lb = 2 * p + 1;
+    {
+      const int c = la / R, rw = la - c * R;
+      if (row0 + rw < nrows) Av = spec[c * S + (long long)(row0 + rw) * m1 + kk];
+    }
+    if (lb < 3 * R) {
+      const int c = lb / R, rw = lb - c * R;
+      if (row0 + rw < nrows) Bv = spec[c * S + (long long)(row0 + rw) * m1 + kk];
+    }
+    if (kk == 0 || kk == h) {
+      Av.y = (T)0;
+      Bv.y = (T)0;
+    }
+    if (k > h) {
+      Av.y = -Av.y;
+      Bv.y = -Bv.y;
+    }
+    za[w] = C{Av.x - Bv.y, Av.y + Bv.x};
+  }
+  __syncthreads();
+  const C *tw = static_cast<const C *>(a.tw);
+  C *res = fft_lines<true>(za, zb, D.p1, tw, ncl, n1, 1, false, t, nthr);
+  T *un = static_cast<T *>(D.u[1 - st->cur]);
+  for (int w = t; w < 3 * R * n1; w += nthr) {
+    const int ell = w / n1, x1 = w - ell * n1;
+    const int c = ell / R, rw = ell - c * R;
+    const int grow = row0 + rw;
+    if (grow < nrows) {
+      const C v = res[(ell >> 1) * n1 + x1];
+      un[c * V + (long long)grow * n1 + x1] = (ell & 1) ? v.y : v.x;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Step 3 + partial sums of Step 4
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
+  __shared__ double red[2 * (kThreads / 64)];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_u, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  RveState *st = a.state + r;
+  if (!st->active) return;
+  const int b = blk - a.blk_u[r];
+  const long long V = D.V;
+  const long long idx = (long long)b * kThreads + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (idx < V) {
+    const int n1 = D.n1, n2 = D.n2, n3 = D.n3;
+    const int x1 = (int)(idx % n1);
+    const long long rest = idx / n1;
+    const int x2 = (int)(rest % n2), x3 = (int)(rest / n2);
+    const double rho = st->rho;
+    const T *un = static_cast<const T *>(D.u[1 - st->cur]);
+    const T *uo = static_cast<const T *>(D.u[st->cur]);
+    const T *Eg = static_cast<const T *>(D.E);
+    T *Lg = static_cast<T *>(D.Lam);
+    double Dn[9], Do[9];
+    grad_u(un, V, n1, n2, n3, x1, x2, x3, Dn);
+    grad_u(uo, V, n1, n2, n3, x1, x2, x3, Do);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const double e = D.Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
+      Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
+      const double dd = Dn[c] - Do[c];
+      v[0] += e * e;
+      v[1] += dd * dd;
+    }
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) a.partials[blk] = double2{v[0], v[1]};
+}
+
+// ----------------------------------------------------------------------------
+// Step 4: residuals, convergence test, adaptive penalty (one workgroup / cell)
+// ----------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams ip) {
+  __shared__ double red[2 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  RveState *st = a.state + r;
+  if (!st->active) return;
+  const int p0 = a.blk_u[r], nb = a.blk_u[r + 1] - p0;
+  double v[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    const double2 q = a.partials[p0 + k];
+    v[0] += q.x;
+    v[1] += q.y;
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x != 0) return;
+  const double V = (double)a.desc[r].V;
+  const double rho = st->rho;
+  const double rp = sqrt(v[0] / V);
+  const double rd = rho / ip.mu_ref * sqrt(v[1] / V);
+  const int it = st->iter;
+  if (it < ip.hist_cap) {
+    double *h = a.hist + ((long long)r * ip.hist_cap + it) * 3;
+    h[0] = rp;
+    h[1] = rd;
+    h[2] = rho;
+  }
+  st->rp = rp;
+  st->rd = rd;
+  st->rho_used = rho;
+  st->iter = it + 1;
+  st->cur ^= 1;
+  if (st->domain_err || !(rp == rp) || !(rd == rd)) {
+    st->status = -5;
+    st->active = 0;
+    return;
+  }
+  if (ip.test_conv && rp <= ip.tol_p && rd <= ip.tol_d) {
+    st->status = 2;  // converged
+    st->active = 0;
+    return;
+  }
+  if (ip.adapt) {
+    double nr = rho;
+    if (rp > ip.tau * rd) nr = ip.kappa_rho * rho;
+    else if (rd > ip.tau * rp) nr = fmax(rho / ip.kappa_rho, ip.rho_min);
+    if (nr > ip.rho_max) nr = ip.rho_max;
+    st->rho = nr;
+  }
+  if (ip.test_conv && it + 1 >= ip.max_iter) {
+    st->status = 1;
+    st->active = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// homogenised stress: partial sums of P(F) and Lambda (double)
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
+  __shared__ double red[18 * (kThreads / 64)];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_u, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const int b = blk - a.blk_u[r];
+  const long long V = D.V;
+  const long long idx = (long long)b * kThreads + threadIdx.x;
+  double v[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) v[k] = 0.0;
+  int bad = 0;
+  if (idx < V) {
+    const T *Eg = static_cast<const T *>(D.E);
+    const T *Lg = static_cast<const T *>(D.Lam);
+    double E[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      E[c] = (double)Eg[c * V + idx];
+      v[9 + c] = (double)Lg[c * V + idx];
+    }
+    const int ph = D.phase[idx];
+    NHPoint s;
+    // with rho = 0 the gradient of the prox objective is the stress P
+    if (ph < a.n_mat && nh_point(E, E, 0.0, a.mats[ph].mu, a.mats[ph].lam, s)) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) v[c] = s.g[c];
+    } else {
+      bad = 1;
+    }
+  }
+  if (bad) atomicOr(&a.state[r].domain_err, 1);
+  block_sum<18>(v, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a.partials18[(long long)blk * 18 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_mean_final(KernelArgs a) {
+  __shared__ double red[18 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  const int p0 = a.blk_u[r], nb = a.blk_u[r + 1] - p0;
+  double v[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) v[k] = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 18; ++k) v[k] += a.partials18[(long long)(p0 + q) * 18 + k];
+  block_sum<18>(v, red);
+  if (threadIdx.x == 0) {
+    const double iV = 1.0 / (double)a.desc[r].V;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a.mean_out[r * 18 + k] = v[k] * iV;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+
+template <typename T> constexpr int tileB() { return 128 / (int)sizeof(typename cplx<T>::type); }
+
+struct Timed {
+  const LaunchCfg &L;
+  int kid;
+  Timed(const LaunchCfg &l, int k) : L(l), kid(k) {
+    if (L.timer) L.timer->begin(kid);
+  }
+  ~Timed() {
+    if (L.timer) L.timer->end(kid);
+  }
+};
+
+template <typename T>
+static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip,
+                                        Part part) {
+  using C = typename cplx<T>::type;
+  constexpr int B = tileB<T>();
+  const dim3 blk(kThreads);
+  const size_t lds_y = 2 * L.n2max * B * sizeof(C), lds_z = 2 * L.n3max * B * sizeof(C);
+  switch (part) {
+    case Part::Local: {
+      Timed tm(L, K_LOCAL);
+      hipLaunchKernelGGL((k_local_fwdx<T, true>), dim3(L.nblk_x), blk, L.lds_x_fwd, L.stream, a, ip);
+      break;
+    }
+    case Part::FormH: {
+      Timed tm(L, K_LOCAL);
+      hipLaunchKernelGGL((k_local_fwdx<T, false>), dim3(L.nblk_x), blk, L.lds_x_fwd, L.stream, a, ip);
+      break;
+    }
+    case Part::ProjectRest: {
+      {
+        Timed tm(L, K_FFT_Y_FWD);
+        hipLaunchKernelGGL((k_fft_y<T, B, false>), dim3(L.nblk_y, 9), blk, lds_y, L.stream, a);
+      }
+      {
+        Timed tm(L, K_GREEN_Z);
+        hipLaunchKernelGGL((k_green_z<T, B>), dim3(L.nblk_z), blk, lds_z, L.stream, a);
+      }
+      {
+        Timed tm(L, K_FFT_Y_INV);
+        hipLaunchKernelGGL((k_fft_y<T, B, true>), dim3(L.nblk_y, 3), blk, lds_y, L.stream, a);
+      }
+      {
+        Timed tm(L, K_INV_X);
+        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_x), blk, L.lds_x_inv, L.stream, a);
+      }
+      break;
+    }
+    case Part::Update: {
+      {
+        Timed tm(L, K_UPDATE);
+        hipLaunchKernelGGL((k_update<T>), dim3(L.nblk_u), blk, 0, L.stream, a);
+      }
+      {
+        Timed tm(L, K_FINALIZE);
+        hipLaunchKernelGGL(k_finalize, dim3(a.n_rve), blk, 0, L.stream, a, ip);
+      }
+      break;
+    }
+    case Part::MeanStress: {
+      Timed tm(L, K_MEAN);
+      hipLaunchKernelGGL((k_mean_stress<T>), dim3(L.nblk_u), blk, 0, L.stream, a);
+      hipLaunchKernelGGL(k_mean_final, dim3(a.n_rve), blk, 0, L.stream, a);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, Part part,
+                       bool fp64) {
+  return fp64 ? launch_iteration_part<double>(L, a, ip, part)
+              : launch_iteration_part<float>(L, a, ip, part);
+}
+
+int tile_b(bool fp64) { return fp64 ? tileB<double>() : tileB<float>(); }
+
+}  // namespace admm

@@ -1,0 +1,57 @@
+// launch.hpp -- interface between the host API (admm_api.cpp) and the kernel
+// launchers (kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace admm {
+
+// device pointers handed to every kernel
+struct KernelArgs {
+  const RveDesc *desc;
+  RveState *state;
+  const int *blk_x;  // prefix tables: first logical workgroup of each cell
+  const int *blk_y;
+  const int *blk_z;
+  const int *blk_u;
+  const Material *mats;
+  const void *tw;       // twiddle pool (float2 or double2)
+  double2 *partials;    // per update workgroup: (sum e^2, sum dd^2)
+  double *partials18;   // per workgroup: sums of P and Lambda
+  double *mean_out;     // per cell: <P>, <Lambda>
+  double *hist;         // per cell, per iteration: r_p, r_d, rho
+  int n_rve;
+  int n_mat;
+};
+
+// kernel ids of the profiling interface (same order as in include/admm.h)
+enum KernelId {
+  K_LOCAL = 0, K_FFT_Y_FWD, K_GREEN_Z, K_FFT_Y_INV, K_INV_X, K_UPDATE, K_FINALIZE, K_MEAN, K_COUNT
+};
+
+// brackets kernel launches with events on the launch stream when profiling
+struct KernelTimer {
+  virtual void begin(int kid) = 0;
+  virtual void end(int kid) = 0;
+  virtual ~KernelTimer() {}
+};
+
+// grid sizes and LDS bytes of one context
+struct LaunchCfg {
+  KernelTimer *timer;  // null unless profiling
+  hipStream_t stream;
+  int nblk_x, nblk_y, nblk_z, nblk_u;
+  int n2max, n3max;
+  size_t lds_x_fwd, lds_x_inv;
+};
+
+enum class Part { Local, FormH, ProjectRest, Update, MeanStress };
+
+// Enqueues one part of the iteration on L.stream.
+hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, Part part,
+                       bool fp64);
+
+// columns per tile of the FFT passes along x2 and x3 (128 bytes of complex)
+int tile_b(bool fp64);
+
+}  // namespace admm

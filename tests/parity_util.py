@@ -1,0 +1,55 @@
+"""Shared helpers of the GPU parity tests: seeded inputs and oracle runs.
+
+Inputs come from paper_2010_06697_amd.microstructure (geometry only) and
+numpy generators seeded here; expected values come only from the oracle.
+"""
+import numpy as np
+
+import oracle as O
+from paper_2010_06697_amd import admm
+
+
+def omats(mats):
+    return [O.material(m["model"], mu=m["mu"], lam=m["lam"], a=m["a"], kappa=m["kappa"])
+            for m in mats]
+
+
+def random_state(shape, seed, amp_u=0.05, amp_E=0.02, amp_L=0.5):
+    """A smooth-ish random state: u (3,...), F (9,...), Lambda (9,...)."""
+    rng = np.random.default_rng(seed)
+    n3, n2, n1 = shape
+    k3, k2, k1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    u = np.zeros((3,) + shape)
+    for i in range(3):
+        for _ in range(4):
+            m = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            u[i] += amp_u * rng.standard_normal() * np.sin(
+                2 * np.pi * (m[0] * k1 / n1 + m[1] * k2 / n2 + m[2] * k3 / n3) + ph)
+    F = amp_E * rng.standard_normal((9,) + shape)
+    F[0] += 1.0
+    F[4] += 1.0
+    F[8] += 1.0
+    L = amp_L * rng.standard_normal((9,) + shape)
+    return u, F, L
+
+
+def rel(a, b):
+    d = np.max(np.abs(np.asarray(a) - np.asarray(b)))
+    s = np.max(np.abs(np.asarray(b)))
+    return d / s if s > 0 else d
+
+
+def oracle_iterations(phase, mats, Fbar, n_iter, rho, mu_ref, adapt=False, state=None,
+                      rho_min=1.0, rho_max=50.0):
+    u, F, L = state if state is not None else O.initial_state(phase.shape)
+    u, F, L = u.copy(), F.copy(), L.copy()
+    p = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=mu_ref, adapt_rho=adapt,
+                 rho_min=rho_min, rho_max=rho_max)
+    r = O.admm_run(phase, omats(mats), np.asarray(Fbar).ravel(), p, u, F, L, rho)
+    return u, F, L, r
+
+
+def gpu_solver(phases, mats, Fbars, precision="fp64", **params):
+    p = admm.default_params(**params)
+    return admm.Solver(phases, mats, Fbars, p, precision=precision)

@@ -1,0 +1,128 @@
+"""Parity at the full benchmark size (256^3 fibre composite, the launch
+configuration bench.py times), on sampled voxels the oracle computes one by one
+and on properties that hold at any size:
+
+  * Step 1: F at sampled voxels equals the oracle's local solve from the same
+    inputs (grad u, Lambda, rho, warm start read back from the GPU);
+  * Step 2: the normal equations D_h^T (D_h u - H) = 0 at sampled voxels and a
+    zero-mean fluctuation;
+  * Step 3: Lambda_new = Lambda + rho (Fbar + D_h u - F) at sampled voxels;
+  * Step 4: r_p, r_d recomputed from the full fields in float64;
+  * <P> equals the oracle's average of P(F) over the GPU's F.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_06697_amd import microstructure as M
+from parity_util import gpu_solver, omats
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dh_at(u, pts):
+    """central differences of u (3, n3, n2, n1) at points (k3, k2, k1) arrays -> (9, npts)"""
+    _, n3, n2, n1 = u.shape
+    k3, k2, k1 = pts
+    out = np.empty((9, k1.size))
+    for j, (d3, d2, d1) in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+        p = ((k3 + d3) % n3, (k2 + d2) % n2, (k1 + d1) % n1)
+        m = ((k3 - d3) % n3, (k2 - d2) % n2, (k1 - d1) % n1)
+        for i in range(3):
+            out[3 * i + j] = 0.5 * (u[i][p] - u[i][m])
+    return out
+
+
+def at(f, pts):
+    return f[(slice(None),) + pts]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fibres256_one_iteration_sampled(precision):
+    case = M.fibres256_case()
+    phase = case["phase"]
+    Fbar = case["loads"][0]
+    rho = case["rho0"]
+    mu_ref = case["mu_ref"]
+    say("fibres256", precision, "phase fraction", float((phase == 0).mean()))
+    s = gpu_solver([phase], case["materials"], [Fbar], precision, rho0=rho, mu_ref=mu_ref,
+                   newton_step_tol=1e-7 if precision == "fp32" else 1e-10)
+    s.step(1)
+    st1 = s.state(0)
+    say("  step 1 done")
+    rng = np.random.default_rng(0)
+    n = phase.shape[0]
+    ns = 400
+    pts = tuple(rng.integers(0, n, ns) for _ in range(3))
+    pts = tuple(np.concatenate([p, [0, n - 1, 0, n - 1]]) for p in pts)
+
+    # Step 1 at sampled voxels
+    s.local_step()
+    F2 = s.state(0)["F"]
+    _, _, nfail = s.info(0)
+    assert nfail == 0
+    A = Fbar.ravel()[:, None] + dh_at(st1["u"], pts) + at(st1["Lambda"], pts) / rho
+    F1s = at(st1["F"], pts)
+    om = omats(case["materials"])
+    ph = phase[pts]
+    err = 0.0
+    for k in range(ph.size):
+        Fx, _, _, rc = O.prox(om[ph[k]], rho, A[:, k], F1s[:, k])
+        assert rc == O.OK
+        err = max(err, np.max(np.abs(Fx - at(F2, pts)[:, k])))
+    say("  local step: max |F - F_oracle| at samples", err)
+    assert err <= (1e-6 if precision == "fp32" else 1e-12)
+
+    # Step 2: normal equations at sampled voxels
+    s.project_step()
+    u2 = s.state(0)["u_prev"]
+    H = F2 - st1["Lambda"] / rho
+    res = np.zeros((3, ph.size))
+    for j, (d3, d2, d1) in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+        pp = ((pts[0] + d3) % n, (pts[1] + d2) % n, (pts[2] + d1) % n)
+        pm = ((pts[0] - d3) % n, (pts[1] - d2) % n, (pts[2] - d1) % n)
+        Rp = dh_at(u2, pp) - at(H, pp)
+        Rm = dh_at(u2, pm) - at(H, pm)
+        for i in range(3):
+            res[i] -= 0.5 * (Rp[3 * i + j] - Rm[3 * i + j])
+    hs = np.max(np.abs(H - H.mean(axis=(1, 2, 3), keepdims=True)))
+    say("  projection: max |D^T(Du - H)| / |H~| =", np.max(np.abs(res)) / hs)
+    assert np.max(np.abs(res)) <= (1e-5 if precision == "fp32" else 1e-12) * hs
+    assert np.max(np.abs(u2.mean(axis=(1, 2, 3)))) <= (1e-6 if precision == "fp32" else 1e-13)
+
+    # Step 3 and 4
+    s.update_step()
+    st3 = s.state(0)
+    hp, hd, hr = s.history(0)
+    P, _ = s.homogenized_stress(0)
+    s.close()
+    Lref = at(st1["Lambda"], pts) + rho * (Fbar.ravel()[:, None] + dh_at(u2, pts) - at(F2, pts))
+    lerr = np.max(np.abs(at(st3["Lambda"], pts) - Lref)) / np.max(np.abs(Lref))
+    say("  update: rel err at samples", lerr)
+    assert lerr <= (1e-6 if precision == "fp32" else 1e-13)
+    G2 = np.empty_like(F2)
+    G1 = np.empty_like(F2)
+    for i in range(3):
+        for j, ax in enumerate((3, 2, 1)):
+            G2[3 * i + j] = 0.5 * (np.roll(u2[i], -1, axis=ax - 1) - np.roll(u2[i], 1, axis=ax - 1))
+            G1[3 * i + j] = 0.5 * (np.roll(st1["u"][i], -1, axis=ax - 1)
+                                   - np.roll(st1["u"][i], 1, axis=ax - 1))
+    e = G2 + Fbar.ravel()[:, None, None, None] - F2
+    rp = np.sqrt(np.mean(np.sum(e * e, axis=0)))
+    rd = rho / mu_ref * np.sqrt(np.mean(np.sum((G2 - G1) ** 2, axis=0)))
+    say("  r_p", hp[-1], rp, " r_d", hd[-1], rd)
+    assert abs(hp[-1] - rp) <= 1e-9 * rp and abs(hd[-1] - rd) <= 1e-9 * rd
+    Po = O.mean_stress(phase, om, F2)
+    say("  <P> rel err vs oracle average", np.max(np.abs(P - Po)) / np.max(np.abs(Po)))
+    assert np.max(np.abs(P - Po)) <= 1e-10 * np.max(np.abs(Po))
