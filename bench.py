@@ -35,23 +35,28 @@ def log(*a):
 
 def kernel_bytes_per_voxel(s, c):
     """Algorithmic HBM bytes per voxel of each kernel (every operand read or
-    written once; s = scalar bytes, c = (n1/2+1)/n1 half-spectrum fraction)."""
+    written once; s = scalar bytes, c = (n1/2+1)/n1 half-spectrum fraction,
+    a complex half-spectrum component costs 2 c s per voxel)."""
     return {
-        "local_fwdx": (30 + 18 * c) * s + 1,
-        "fft_y_fwd": 36 * c * s,
-        "green_z": 24 * c * s,
+        "local": 30 * s + 1,             # u 3, F 9, Lambda 9, phase in; F 9 out
+        "div_fwdx": (18 + 6 * c) * s,    # F 9, Lambda 9 in; 3 half spectra out
+        "fft_y_fwd": 12 * c * s,         # 3 components in and out
+        "poisson_z": 12 * c * s,
         "fft_y_inv": 12 * c * s,
-        "inv_x": (6 * c + 3) * s,
-        "update": 33 * s,
+        "inv_x": (6 * c + 3) * s,        # 3 half spectra in; u 3 out
+        "update": 33 * s,                # u_{i+1} 3, u_i 3, F 9, Lambda 9 in; Lambda 9 out
         "finalize": 0.0,
         "mean_stress": 18 * s + 1,
     }
 
 
-def iteration_bytes_alg(s, c):
-    """Minimum bytes per voxel-iteration of the method (state once in and out,
-    one round trip of the forward and inverse spectra)."""
-    return s * (45 + 48 * c) + 1
+def iteration_bytes_alg(s, c, forward_components=3):
+    """Minimum bytes per voxel-iteration of the method: the state once in and
+    out (u_{i+1}, u_i, F, Lambda in; F, Lambda, u out: 45 scalars) plus one HBM
+    round trip of the forward and of the inverse spectrum. With the right-hand
+    side of Step 2 formed as a divergence in real space the forward spectrum
+    has 3 components; transforming F - Lambda/rho itself needs 9."""
+    return s * (45 + 4 * c * (forward_components + 3)) + 1
 
 
 def run_single(case, precision, steps, warmup, profile=True):
@@ -60,11 +65,10 @@ def run_single(case, precision, steps, warmup, profile=True):
 
     n3, n2, n1 = case["phase"].shape
     V = n1 * n2 * n3
-    p = admm.default_params(rho0=case["rho0"], rho_min=case["rho_min"], rho_max=case["rho_max"],
-                            adapt_rho=1, mu_ref=case["mu_ref"],
+    p = admm.default_params(precision, rho0=case["rho0"], rho_min=case["rho_min"],
+                            rho_max=case["rho_max"], adapt_rho=1, mu_ref=case["mu_ref"],
                             tol_p=case["tol_fp32" if precision == "fp32" else "tol_fp64"],
-                            tol_d=case["tol_fp32" if precision == "fp32" else "tol_fp64"],
-                            newton_step_tol=1e-7 if precision == "fp32" else 1e-10)
+                            tol_d=case["tol_fp32" if precision == "fp32" else "tol_fp64"])
     s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
                     precision=precision)
     log(f"[bench] {precision}: warmup {warmup} iterations")
@@ -80,7 +84,8 @@ def run_single(case, precision, steps, warmup, profile=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = s.profile_read() if profile else {}
-    it, status, nfail = s.info(0)
+    it, status, nfail, newton_its = s.info(0)
+    newton_per_voxel_it = newton_its / float(V * (warmup + steps))
     s.profile(False)
     s.close()
     del s
@@ -91,6 +96,7 @@ def run_single(case, precision, steps, warmup, profile=True):
         "ms_per_step": 1e3 * dt / steps,
         "r_p": float(rp[0]), "r_d": float(rd[0]), "rho": float(rho[0]),
         "newton_fail": int(nfail),
+        "newton_iters_per_voxel_iteration": newton_per_voxel_it,
         "P_mean": [float(x) for x in P],
         "kernels_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()},
         "kernels_launches": {k: v[1] for k, v in prof.items()},
@@ -106,9 +112,8 @@ def run_batch(count, steps_warm=2):
     log(f"[bench] batch: generating {count} cells")
     cells = M.rve_batch(count)
     mats = M.rve_batch_materials()
-    p = admm.default_params(rho0=10.0, rho_min=1.0, rho_max=50.0, adapt_rho=1, mu_ref=5.0,
-                            tol_p=1e-6, tol_d=1e-6, max_iter=2000, check_every=20,
-                            newton_step_tol=1e-7)
+    p = admm.default_params("fp32", rho0=10.0, rho_min=1.0, rho_max=50.0, adapt_rho=1,
+                            mu_ref=5.0, tol_p=1e-6, tol_d=1e-6, max_iter=2000, check_every=20)
     s = admm.Solver([c["phase"] for c in cells], mats, [c["Fbar"] for c in cells], p,
                     precision="fp32")
     s.step(steps_warm)  # loads the kernels; the state is reset below
@@ -240,10 +245,13 @@ def main():
     roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": bytes_launch, "avg_ms": avg_ms}
-    b_it = iteration_bytes_alg(4, c)
+    b_it = iteration_bytes_alg(4, c, 3)
+    b_it9 = iteration_bytes_alg(4, c, 9)
     it_roof = {"bytes_per_voxel_iteration": b_it,
                "achieved_GBs": b_it * f32["value"] / 1e9,
-               "frac": b_it * f32["value"] / (HBM_PEAK_GBS * 1e9)}
+               "frac": b_it * f32["value"] / (HBM_PEAK_GBS * 1e9),
+               "bytes_per_voxel_iteration_9_component_form": b_it9,
+               "frac_9_component_form": b_it9 * f32["value"] / (HBM_PEAK_GBS * 1e9)}
     per_kernel = {k: {"avg_ms": f32["kernels_ms"][k],
                       "GBs": (kb[k] * V / (f32["kernels_ms"][k] * 1e-3) / 1e9
                               if f32["kernels_ms"][k] > 0 and kb[k] > 0 else None)}

@@ -98,8 +98,10 @@ typedef struct {
   double tau;           /* adaptive ratio threshold tau (10) */
   double tol_p, tol_d;  /* primal / dual tolerances */
   double mu_ref;        /* representative modulus in r_d */
-  double newton_gtol;   /* local Newton: gradient test, relative (1e-15) */
-  double newton_step_tol; /* local Newton: step test, relative (1e-10) */
+  double newton_gtol;   /* local Newton: stop when |grad| <= gtol * (mu + lambda
+                           + rho)(1 + |F| + |A|) (1e-14 FP64, 1e-10 FP32) */
+  double newton_step_tol; /* local Newton: stop after a full Newton step
+                           |dF| <= step_tol * max(1, |F|) (1e-10 FP64, 2e-6 FP32) */
   int32_t adapt_rho;    /* 1: adaptive penalty after each test */
   int32_t max_iter;     /* iteration cap of admm_solve */
   int32_t check_every;  /* admm_solve: iterations between host checks (10) */
@@ -113,8 +115,9 @@ typedef struct admm_ctx admm_ctx;
 int admm_check_grid(int32_t n1, int32_t n2, int32_t n3);
 
 /* Device workspace the library needs for these cells and precision (bytes):
- * the half-spectrum buffers of Step 2 (9 components per cell) and the
- * reduction partials. Host only. Returns 0 on invalid input. */
+ * the half-spectrum buffers of Step 2, three components of
+ * n3 * n2 * (n1/2 + 1) complex values per cell. Host only. Returns 0 on
+ * invalid input. */
 size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precision);
 
 /* Creates a context for n_rve cells sharing one material table.
@@ -155,9 +158,10 @@ int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out);
 
 /* The three parts of one iteration, for testing each on its own:
  *   admm_local_step    Step 1 on every cell (F from u, Lambda, rho);
- *   admm_project_step  Step 2 on every cell (u from F - Lambda/rho);
+ *   admm_project_step  Step 2 on every cell (the new fluctuation, from
+ *                      F - Lambda/rho, is written to u_prev; u keeps u_i);
  *   admm_update_step   Step 3 and Step 4 (Lambda, r_p, r_d, the penalty
- *                      rule) against the u held before admm_project_step.
+ *                      rule) from u_i and u_{i+1}; u_{i+1} then is in u.
  * admm_step(ctx, 1, ...) equals the three in this order. */
 int admm_local_step(admm_ctx *ctx);
 int admm_project_step(admm_ctx *ctx);
@@ -176,21 +180,25 @@ int admm_homogenized_stress(admm_ctx *ctx, int32_t rve, double P_out[9],
 int admm_history(admm_ctx *ctx, int32_t rve, int32_t max_n, double *r_p,
                  double *r_d, double *rho, int32_t *n_out);
 
-/* Iteration count, status, Newton-failure count of one cell. */
+/* Iteration count of the current load step, status (as admm_solve reports
+ * it), the number of local solves that hit the Newton cap, and the Newton
+ * iterations summed over voxels since the load step began (for cost
+ * accounting) of one cell. Outputs may be NULL. */
 int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
-                   int32_t *newton_fail);
+                   int32_t *newton_fail, int64_t *newton_iters);
 
 /* Kernels timed by the profiling interface, in launch order. */
 typedef enum {
-  ADMM_KERNEL_LOCAL = 0,    /* Step 1 + H = F - Lambda/rho + forward FFT along x1 */
-  ADMM_KERNEL_FFT_Y_FWD = 1, /* forward FFT along x2, 9 components */
-  ADMM_KERNEL_GREEN_Z = 2,  /* FFT along x3, Fourier-space solve, inverse along x3 */
-  ADMM_KERNEL_FFT_Y_INV = 3, /* inverse FFT along x2, 3 components */
-  ADMM_KERNEL_INV_X = 4,    /* inverse FFT along x1 into u */
-  ADMM_KERNEL_UPDATE = 5,   /* Step 3 + residual partial sums */
-  ADMM_KERNEL_FINALIZE = 6, /* Step 4 reductions, test, penalty rule */
-  ADMM_KERNEL_MEAN = 7,     /* homogenised stress reductions */
-  ADMM_KERNEL_COUNT = 8
+  ADMM_KERNEL_LOCAL = 0,     /* Step 1: local Newton solve per voxel */
+  ADMM_KERNEL_DIV_FWDX = 1,  /* b = D_h^T (F - Lambda/rho), forward FFT along x1 */
+  ADMM_KERNEL_FFT_Y_FWD = 2, /* forward FFT along x2 */
+  ADMM_KERNEL_POISSON_Z = 3, /* FFT along x3, Fourier-space solve, inverse along x3 */
+  ADMM_KERNEL_FFT_Y_INV = 4, /* inverse FFT along x2 */
+  ADMM_KERNEL_INV_X = 5,     /* inverse FFT along x1 into u */
+  ADMM_KERNEL_UPDATE = 6,    /* Step 3 + residual partial sums */
+  ADMM_KERNEL_FINALIZE = 7,  /* Step 4 reductions, test, penalty rule */
+  ADMM_KERNEL_MEAN = 8,      /* homogenised stress reductions */
+  ADMM_KERNEL_COUNT = 9
 } admm_kernel;
 
 /* Profiling (for measurement, not part of the method): when on, every kernel

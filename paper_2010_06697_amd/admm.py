@@ -31,8 +31,8 @@ ENTRY_POINTS = (
     "admm_profile_read", "admm_strerror", "admm_destroy",
 )
 
-KERNELS = ("local_fwdx", "fft_y_fwd", "green_z", "fft_y_inv", "inv_x", "update", "finalize",
-           "mean_stress")
+KERNELS = ("local", "div_fwdx", "fft_y_fwd", "poisson_z", "fft_y_inv", "inv_x", "update",
+           "finalize", "mean_stress")
 
 
 class Material(ctypes.Structure):
@@ -87,7 +87,7 @@ def lib():
         L.admm_update_step.argtypes = [vp]
         L.admm_homogenized_stress.argtypes = [vp, i32, dp, dp]
         L.admm_history.argtypes = [vp, i32, i32, dp, dp, dp, ip]
-        L.admm_cell_info.argtypes = [vp, i32, ip, ip, ip]
+        L.admm_cell_info.argtypes = [vp, i32, ip, ip, ip, ctypes.POINTER(ctypes.c_int64)]
         L.admm_profile_enable.argtypes = [vp, i32]
         L.admm_profile_read.argtypes = [vp, i32, dp, ip]
         L.admm_strerror.argtypes = [ctypes.c_int]
@@ -197,10 +197,12 @@ def admm_history(ctx, rve: int, max_n: int):
 
 
 def admm_cell_info(ctx, rve: int):
+    """(iterations, status, Newton-cap hits, Newton iterations summed over voxels)"""
     it, st, nf = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
-    _check(lib().admm_cell_info(ctx, rve, ctypes.byref(it), ctypes.byref(st), ctypes.byref(nf)),
-           "admm_cell_info")
-    return it.value, st.value, nf.value
+    ni = ctypes.c_int64(0)
+    _check(lib().admm_cell_info(ctx, rve, ctypes.byref(it), ctypes.byref(st), ctypes.byref(nf),
+                                ctypes.byref(ni)), "admm_cell_info")
+    return it.value, st.value, nf.value, ni.value
 
 
 def admm_profile_enable(ctx, on: bool) -> int:
@@ -225,11 +227,14 @@ def admm_destroy(ctx) -> None:
 
 # ---- convenience: device buffers of a batch of cells -----------------------
 
-def default_params(**kw) -> Params:
+def default_params(precision: str = "fp64", **kw) -> Params:
     p = Params()
     p.rho0, p.rho_min, p.rho_max, p.kappa_rho, p.tau = 10.0, 1.0, 50.0, 1.3, 10.0
     p.tol_p, p.tol_d, p.mu_ref = 1e-8, 1e-8, 1.0
-    p.newton_gtol, p.newton_step_tol = 1e-15, 1e-10
+    if precision == "fp64":
+        p.newton_gtol, p.newton_step_tol = 1e-14, 1e-10
+    else:
+        p.newton_gtol, p.newton_step_tol = 1e-10, 2e-6
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
     for k, v in kw.items():
         if not hasattr(p, k):

@@ -89,9 +89,11 @@ void twiddles(int n, std::vector<double> &re, std::vector<double> &im) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// three half-spectrum components (the divergence of F - Lambda/rho, then the
+// displacement fluctuation) per cell
 size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
   const size_t S = (size_t)n3 * n2 * (n1 / 2 + 1);
-  return align_up(9 * S * (fp64 ? 16 : 8), 256);
+  return align_up(3 * S * (fp64 ? 16 : 8), 256);
 }
 
 int rows_per_block(int n1) { return std::max(1, kThreads / n1); }
@@ -266,7 +268,7 @@ int launch(admm_ctx *c, Part part, const IterParams &ip) {
 
 int one_iteration(admm_ctx *c, const IterParams &ip) {
   int rc = launch(c, Part::Local, ip);
-  if (rc == ADMM_OK) rc = launch(c, Part::ProjectRest, ip);
+  if (rc == ADMM_OK) rc = launch(c, Part::Project, ip);
   if (rc == ADMM_OK) rc = launch(c, Part::Update, ip);
   return rc;
 }
@@ -426,7 +428,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1);
   bx[0] = by[0] = bz[0] = bu[0] = 0;
   size_t spec_off = 0;
-  int n2max = 0, n3max = 0, lds_fwd = 0, lds_inv = 0;
+  int n2max = 0, n3max = 0, lds_x = 0;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
     RveDesc &D = c->desc_h[r];
@@ -457,11 +459,11 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
-    bu[r + 1] = bu[r] + (int)((D.V + kThreads - 1) / kThreads);
+    const int rows_u = D.rows * kVoxelsPerThread;
+    bu[r + 1] = bu[r] + (nrows + rows_u - 1) / rows_u;
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
-    lds_fwd = std::max(lds_fwd, 2 * ((9 * D.rows + 1) / 2) * D.n1);
-    lds_inv = std::max(lds_inv, 2 * ((3 * D.rows + 1) / 2) * D.n1);
+    lds_x = std::max(lds_x, 2 * ((3 * D.rows + 1) / 2) * D.n1);
   }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
@@ -472,8 +474,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   c->L.nblk_u = bu[n_rve];
   c->L.n2max = n2max;
   c->L.n3max = n3max;
-  c->L.lds_x_fwd = (size_t)lds_fwd * csz;
-  c->L.lds_x_inv = (size_t)lds_inv * csz;
+  c->L.lds_x = (size_t)lds_x * csz;
 
   INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
   INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
@@ -548,6 +549,7 @@ int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
   s.active = 1;
   s.status = ST_RUNNING;
   s.newton_fail = 0;
+  s.newton_iters = 0;
   s.domain_err = 0;
   int rc = upload_states(ctx);
   if (rc != ADMM_OK) return rc;
@@ -643,8 +645,7 @@ int admm_project_step(admm_ctx *ctx) {
   if (!ctx) return ADMM_EINVAL;
   int rc = activate_all(ctx);
   const IterParams ip = iter_params(ctx, 0);
-  if (rc == ADMM_OK) rc = launch(ctx, Part::FormH, ip);
-  if (rc == ADMM_OK) rc = launch(ctx, Part::ProjectRest, ip);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::Project, ip);
   if (rc == ADMM_OK) rc = download_states(ctx);
   return rc;
 }
@@ -693,7 +694,7 @@ int admm_history(admm_ctx *ctx, int32_t rve, int32_t max_n, double *r_p, double 
 }
 
 int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
-                   int32_t *newton_fail) {
+                   int32_t *newton_fail, int64_t *newton_iters) {
   if (!ctx || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
   const RveState &s = ctx->state_h[rve];
   if (iters) *iters = s.iter;
@@ -703,6 +704,7 @@ int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
               : s.status == ST_CAP     ? ADMM_NOT_CONVERGED
                                        : ADMM_OK;
   if (newton_fail) *newton_fail = s.newton_fail;
+  if (newton_iters) *newton_iters = (int64_t)s.newton_iters;
   return ADMM_OK;
 }
 

@@ -49,7 +49,10 @@ struct RveState {
   int newton_fail;   // local solves that hit the Newton cap
   int domain_err;    // set when det F <= 0 or NaN met
   int pad0, pad1;
+  unsigned long long newton_iters;  // Newton iterations summed over voxels and iterations
 };
+
+constexpr int kVoxelsPerThread = 4;  // grid-stride depth of the per-voxel reduction kernels
 
 struct Material {
   int model;

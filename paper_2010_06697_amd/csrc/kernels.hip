@@ -1,16 +1,21 @@
 // kernels.hip -- the HIP kernels of one ADMM iteration (gfx950) and their
 // host launchers.
 //
+// Step 2 solves D_h^T D_h u = D_h^T H for H = F - Lambda/rho, D_h the central
+// difference. In Fourier space this is |K|^2 u_hat = b_hat with b = D_h^T H,
+// b_i = -sum_j (H_ij(x+e_j) - H_ij(x-e_j))/2, whose transform is
+// -i sum_j K_j H_hat_ij, K_j = sin(2 pi m_j/n_j): the Fourier-space solve of
+// Sec. 2.3 with central-difference symbols. Forming b in real space first
+// leaves three components to transform instead of nine.
+//
 // Per iteration, over every active cell of the batch, in this order:
-//   k_local_fwdx   Step 1 (local Newton per voxel) fused with forming
-//                  H = F - Lambda/rho and the forward real-to-complex FFT
-//                  along x1 (two real rows per complex transform)
-//   k_fft_y        forward FFT along x2 of the 9 half-spectrum components
-//   k_green_z      forward FFT along x3, the Fourier-space solve of Step 2
-//                  (u_i = -i sum_j K_j H_ij / |K|^2, K_j = sin(2 pi m_j/n_j),
-//                  zero on the eight null modes, scaled by 1/V) and the
-//                  inverse FFT along x3 of the 3 displacement components
-//   k_fft_y        inverse FFT along x2 of the 3 components
+//   k_local        Step 1: the local Newton solve per voxel (F)
+//   k_div_fwdx     b = D_h^T (F - Lambda/rho) and its forward real-to-complex
+//                  FFT along x1 (two real rows per complex transform)
+//   k_fft_y        forward FFT along x2 of the three components
+//   k_poisson_z    forward FFT along x3, u_hat = b_hat / (|K|^2 V) (zero on
+//                  the eight modes where every K_j vanishes), inverse along x3
+//   k_fft_y        inverse FFT along x2
 //   k_inv_x        inverse complex-to-real FFT along x1 into u_{i+1}
 //   k_update       Step 3 (Lambda += rho (grad u_{i+1} - F)) and the
 //                  per-workgroup partial sums of Step 4
@@ -29,24 +34,36 @@ namespace admm {
 // helpers
 // ----------------------------------------------------------------------------
 
-// periodic central difference (u(x+e_j) - u(x-e_j))/2 of the three
-// components of u at voxel (x1,x2,x3); out[3i+j]
-template <typename T>
-__device__ __forceinline__ void grad_u(const T *__restrict__ u, long long V, int n1, int n2, int n3,
-                                       int x1, int x2, int x3, double *out) {
+// neighbour offsets of voxel (x1,x2,x3) along +-e1, +-e2, +-e3 (periodic)
+struct Stencil {
+  int o[6];
+};
+
+__device__ __forceinline__ Stencil stencil(int n1, int n2, int n3, int x1, int x2, int x3) {
   const int x1p = x1 + 1 == n1 ? 0 : x1 + 1, x1m = x1 == 0 ? n1 - 1 : x1 - 1;
   const int x2p = x2 + 1 == n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
   const int x3p = x3 + 1 == n3 ? 0 : x3 + 1, x3m = x3 == 0 ? n3 - 1 : x3 - 1;
-  const long long row = ((long long)x3 * n2 + x2) * n1;
-  const long long o[6] = {row + x1p, row + x1m,
-                          ((long long)x3 * n2 + x2p) * n1 + x1, ((long long)x3 * n2 + x2m) * n1 + x1,
-                          ((long long)x3p * n2 + x2) * n1 + x1, ((long long)x3m * n2 + x2) * n1 + x1};
+  const int row = (x3 * n2 + x2) * n1;
+  Stencil s;
+  s.o[0] = row + x1p;
+  s.o[1] = row + x1m;
+  s.o[2] = (x3 * n2 + x2p) * n1 + x1;
+  s.o[3] = (x3 * n2 + x2m) * n1 + x1;
+  s.o[4] = (x3p * n2 + x2) * n1 + x1;
+  s.o[5] = (x3m * n2 + x2) * n1 + x1;
+  return s;
+}
+
+// central differences (u_i(x+e_j) - u_i(x-e_j))/2 of a 3-vector field; out[3i+j]
+template <typename T>
+__device__ __forceinline__ void grad_u(const T *__restrict__ u, int V, const Stencil &s,
+                                       double *out) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const T *ui = u + i * V;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      out[3 * i + j] = 0.5 * ((double)ui[o[2 * j]] - (double)ui[o[2 * j + 1]]);
+      out[3 * i + j] = 0.5 * ((double)ui[s.o[2 * j]] - (double)ui[s.o[2 * j + 1]]);
   }
 }
 
@@ -73,75 +90,129 @@ __device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwave
 }
 
 // ----------------------------------------------------------------------------
-// Step 1 + H + forward FFT along x1
+// Step 1: local problem per voxel
 // ----------------------------------------------------------------------------
 
-template <typename T, bool DO_LOCAL>
-__global__ __launch_bounds__(kThreads) void k_local_fwdx(KernelArgs a, IterParams ip) {
-  using C = typename cplx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+// Occupancy of the local kernel: the Newton state (about 200 live registers)
+// bounds it; a value of 2 or more trades spills for waves per SIMD.
+#ifndef ADMM_LOCAL_WAVES_PER_EU
+#define ADMM_LOCAL_WAVES_PER_EU 1
+#endif
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
+void k_local(KernelArgs a, IterParams ip) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_x, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
   const int b = blk - a.blk_x[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
   const int nrows = n2 * n3;
-  const int row0 = b * R;
-  const int ncl = (9 * R + 1) / 2;
-  const long long V = D.V, S = D.S;
-  C *za = reinterpret_cast<C *>(smem);
-  C *zb = za + ncl * n1;
+  const int V = (int)D.V;
   const int t = threadIdx.x;
-  const double rho = st->rho;
-  const double irho = 1.0 / rho;
-
-  for (int w = t; w < ncl * n1; w += blockDim.x) za[w] = C{(T)0, (T)0};
-  __syncthreads();
-
   const int row = t / n1, x1 = t - row * n1;
-  const int grow = row0 + row;
+  const int grow = b * R + row;
+  int n_fail = 0, n_its = 0;
   if (row < R && grow < nrows) {
+    const double rho = st->rho;
+    const double irho = 1.0 / rho;
     const int x2 = grow % n2, x3 = grow / n2;
-    const long long idx = (long long)grow * n1 + x1;
+    const int idx = grow * n1 + x1;
     const T *u = static_cast<const T *>(D.u[st->cur]);
     T *Eg = static_cast<T *>(D.E);
     const T *Lg = static_cast<const T *>(D.Lam);
-    double Du[9], E[9], Lm[9], A[9];
-    grad_u(u, V, n1, n2, n3, x1, x2, x3, Du);
+    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
+    T E[9], At[9];
+    double A[9];
+    grad_u(u, V, sn, A);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      E[c] = (double)Eg[c * V + idx];
-      Lm[c] = (double)Lg[c * V + idx];
-      A[c] = D.Ebar[c] + Du[c] + Lm[c] * irho;
+      E[c] = Eg[c * V + idx];
+      At[c] = (T)(A[c] + D.Ebar[c] + (double)Lg[c * V + idx] * irho);
     }
     const int ph = D.phase[idx];
-    if (ph >= a.n_mat) atomicOr(&st->domain_err, 2);  // invalid phase index
-    if (DO_LOCAL && ph < a.n_mat) {
+    if (ph < a.n_mat) {
       const Material m = a.mats[ph];
-      const int rc = nh_newton<T>(E, A, rho, m.mu, m.lam, ip.newton_max, ip.gtol, ip.step_tol);
-      if (rc == -1) atomicAdd(&st->newton_fail, 1);
+      const int rc = nh_newton<T, T>(E, At, (T)rho, (T)m.mu, (T)m.lam, ip.newton_max, ip.gtol,
+                                     ip.step_tol);
+      n_fail = rc == -1;
+      n_its = rc >= 0 ? rc : ip.newton_max;
       if (rc == -2) atomicOr(&st->domain_err, 1);
 #pragma unroll
-      for (int c = 0; c < 9; ++c) Eg[c * V + idx] = (T)E[c];
+      for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
+    } else {
+      atomicOr(&st->domain_err, 2);  // invalid phase index
     }
+  }
+  // one atomic per wave for the Newton statistics
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const int ell = c * R + row;
+  for (int off = 32; off > 0; off >>= 1) {
+    n_fail += __shfl_xor(n_fail, off, 64);
+    n_its += __shfl_xor(n_its, off, 64);
+  }
+  if ((t & 63) == 0) {
+    if (n_fail) atomicAdd(&st->newton_fail, n_fail);
+    if (n_its) atomicAdd(&st->newton_iters, (unsigned long long)n_its);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// b = D_h^T (F - Lambda/rho) and its forward FFT along x1
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
+  using C = typename cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  if (!st->active) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int nrows = n2 * n3;
+  const int row0 = b * R;
+  const int ncl = (3 * R + 1) / 2;
+  const int V = (int)D.V;
+  const long long S = D.S;
+  C *za = reinterpret_cast<C *>(smem);
+  C *zb = za + ncl * n1;
+  const int t = threadIdx.x, nthr = blockDim.x;
+
+  for (int w = t; w < ncl * n1; w += nthr) za[w] = C{(T)0, (T)0};
+  __syncthreads();
+  const int row = t / n1, x1 = t - row * n1;
+  const int grow = row0 + row;
+  if (row < R && grow < nrows) {
+    const double irho = 1.0 / st->rho;
+    const int x2 = grow % n2, x3 = grow / n2;
+    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
+    const T *Eg = static_cast<const T *>(D.E);
+    const T *Lg = static_cast<const T *>(D.Lam);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double bi = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int c = (3 * i + j) * V;
+        const double hp = (double)Eg[c + sn.o[2 * j]] - (double)Lg[c + sn.o[2 * j]] * irho;
+        const double hm =
+            (double)Eg[c + sn.o[2 * j + 1]] - (double)Lg[c + sn.o[2 * j + 1]] * irho;
+        bi -= 0.5 * (hp - hm);
+      }
+      const int ell = i * R + row;
       C *z = za + (ell >> 1) * n1 + x1;
-      // in the reduced mode E is rounded to storage precision first, so that
-      // the projected field is the one Step 3 sees
-      const T h = (T)((double)(T)E[c] - Lm[c] * irho);
-      if (ell & 1) z->y = h; else z->x = h;
+      if (ell & 1) z->y = (T)bi; else z->x = (T)bi;
     }
   }
   __syncthreads();
   const C *tw = static_cast<const C *>(a.tw);
-  C *res = fft_lines<false>(za, zb, D.p1, tw, ncl, n1, 1, false, t, (int)blockDim.x);
-
+  C *res = fft_lines<false>(za, zb, D.p1, tw, ncl, n1, 1, false, t, nthr);
   C *spec = static_cast<C *>(D.spec);
-  for (int w = t; w < ncl * m1; w += blockDim.x) {
+  for (int w = t; w < ncl * m1; w += nthr) {
     const int p = w / m1, m = w - p * m1;
     const C Zm = res[p * n1 + m];
     const C Zn = res[p * n1 + (m == 0 ? 0 : n1 - m)];
@@ -152,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_local_fwdx(KernelArgs a, IterParam
       const int c = la / R, rw = la - c * R;
       if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Av;
     }
-    if (lb < 9 * R) {
+    if (lb < 3 * R) {
       const int c = lb / R, rw = lb - c * R;
       if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Bv;
     }
@@ -160,12 +231,13 @@ __global__ __launch_bounds__(kThreads) void k_local_fwdx(KernelArgs a, IterParam
 }
 
 // ----------------------------------------------------------------------------
-// FFT along x2 of ncomp spectral components (blockIdx.y = component)
+// FFT along x2 of the three spectral components (blockIdx.y = component)
 // ----------------------------------------------------------------------------
 
 template <typename T, int B, bool INV>
 __global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
   using C = typename cplx<T>::type;
+  constexpr int PMAX = (kMaxN * B) / kThreads;
   extern __shared__ __align__(16) unsigned char smem[];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_y, a.n_rve, blk);
@@ -178,26 +250,44 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
   C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + (long long)x3 * n2 * m1;
   C *za = reinterpret_cast<C *>(smem);
   C *zb = za + n2 * B;
-  const int t = threadIdx.x;
-  for (int w = t; w < n2 * B; w += blockDim.x) {
+  const int t = threadIdx.x, nthr = blockDim.x;
+  const int npts = n2 * B;
+  // every load of the tile in flight before the first LDS store
+  C v[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
     const int x2 = w / B, bb = w - x2 * B;
-    za[w] = (m0 + bb < m1) ? base[(long long)x2 * m1 + m0 + bb] : C{(T)0, (T)0};
+    v[k] = (w < npts && m0 + bb < m1) ? base[x2 * m1 + m0 + bb] : C{(T)0, (T)0};
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    if (w < npts) za[w] = v[k];
   }
   __syncthreads();
   const C *tw = static_cast<const C *>(a.tw);
-  C *res = fft_lines<INV>(za, zb, D.p2, tw, B, 1, B, true, t, (int)blockDim.x);
-  for (int w = t; w < n2 * B; w += blockDim.x) {
+  C *res = fft_lines<INV>(za, zb, D.p2, tw, B, 1, B, true, t, nthr);
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    if (w < npts) v[k] = res[w];
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
     const int x2 = w / B, bb = w - x2 * B;
-    if (m0 + bb < m1) base[(long long)x2 * m1 + m0 + bb] = res[w];
+    if (w < npts && m0 + bb < m1) base[x2 * m1 + m0 + bb] = v[k];
   }
 }
 
 // ----------------------------------------------------------------------------
-// FFT along x3 + Fourier-space solve of Step 2 + inverse FFT along x3
+// FFT along x3, Poisson solve in Fourier space, inverse FFT along x3
+// (blockIdx.y = component)
 // ----------------------------------------------------------------------------
 
 template <typename T, int B>
-__global__ __launch_bounds__(kThreads) void k_green_z(KernelArgs a) {
+__global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
   using C = typename cplx<T>::type;
   constexpr int PMAX = (kMaxN * B) / kThreads;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -207,92 +297,68 @@ __global__ __launch_bounds__(kThreads) void k_green_z(KernelArgs a) {
   if (!a.state[r].active) return;
   const int b = blk - a.blk_z[r];
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, m1 = D.m1;
-  const long long plane = (long long)n2 * m1;  // stride between x3 planes
-  const int nq = n2 * m1;
+  const int plane = n2 * m1;  // stride between x3 planes
   const int q0 = b * B;
   const int npts = n3 * B;
-  C *spec = static_cast<C *>(D.spec);
+  C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + q0;
   const C *tw = static_cast<const C *>(a.tw);
   C *za = reinterpret_cast<C *>(smem);
   C *zb = za + n3 * B;
   const int t = threadIdx.x, nthr = blockDim.x;
-
-  C acc[3][PMAX];
+  C v[PMAX];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) acc[i][k] = C{(T)0, (T)0};
-
-  // the row index i of H_ij selects the accumulator: unrolled, so that the
-  // accumulators stay in registers
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-  for (int j = 0; j < 3; ++j) {
-    const int c = 3 * i + j;
-    const C *src = spec + c * D.S + q0;
-    for (int w = t; w < npts; w += nthr) {
-      const int x3 = w / B, bb = w - x3 * B;
-      za[w] = (q0 + bb < nq) ? src[x3 * plane + bb] : C{(T)0, (T)0};
-    }
-    __syncthreads();
-    C *res = fft_lines<false>(za, zb, D.p3, tw, B, 1, B, true, t, nthr);
-#pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      const int p = t + k * nthr;
-      if (p < npts) {
-        const int m3 = p / B, bb = p - m3 * B;
-        const int q = q0 + bb;
-        const int m2 = q / m1, mm1 = q - m2 * m1;
-        T K;
-        if (j == 0) K = -tw[D.p1.tw + mm1].y;
-        else if (j == 1) K = -tw[D.p2.tw + (m2 < n2 ? m2 : 0)].y;
-        else K = -tw[D.p3.tw + m3].y;
-        const C h = res[p];
-        acc[i][k].x += K * h.x;
-        acc[i][k].y += K * h.y;
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    const int x3 = w / B, bb = w - x3 * B;
+    v[k] = (w < npts && q0 + bb < plane) ? base[x3 * plane + bb] : C{(T)0, (T)0};
   }
-
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    if (w < npts) za[w] = v[k];
+  }
+  __syncthreads();
+  C *res = fft_lines<false>(za, zb, D.p3, tw, B, 1, B, true, t, nthr);
+  // u_hat = b_hat / (|K|^2 V); zero where every K_j vanishes
   const double iV = 1.0 / (double)D.V;
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) {
-    const int p = t + k * nthr;
-    if (p < npts) {
-      const int m3 = p / B, bb = p - m3 * B;
-      const int q = q0 + bb;
+    const int w = t + k * nthr;
+    if (w < npts) {
+      const int m3 = w / B, bb = w - m3 * B;
+      int q = q0 + bb;
+      if (q >= plane) q = 0;
       const int m2 = q / m1, mm1 = q - m2 * m1;
-      const double K1 = -(double)tw[D.p1.tw + mm1].y;
-      const double K2 = -(double)tw[D.p2.tw + (m2 < n2 ? m2 : 0)].y;
-      const double K3 = -(double)tw[D.p3.tw + m3].y;
+      const double K1 = (double)tw[D.p1.tw + mm1].y;
+      const double K2 = (double)tw[D.p2.tw + m2].y;
+      const double K3 = (double)tw[D.p3.tw + m3].y;
       const bool null = (mm1 == 0 || 2 * mm1 == n1) && (m2 == 0 || 2 * m2 == n2) &&
                         (m3 == 0 || 2 * m3 == n3);
-      const double k2 = K1 * K1 + K2 * K2 + K3 * K3;
-      const T s = null ? (T)0 : (T)(iV / k2);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {  // -i * acc * s
-        const C v = acc[i][k];
-        acc[i][k] = C{v.y * s, -v.x * s};
-      }
+      const T s = null ? (T)0 : (T)(iV / (K1 * K1 + K2 * K2 + K3 * K3));
+      const C h = res[w];
+      v[k] = C{h.x * s, h.y * s};
     }
   }
-
+  // res is one of the two buffers and every thread has read what it needs
+  // from it; the scaled values go to the other one
+  C *dst = (res == za) ? zb : za;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    if (w < npts) dst[w] = v[k];
+  }
+  __syncthreads();
+  res = fft_lines<true>(dst, res, D.p3, tw, B, 1, B, true, t, nthr);
 #pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-      const int p = t + k * nthr;
-      if (p < npts) za[p] = acc[i][k];
-    }
-    __syncthreads();
-    C *res = fft_lines<true>(za, zb, D.p3, tw, B, 1, B, true, t, nthr);
-    C *dst = spec + i * D.S + q0;
-    for (int w = t; w < npts; w += nthr) {
-      const int x3 = w / B, bb = w - x3 * B;
-      if (q0 + bb < nq) dst[x3 * plane + bb] = res[w];
-    }
-    __syncthreads();
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    if (w < npts) v[k] = res[w];
+  }
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    const int w = t + k * nthr;
+    const int x3 = w / B, bb = w - x3 * B;
+    if (w < npts && q0 + bb < plane) base[x3 * plane + bb] = v[k];
   }
 }
 
@@ -314,7 +380,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   const int nrows = n2 * n3;
   const int row0 = b * R;
   const int ncl = (3 * R + 1) / 2;
-  const long long V = D.V, S = D.S;
+  const int V = (int)D.V;
+  const long long S = D.S;
   const C *spec = static_cast<const C *>(D.spec);
   C *za = reinterpret_cast<C *>(smem);
   C *zb = za + ncl * n1;
@@ -356,13 +423,13 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
     const int grow = row0 + rw;
     if (grow < nrows) {
       const C v = res[(ell >> 1) * n1 + x1];
-      un[c * V + (long long)grow * n1 + x1] = (ell & 1) ? v.y : v.x;
+      un[c * V + grow * n1 + x1] = (ell & 1) ? v.y : v.x;
     }
   }
 }
 
 // ----------------------------------------------------------------------------
-// Step 3 + partial sums of Step 4
+// Step 3 + partial sums of Step 4 (kVoxelsPerThread groups of rows per block)
 // ----------------------------------------------------------------------------
 
 template <typename T>
@@ -374,22 +441,27 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   RveState *st = a.state + r;
   if (!st->active) return;
   const int b = blk - a.blk_u[r];
-  const long long V = D.V;
-  const long long idx = (long long)b * kThreads + threadIdx.x;
+  const int V = (int)D.V;
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
+  const int nrows = n2 * n3;
+  const double rho = st->rho;
+  const T *un = static_cast<const T *>(D.u[1 - st->cur]);
+  const T *uo = static_cast<const T *>(D.u[st->cur]);
+  const T *Eg = static_cast<const T *>(D.E);
+  T *Lg = static_cast<T *>(D.Lam);
+  const int t = threadIdx.x;
+  const int row = t / n1, x1 = t - row * n1;
   double v[2] = {0.0, 0.0};
-  if (idx < V) {
-    const int n1 = D.n1, n2 = D.n2, n3 = D.n3;
-    const int x1 = (int)(idx % n1);
-    const long long rest = idx / n1;
-    const int x2 = (int)(rest % n2), x3 = (int)(rest / n2);
-    const double rho = st->rho;
-    const T *un = static_cast<const T *>(D.u[1 - st->cur]);
-    const T *uo = static_cast<const T *>(D.u[st->cur]);
-    const T *Eg = static_cast<const T *>(D.E);
-    T *Lg = static_cast<T *>(D.Lam);
+#pragma unroll
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int grow = (b * kVoxelsPerThread + k) * R + row;
+    if (row >= R || grow >= nrows) continue;
+    const int x2 = grow % n2, x3 = grow / n2;
+    const int idx = grow * n1 + x1;
+    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     double Dn[9], Do[9];
-    grad_u(un, V, n1, n2, n3, x1, x2, x3, Dn);
-    grad_u(uo, V, n1, n2, n3, x1, x2, x3, Do);
+    grad_u(un, V, sn, Dn);
+    grad_u(uo, V, sn, Do);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const double e = D.Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
@@ -471,27 +543,32 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
   const int r = find_rve(a.blk_u, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   const int b = blk - a.blk_u[r];
-  const long long V = D.V;
-  const long long idx = (long long)b * kThreads + threadIdx.x;
+  const int V = (int)D.V;
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3;
+  const T *Eg = static_cast<const T *>(D.E);
+  const T *Lg = static_cast<const T *>(D.Lam);
+  const int t = threadIdx.x;
+  const int row = t / n1, x1 = t - row * n1;
   double v[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) v[k] = 0.0;
   int bad = 0;
-  if (idx < V) {
-    const T *Eg = static_cast<const T *>(D.E);
-    const T *Lg = static_cast<const T *>(D.Lam);
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int grow = (b * kVoxelsPerThread + k) * R + row;
+    if (row >= R || grow >= nrows) continue;
+    const int idx = grow * n1 + x1;
     double E[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       E[c] = (double)Eg[c * V + idx];
-      v[9 + c] = (double)Lg[c * V + idx];
+      v[9 + c] += (double)Lg[c * V + idx];
     }
     const int ph = D.phase[idx];
-    NHPoint s;
+    NHPoint<double> s;
     // with rho = 0 the gradient of the prox objective is the stress P
-    if (ph < a.n_mat && nh_point(E, E, 0.0, a.mats[ph].mu, a.mats[ph].lam, s)) {
+    if (ph < a.n_mat && nh_point<double>(E, E, 0.0, a.mats[ph].mu, a.mats[ph].lam, s)) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) v[c] = s.g[c];
+      for (int c = 0; c < 9; ++c) v[c] += s.g[c];
     } else {
       bad = 1;
     }
@@ -539,8 +616,8 @@ struct Timed {
 };
 
 template <typename T>
-static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip,
-                                        Part part) {
+static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
+                                        const IterParams &ip, Part part) {
   using C = typename cplx<T>::type;
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads);
@@ -548,22 +625,21 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
   switch (part) {
     case Part::Local: {
       Timed tm(L, K_LOCAL);
-      hipLaunchKernelGGL((k_local_fwdx<T, true>), dim3(L.nblk_x), blk, L.lds_x_fwd, L.stream, a, ip);
+      hipLaunchKernelGGL((k_local<T>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
       break;
     }
-    case Part::FormH: {
-      Timed tm(L, K_LOCAL);
-      hipLaunchKernelGGL((k_local_fwdx<T, false>), dim3(L.nblk_x), blk, L.lds_x_fwd, L.stream, a, ip);
-      break;
-    }
-    case Part::ProjectRest: {
+    case Part::Project: {
       {
-        Timed tm(L, K_FFT_Y_FWD);
-        hipLaunchKernelGGL((k_fft_y<T, B, false>), dim3(L.nblk_y, 9), blk, lds_y, L.stream, a);
+        Timed tm(L, K_DIV_FWDX);
+        hipLaunchKernelGGL((k_div_fwdx<T>), dim3(L.nblk_x), blk, L.lds_x, L.stream, a);
       }
       {
-        Timed tm(L, K_GREEN_Z);
-        hipLaunchKernelGGL((k_green_z<T, B>), dim3(L.nblk_z), blk, lds_z, L.stream, a);
+        Timed tm(L, K_FFT_Y_FWD);
+        hipLaunchKernelGGL((k_fft_y<T, B, false>), dim3(L.nblk_y, 3), blk, lds_y, L.stream, a);
+      }
+      {
+        Timed tm(L, K_POISSON_Z);
+        hipLaunchKernelGGL((k_poisson_z<T, B>), dim3(L.nblk_z, 3), blk, lds_z, L.stream, a);
       }
       {
         Timed tm(L, K_FFT_Y_INV);
@@ -571,7 +647,7 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       }
       {
         Timed tm(L, K_INV_X);
-        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_x), blk, L.lds_x_inv, L.stream, a);
+        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_x), blk, L.lds_x, L.stream, a);
       }
       break;
     }

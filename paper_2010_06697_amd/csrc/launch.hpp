@@ -26,7 +26,8 @@ struct KernelArgs {
 
 // kernel ids of the profiling interface (same order as in include/admm.h)
 enum KernelId {
-  K_LOCAL = 0, K_FFT_Y_FWD, K_GREEN_Z, K_FFT_Y_INV, K_INV_X, K_UPDATE, K_FINALIZE, K_MEAN, K_COUNT
+  K_LOCAL = 0, K_DIV_FWDX, K_FFT_Y_FWD, K_POISSON_Z, K_FFT_Y_INV, K_INV_X, K_UPDATE, K_FINALIZE,
+  K_MEAN, K_COUNT
 };
 
 // brackets kernel launches with events on the launch stream when profiling
@@ -42,10 +43,10 @@ struct LaunchCfg {
   hipStream_t stream;
   int nblk_x, nblk_y, nblk_z, nblk_u;
   int n2max, n3max;
-  size_t lds_x_fwd, lds_x_inv;
+  size_t lds_x;  // LDS bytes of the x1-pass kernels
 };
 
-enum class Part { Local, FormH, ProjectRest, Update, MeanStress };
+enum class Part { Local, Project, Update, MeanStress };
 
 // Enqueues one part of the iteration on L.stream.
 hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, Part part,

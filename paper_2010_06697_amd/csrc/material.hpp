@@ -14,177 +14,230 @@
 // plus rho I, a Cholesky factorisation (steepest descent when it is not
 // positive definite) and backtracking (Armijo on phi, or on |grad phi| once
 // the predicted decrease is below phi's rounding floor), rejecting det F <= 0.
-// J, ln J, the stress and the gradient are always double; the tangent, its
-// factorisation and the solve are in HT (float in the reduced-precision mode).
+//
+// Precision: J - 1, ln J and phi are double in both modes. The iterate, the
+// stress and the gradient are TG, the tangent, its factorisation and the
+// solve TH: double/double in the FP64 mode, float/float in the reduced mode.
 #pragma once
 
 #include "common.hpp"
 
 namespace admm {
 
-struct NHPoint {
-  double J, lnJ, gn;
-  double G[9];  // F^-T
-  double g[9];  // grad phi = P + rho (E - A)
+// ln(1 + x) by the series ln((1+s)/(1-s)) = 2 (s + s^3/3 + s^5/5 + ...),
+// s = x / (2 + x): for J = 1 + x in [0.8, 1.25], |s| <= 1/9 and ten terms
+// leave a truncation below 1e-18 relative. The library log1p elsewhere.
+__device__ __forceinline__ double log1p_near1(double x) {
+  if (x > -0.2 && x < 0.25) {
+    const double s = x / (2.0 + x);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    return 2.0 * s * p;
+  }
+  return log1p(x);
+}
+
+template <typename TG> struct NHPoint {
+  double lnJ;   // ln J (double)
+  TG gn2;       // |grad phi|^2
+  TG G[9];      // F^-T
+  TG g[9];      // grad phi = P + rho (E - A)
 };
 
-__device__ __forceinline__ bool nh_point(const double *E, const double *A, double rho, double mu,
-                                         double lam, NHPoint &s) {
-  double cE[9];
-  cE[0] = E[4] * E[8] - E[5] * E[7];
-  cE[1] = E[5] * E[6] - E[3] * E[8];
-  cE[2] = E[3] * E[7] - E[4] * E[6];
-  cE[3] = E[2] * E[7] - E[1] * E[8];
-  cE[4] = E[0] * E[8] - E[2] * E[6];
-  cE[5] = E[1] * E[6] - E[0] * E[7];
-  cE[6] = E[1] * E[5] - E[2] * E[4];
-  cE[7] = E[2] * E[3] - E[0] * E[5];
-  cE[8] = E[0] * E[4] - E[1] * E[3];
-  const double tr = E[0] + E[4] + E[8];
-  const double s2 = cE[0] + cE[4] + cE[8];
-  const double dE = E[0] * cE[0] + E[1] * cE[1] + E[2] * cE[2];
+// state of the local problem at E; false when det F <= 0
+template <typename TG>
+__device__ __forceinline__ bool nh_point(const TG *E, const TG *A, TG rho, TG mu, TG lam,
+                                         NHPoint<TG> &s) {
+  // J - 1 in double from the (exactly converted) components of E
+  double e[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) e[k] = (double)E[k];
+  const double c0 = e[4] * e[8] - e[5] * e[7];
+  const double c1 = e[5] * e[6] - e[3] * e[8];
+  const double c2 = e[3] * e[7] - e[4] * e[6];
+  const double c4 = e[0] * e[8] - e[2] * e[6];
+  const double c8 = e[0] * e[4] - e[1] * e[3];
+  const double tr = e[0] + e[4] + e[8];
+  const double s2 = c0 + c4 + c8;
+  const double dE = e[0] * c0 + e[1] * c1 + e[2] * c2;
   const double jm1 = tr + s2 + dE;
   const double J = 1.0 + jm1;
   if (!(J > 0.0)) return false;
-  const double lnJ = log1p(jm1);
-  const double iJ = 1.0 / J;
-  const double q = s2 + dE;
-  double gn = 0.0;
+  s.lnJ = log1p_near1(jm1);
+  TG cE[9];
+  cE[0] = (TG)c0;
+  cE[1] = (TG)c1;
+  cE[2] = (TG)c2;
+  cE[3] = E[2] * E[7] - E[1] * E[8];
+  cE[4] = (TG)c4;
+  cE[5] = E[1] * E[6] - E[0] * E[7];
+  cE[6] = E[1] * E[5] - E[2] * E[4];
+  cE[7] = E[2] * E[3] - E[0] * E[5];
+  cE[8] = (TG)c8;
+  const TG Jt = (TG)J, iJ = (TG)1 / Jt, q = (TG)(s2 + dE), trt = (TG)tr;
+  const TG lnJt = (TG)s.lnJ;
+  TG gn2 = (TG)0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const int a = 3 * i + j;
-      const double Et = E[3 * j + i];
-      const double dia = (i == j) ? 1.0 : 0.0;
-      const double G = (cE[a] - Et + dia * (1.0 + tr)) * iJ;
-      const double P = mu * iJ * (dia * q + J * E[a] + Et - cE[a]) + lam * lnJ * G;
-      const double g = P + rho * (E[a] - A[a]);
+      const TG Et = E[3 * j + i];
+      const TG dia = (i == j) ? (TG)1 : (TG)0;
+      const TG G = (cE[a] - Et + dia * ((TG)1 + trt)) * iJ;
+      const TG P = mu * iJ * (dia * q + Jt * E[a] + Et - cE[a]) + lam * lnJt * G;
+      const TG g = P + rho * (E[a] - A[a]);
       s.G[a] = G;
       s.g[a] = g;
-      gn += g * g;
+      gn2 += g * g;
     }
-  s.J = J;
-  s.lnJ = lnJ;
-  s.gn = sqrt(gn);
+  s.gn2 = gn2;
   return true;
 }
 
-__device__ __forceinline__ double nh_phi(const double *E, const double *A, double rho, double mu,
-                                         double lam, const NHPoint &s) {
-  double tr = E[0] + E[4] + E[8], e2 = 0.0, d2 = 0.0;
+template <typename TG>
+__device__ __forceinline__ double nh_phi(const TG *E, const TG *A, double rho, double mu,
+                                         double lam, double lnJ) {
+  double tr = (double)E[0] + (double)E[4] + (double)E[8], e2 = 0.0, d2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    e2 += E[k] * E[k];
-    d2 += (E[k] - A[k]) * (E[k] - A[k]);
+    const double ek = (double)E[k], dk = ek - (double)A[k];
+    e2 += ek * ek;
+    d2 += dk * dk;
   }
-  return 0.5 * mu * (2.0 * tr + e2) - mu * s.lnJ + 0.5 * lam * s.lnJ * s.lnJ + 0.5 * rho * d2;
+  return 0.5 * mu * (2.0 * tr + e2) - mu * lnJ + 0.5 * lam * lnJ * lnJ + 0.5 * rho * d2;
 }
 
-// |I + X|_F from X
-__device__ __forceinline__ double norm_ipx(const double *X) {
-  double tr = X[0] + X[4] + X[8], x2 = 0.0;
+// |I + X|_F^2 from X
+template <typename TG> __device__ __forceinline__ TG norm2_ipx(const TG *X) {
+  TG tr = X[0] + X[4] + X[8], x2 = (TG)0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) x2 += X[k] * X[k];
-  return sqrt(fmax(3.0 + 2.0 * tr + x2, 0.0));
+  return fmax((TG)3 + (TG)2 * tr + x2, (TG)0);
 }
+
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 
 constexpr __host__ __device__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // Newton solve of the local problem. E: warm start in, minimiser out.
-// Returns the iteration count (>= 0), -1 when the iteration cap or the line
-// search gave up (E keeps the last accepted iterate), -2 when det F <= 0 at
-// the start.
-template <typename HT>
-__device__ int nh_newton(double *E, const double *A, double rho, double mu, double lam, int maxit,
-                         double gtol, double step_tol) {
-  NHPoint s;
+// Stops when |grad phi| <= gtol (mu + lambda + rho)(1 + |F| + |A|) before a
+// step, or after a full positive-definite Newton step with
+// |dE| <= step_tol max(1, |F|) (which leaves an error of order |dE|^2).
+// Returns the iteration count (>= 0), -1 when the cap or the line search gave
+// up (E keeps the last accepted iterate), -2 when det F <= 0 at the start.
+template <typename TG, typename TH>
+__device__ int nh_newton(TG *E, const TG *A, TG rho, TG mu, TG lam, int maxit, double gtol,
+                         double step_tol) {
+  NHPoint<TG> s;
   if (!nh_point(E, A, rho, mu, lam, s)) return -2;
-  const double smod = mu + lam + rho;
-  const double nA = norm_ipx(A);
+  const double smod = (double)mu + (double)lam + (double)rho;
+  const double nA = sqrt((double)norm2_ipx(A));
+  const double tol_step2 = step_tol * step_tol;
   for (int it = 0; it < maxit; ++it) {
-    const double nF = norm_ipx(E);
-    if (s.gn <= gtol * smod * (1.0 + nF + nA)) return it;
+    const double nF2 = (double)norm2_ipx(E);
+    const double thr = gtol * smod * (1.0 + sqrt(nF2) + nA);
+    if ((double)s.gn2 <= thr * thr) return it;
 
-    // prox tangent, lower triangle packed
-    HT L[45];
-    const double c1 = mu - lam * s.lnJ;
+    // prox tangent, lower triangle packed, assembled in TH
+    TH L[45], Gh[9], id[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Gh[k] = (TH)s.G[k];
+    const TH c1 = (TH)((double)mu - (double)lam * s.lnJ), lh = (TH)lam, dia = (TH)(mu + rho);
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
       for (int b = 0; b <= a; ++b) {
         const int i = a / 3, J = a % 3, k = b / 3, l = b % 3;
-        double v = c1 * s.G[3 * k + J] * s.G[3 * i + l] + lam * s.G[a] * s.G[b];
-        if (a == b) v += mu + rho;
-        L[tri(a, b)] = (HT)v;
+        TH v = c1 * Gh[3 * k + J] * Gh[3 * i + l] + lh * Gh[a] * Gh[b];
+        if (a == b) v += dia;
+        L[tri(a, b)] = v;
       }
     bool pd = true;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-      HT d = L[tri(j, j)];
+      TH d = L[tri(j, j)];
 #pragma unroll
       for (int k = 0; k < j; ++k) d -= L[tri(j, k)] * L[tri(j, k)];
-      pd = pd && (d > (HT)0);
-      d = sqrt(d);
-      L[tri(j, j)] = d;
-      const HT id = (HT)1 / d;
+      pd = pd && (d > (TH)0);
+      id[j] = rsqrt_t(d);
 #pragma unroll
       for (int i = j + 1; i < 9; ++i) {
-        HT v = L[tri(i, j)];
+        TH v = L[tri(i, j)];
 #pragma unroll
         for (int k = 0; k < j; ++k) v -= L[tri(i, k)] * L[tri(j, k)];
-        L[tri(i, j)] = v * id;
+        L[tri(i, j)] = v * id[j];
       }
     }
-    double d[9];
+    TG d[9];
     if (pd) {
-      HT y[9];
+      TH y[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        HT v = (HT)(-s.g[i]);
+        TH v = (TH)(-s.g[i]);
 #pragma unroll
         for (int k = 0; k < i; ++k) v -= L[tri(i, k)] * y[k];
-        y[i] = v / L[tri(i, i)];
+        y[i] = v * id[i];
       }
 #pragma unroll
       for (int i = 8; i >= 0; --i) {
-        HT v = y[i];
+        TH v = y[i];
 #pragma unroll
         for (int k = i + 1; k < 9; ++k) v -= L[tri(k, i)] * y[k];
-        y[i] = v / L[tri(i, i)];
+        y[i] = v * id[i];
       }
 #pragma unroll
-      for (int i = 0; i < 9; ++i) d[i] = (double)y[i];
+      for (int i = 0; i < 9; ++i) d[i] = (TG)y[i];
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) d[i] = -s.g[i];
     }
 
-    double slope = 0.0, nd = 0.0;
+    double slope = 0.0, nd2 = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      slope += s.g[k] * d[k];
-      nd += d[k] * d[k];
+      slope += (double)s.g[k] * (double)d[k];
+      nd2 += (double)d[k] * (double)d[k];
     }
-    nd = sqrt(nd);
-    const bool small = -slope <= 1e-12 * smod * (1.0 + nF * nF);
-    const double phi0 = small ? 0.0 : nh_phi(E, A, rho, mu, lam, s);
+    const bool small = -slope <= 1e-12 * smod * (1.0 + nF2);
+    // float iterate: a full Newton step already below the step tolerance is
+    // taken as it is; the float gradient is at its rounding floor there and
+    // no longer decides a line search
+    const bool tiny = sizeof(TG) == 4 && pd && nd2 <= tol_step2 * fmax(1.0, nF2);
+    const double phi0 = small ? 0.0 : nh_phi(E, A, rho, mu, lam, s.lnJ);
     double t = 1.0;
     bool acc = false;
-    NHPoint st;
-    double Et[9];
+    NHPoint<TG> st;
+    TG Et[9];
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Et[k] = E[k] + t * d[k];
+      for (int k = 0; k < 9; ++k) Et[k] = E[k] + (TG)t * d[k];
       if (nh_point(Et, A, rho, mu, lam, st)) {
+        if (tiny) {
+          acc = true;
+          break;
+        }
         if (!small) {
-          if (nh_phi(Et, A, rho, mu, lam, st) <= phi0 + 1e-4 * t * slope) {
+          if (nh_phi(Et, A, rho, mu, lam, st.lnJ) <= phi0 + 1e-4 * t * slope) {
             acc = true;
             break;
           }
-        } else if (st.gn <= (1.0 - 1e-4 * t) * s.gn) {
-          acc = true;
-          break;
+        } else {
+          const double f = 1.0 - 1e-4 * t;
+          if ((double)st.gn2 <= f * f * (double)s.gn2) {
+            acc = true;
+            break;
+          }
         }
       }
       t *= 0.5;
@@ -193,7 +246,7 @@ __device__ int nh_newton(double *E, const double *A, double rho, double mu, doub
 #pragma unroll
     for (int k = 0; k < 9; ++k) E[k] = Et[k];
     s = st;
-    if (pd && t == 1.0 && nd <= step_tol * fmax(1.0, norm_ipx(E))) return it + 1;
+    if (pd && t == 1.0 && nd2 <= tol_step2 * fmax(1.0, (double)norm2_ipx(E))) return it + 1;
   }
   return -1;
 }

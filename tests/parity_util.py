@@ -40,16 +40,20 @@ def rel(a, b):
     return d / s if s > 0 else d
 
 
+# the local Newton stopping rule the GPU's double-precision form uses by default
+NEWTON64 = dict(gtol=1e-14, step_tol=1e-10)
+
+
 def oracle_iterations(phase, mats, Fbar, n_iter, rho, mu_ref, adapt=False, state=None,
                       rho_min=1.0, rho_max=50.0):
     u, F, L = state if state is not None else O.initial_state(phase.shape)
     u, F, L = u.copy(), F.copy(), L.copy()
     p = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=mu_ref, adapt_rho=adapt,
-                 rho_min=rho_min, rho_max=rho_max)
+                 rho_min=rho_min, rho_max=rho_max, newton=O.newton_opts(**NEWTON64))
     r = O.admm_run(phase, omats(mats), np.asarray(Fbar).ravel(), p, u, F, L, rho)
     return u, F, L, r
 
 
 def gpu_solver(phases, mats, Fbars, precision="fp64", **params):
-    p = admm.default_params(**params)
+    p = admm.default_params(precision, **params)
     return admm.Solver(phases, mats, Fbars, p, precision=precision)

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from paper_2010_06697_amd import admm, microstructure as M
-from parity_util import gpu_solver, omats, oracle_iterations, random_state, rel
+from parity_util import NEWTON64, gpu_solver, omats, oracle_iterations, random_state, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -60,13 +60,12 @@ def test_local_step_matches_oracle(shape, precision):
     Fbar = M.random_fbar(0.04, seed=5)
     u, F, L = random_state(shape, seed=6)
     rho = 12.0
-    s = gpu_solver([phase], MATS, [Fbar], precision, rho0=rho,
-                   newton_step_tol=1e-10 if precision == "fp64" else 1e-7)
+    s = gpu_solver([phase], MATS, [Fbar], precision, rho0=rho)
     s.set_state(0, u=u, F=F, Lambda=L)
     st0 = s.state(0)
     s.local_step()
     got = s.state(0)["F"]
-    it, status, nfail = s.info(0)
+    it, status, nfail, newton_its = s.info(0)
     s.close()
     assert nfail == 0
     # oracle: per voxel, from the same (stored-precision) inputs and warm start
@@ -76,7 +75,8 @@ def test_local_step_matches_oracle(shape, precision):
     ref = np.empty_like(got)
     n3, n2, n1 = shape
     for x in np.ndindex(shape):
-        Fx, _, _, rc = O.prox(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x])
+        Fx, _, _, rc = O.prox(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x],
+                              opts=O.newton_opts(**NEWTON64))
         assert rc == O.OK
         ref[(slice(None),) + x] = Fx
     err = np.max(np.abs(got - ref))
@@ -160,8 +160,7 @@ def test_fp32_mode_homogenized_stress_within_1e5(shape):
     Fbar = M.random_fbar(0.04, seed=15)
     rho, mu_ref = 8.0, 4.0
     n_iter = 10
-    s = gpu_solver([phase], MATS, [Fbar], "fp32", rho0=rho, mu_ref=mu_ref,
-                   newton_step_tol=1e-7)
+    s = gpu_solver([phase], MATS, [Fbar], "fp32", rho0=rho, mu_ref=mu_ref)
     s.step(n_iter)
     st = s.state(0)
     P, _ = s.homogenized_stress(0)
@@ -195,8 +194,7 @@ def test_laminate16_solve_matches_exact_solution(precision):
     tol = 1e-12 if precision == "fp64" else 2e-7
     s = gpu_solver([case["phase"]], case["materials"], case["loads"], precision,
                    rho0=case["rho0"], mu_ref=case["mu_ref"], tol_p=tol, tol_d=tol,
-                   max_iter=3000, check_every=50,
-                   newton_step_tol=1e-10 if precision == "fp64" else 1e-7)
+                   max_iter=3000, check_every=50)
     rc, it, status = s.solve()
     P, L = s.homogenized_stress(0)
     s.close()
@@ -218,7 +216,7 @@ def test_laminate16_config_matches_oracle():
     P, _ = s.homogenized_stress(0)
     s.close()
     u, F, L = O.initial_state(case["phase"].shape)
-    p = O.params(max_iter=200, tol_p=1e-8, tol_d=1e-8, mu_ref=5.5)
+    p = O.params(max_iter=200, tol_p=1e-8, tol_d=1e-8, mu_ref=5.5, newton=O.newton_opts(**NEWTON64))
     r = O.admm_run(case["phase"], omats(case["materials"]), case["loads"][0].ravel(), p, u, F, L, 5.0)
     Po = O.mean_stress(case["phase"], omats(case["materials"]), F)
     say("  gpu iters", it[0], "oracle iters", r["iters"], "rel P", rel(P, Po))
@@ -265,7 +263,7 @@ def test_set_load_warm_start_and_load_path():
     s.close()
     u, F, L = O.initial_state(shape)
     for Fb in loads:
-        p = O.params(max_iter=5, fixed_iters=True, mu_ref=4.0)
+        p = O.params(max_iter=5, fixed_iters=True, mu_ref=4.0, newton=O.newton_opts(**NEWTON64))
         O.admm_run(phase, omats(MATS), Fb.ravel(), p, u, F, L, 8.0)
     assert rel(st["u"], u) <= 1e-10 and rel(st["F"], F) <= 1e-10 and rel(st["Lambda"], L) <= 1e-10
 
