@@ -65,7 +65,10 @@ typedef enum {
                             + kappa/2 (J - 1)^2, director n per voxel
                         (neo-classical energy of Sec. 5.1 with step-length
                         tensor a^(-1/3)(I + (a-1) n n) and a volumetric
-                        penalty); not supported yet: ADMM_EUNSUPPORTED */
+                        penalty). The local problem minimises over F and the
+                        unit director jointly: F-Newton at fixed n alternating
+                        with n = top eigenvector of F F^T (double precision,
+                        renormalised), until n moves less than dir_tol. */
 } admm_model;
 
 /* One phase of the material table. */
@@ -85,7 +88,8 @@ typedef struct {
   void *u_prev;          /* 3V: second buffer the library iterates into */
   void *F;               /* 9V: F - I (in/out) */
   void *Lambda;          /* 9V: multiplier (in/out) */
-  void *director;        /* 3V unit director (LCE) or NULL */
+  void *director;        /* 3V unit director (in/out; required when a phase
+                            is ADMM_LCE, else may be NULL) */
   double Fbar[9];        /* macroscopic gradient <F>, row-major, det > 0 */
 } admm_rve;
 
@@ -106,6 +110,10 @@ typedef struct {
   int32_t max_iter;     /* iteration cap of admm_solve */
   int32_t check_every;  /* admm_solve: iterations between host checks (10) */
   int32_t newton_max;   /* local Newton iteration cap (100) */
+  int32_t dir_max;      /* LCE: cap on the F / director alternations (200) */
+  int32_t reserved;
+  double dir_tol;       /* LCE: alternation stops when the director moves less
+                           than this (1e-13 FP64, 1e-6 FP32) */
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;

@@ -56,7 +56,9 @@ class Params(ctypes.Structure):
                 ("tol_d", ctypes.c_double), ("mu_ref", ctypes.c_double),
                 ("newton_gtol", ctypes.c_double), ("newton_step_tol", ctypes.c_double),
                 ("adapt_rho", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32),
+                ("dir_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dir_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -232,10 +234,11 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     p.rho0, p.rho_min, p.rho_max, p.kappa_rho, p.tau = 10.0, 1.0, 50.0, 1.3, 10.0
     p.tol_p, p.tol_d, p.mu_ref = 1e-8, 1e-8, 1.0
     if precision == "fp64":
-        p.newton_gtol, p.newton_step_tol = 1e-14, 1e-10
+        p.newton_gtol, p.newton_step_tol, p.dir_tol = 1e-14, 1e-10, 1e-13
     else:
-        p.newton_gtol, p.newton_step_tol = 1e-10, 2e-6
+        p.newton_gtol, p.newton_step_tol, p.dir_tol = 1e-10, 2e-6, 1e-6
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
+    p.dir_max = 200
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -261,7 +264,8 @@ class Solver:
     """
 
     def __init__(self, phases, materials, Fbars, params: Params | None = None,
-                 precision: str = "fp64", device: str = "cuda:0", stream=None):
+                 precision: str = "fp64", device: str = "cuda:0", stream=None,
+                 directors=None):
         import torch
 
         self.torch = torch
@@ -272,7 +276,10 @@ class Solver:
         mats = [m if isinstance(m, Material) else material(**m) for m in materials]
         self.cells = []
         rves = []
-        for ph, Fb in zip(phases, Fbars):
+        any_lce = any(m.model == LCE for m in mats)
+        if directors is None:
+            directors = [None] * len(phases)
+        for ph, Fb, n0 in zip(phases, Fbars, directors):
             ph = np.ascontiguousarray(ph, np.uint8)
             n3, n2, n1 = ph.shape
             if admm_check_grid(n1, n2, n3) != OK:
@@ -284,7 +291,13 @@ class Solver:
                 "u_prev": torch.zeros((3, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "F": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "Lambda": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
+                "director": None,
             }
+            if any_lce:
+                if n0 is None:
+                    raise AdmmError(EINVAL, "an LCE phase needs a director field per cell")
+                n0 = np.ascontiguousarray(n0, np.float64).reshape(3, n3, n2, n1)
+                cell["director"] = torch.from_numpy(n0).to(self.device, self.dtype)
             self.cells.append(cell)
             r = Rve()
             r.n[0], r.n[1], r.n[2] = n1, n2, n3
@@ -293,7 +306,7 @@ class Solver:
             r.u_prev = cell["u_prev"].data_ptr()
             r.F = cell["F"].data_ptr()
             r.Lambda = cell["Lambda"].data_ptr()
-            r.director = None
+            r.director = cell["director"].data_ptr() if cell["director"] is not None else None
             for k, v in enumerate(np.asarray(Fb, np.float64).reshape(9)):
                 r.Fbar[k] = v
             rves.append(r)
@@ -353,10 +366,13 @@ class Solver:
         F[0] += 1.0
         F[4] += 1.0
         F[8] += 1.0
-        return {"u": c["u"].double().cpu().numpy(), "u_prev": c["u_prev"].double().cpu().numpy(),
-                "F": F, "Lambda": c["Lambda"].double().cpu().numpy()}
+        out = {"u": c["u"].double().cpu().numpy(), "u_prev": c["u_prev"].double().cpu().numpy(),
+               "F": F, "Lambda": c["Lambda"].double().cpu().numpy()}
+        if c["director"] is not None:
+            out["director"] = c["director"].double().cpu().numpy()
+        return out
 
-    def set_state(self, rve=0, u=None, F=None, Lambda=None):
+    def set_state(self, rve=0, u=None, F=None, Lambda=None, director=None):
         """Overwrites the fields of one cell (F given as F itself)."""
         c = self.cells[rve]
         t = self.torch
@@ -371,6 +387,9 @@ class Solver:
         if Lambda is not None:
             c["Lambda"].copy_(t.from_numpy(np.ascontiguousarray(Lambda, np.float64))
                               .to(self.device, self.dtype))
+        if director is not None:
+            c["director"].copy_(t.from_numpy(np.ascontiguousarray(director, np.float64))
+                                .to(self.device, self.dtype))
         t.cuda.synchronize(self.device)
 
     def close(self):

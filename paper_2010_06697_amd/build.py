@@ -21,6 +21,19 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+# the host compilation pass does not know the (device-only) feature; harmless
+_HOST_NOTE = "is not a recognized feature for this target"
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    for line in (p.stdout + p.stderr).splitlines():
+        if _HOST_NOTE not in line:
+            print(line, file=sys.stderr)
+    if p.returncode != 0:
+        raise subprocess.CalledProcessError(p.returncode, cmd)
+
+
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     for src in SOURCES:
@@ -31,12 +44,12 @@ def build(verbose: bool = False, extra=()) -> str:
                *extra]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        _run(cmd)
         objs.append(obj)
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    _run(cmd)
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)

@@ -258,6 +258,8 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   ip.hist_cap = c->hist_cap;
   ip.n_rve = c->n_rve;
   ip.n_mat = c->n_mat;
+  ip.dir_max = p.dir_max;
+  ip.dir_tol = p.dir_tol;
   return ip;
 }
 
@@ -341,21 +343,29 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   *out = nullptr;
   if (!rves || n_rve <= 0 || !mats || n_mat <= 0 || n_mat > 256 || !params) return ADMM_EINVAL;
   if (precision != ADMM_FP64 && precision != ADMM_FP32_FP64RED) return ADMM_EINVAL;
+  bool any_lce = false;
   for (int q = 0; q < n_mat; ++q) {
-    if (mats[q].model == ADMM_LCE) return ADMM_EUNSUPPORTED;
-    if (mats[q].model != ADMM_NEOHOOKE) return ADMM_EINVAL;
-    if (!(mats[q].mu > 0.0) || !(mats[q].lambda >= 0.0)) return ADMM_EINVAL;
+    if (mats[q].model == ADMM_LCE) {
+      if (!(mats[q].mu > 0.0) || !(mats[q].a > 0.0) || !(mats[q].kappa >= 0.0)) return ADMM_EINVAL;
+      any_lce = true;
+    } else if (mats[q].model == ADMM_NEOHOOKE) {
+      if (!(mats[q].mu > 0.0) || !(mats[q].lambda >= 0.0)) return ADMM_EINVAL;
+    } else {
+      return ADMM_EINVAL;
+    }
   }
   const admm_params &p = *params;
   if (!(p.rho0 > 0.0) || !(p.rho_min > 0.0) || !(p.rho_max >= p.rho_min) || !(p.kappa_rho > 1.0) ||
       !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
       p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0))
     return ADMM_EINVAL;
+  if (any_lce && (p.dir_max < 1 || !(p.dir_tol >= 0.0))) return ADMM_EINVAL;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
     int g = admm_check_grid(R.n[0], R.n[1], R.n[2]);
     if (g != ADMM_OK) return g;
     if (!R.phase || !R.u || !R.u_prev || !R.F || !R.Lambda || R.u == R.u_prev) return ADMM_EINVAL;
+    if (any_lce && !R.director) return ADMM_EINVAL;
     if (!valid_fbar(R.Fbar)) return ADMM_EINVAL;
   }
   const bool fp64 = precision == ADMM_FP64;
@@ -467,6 +477,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
+  c->L.any_lce = any_lce;
   c->L.stream = c->stream;
   c->L.nblk_x = bx[n_rve];
   c->L.nblk_y = by[n_rve];
@@ -488,7 +499,10 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
 
   std::vector<Material> mh(n_mat);
   for (int q = 0; q < n_mat; ++q) {
-    mh[q] = Material{mats[q].model, 0, mats[q].mu, mats[q].lambda, mats[q].a, mats[q].kappa};
+    const admm_material &m = mats[q];
+    const bool lce = m.model == ADMM_LCE;
+    mh[q] = Material{m.model, 0, m.mu, m.lambda, m.a, m.kappa,
+                     lce ? m.mu * std::cbrt(m.a) : 0.0, lce ? 1.0 / m.a - 1.0 : 0.0};
   }
   INIT_TRY(hipMalloc(&c->mats_d, sizeof(Material) * n_mat));
   INIT_TRY(hipMemcpy(c->mats_d, mh.data(), sizeof(Material) * n_mat, hipMemcpyHostToDevice));

@@ -55,9 +55,11 @@ struct RveState {
 constexpr int kVoxelsPerThread = 4;  // grid-stride depth of the per-voxel reduction kernels
 
 struct Material {
-  int model;
+  int model;  // 0 neo-Hookean, 1 LCE
   int pad;
   double mu, lam, a, kappa;
+  double mua;   // mu a^(1/3)
+  double beta;  // 1/a - 1
 };
 
 // scalar parameters of one launch sequence (passed by value: kernel arguments
@@ -73,7 +75,8 @@ struct IterParams {
   int hist_cap;
   int n_rve;
   int n_mat;
-  int pad;
+  int dir_max;       // LCE: cap on the F / director alternations
+  double dir_tol;    // LCE: stop when the director moves less than this
 };
 
 template <typename T> struct cplx;

@@ -99,7 +99,37 @@ __device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwave
 #define ADMM_LOCAL_WAVES_PER_EU 1
 #endif
 
+// LCE: alternate the F-minimisation at fixed director and the exact
+// director-minimisation at fixed F (top eigenvector of F F^T) until the
+// director moves less than dir_tol. Returns the last Newton status and adds
+// the Newton iterations to its.
 template <typename T>
+__device__ int lce_local(T *E, const T *At, const Material &m, double rho, double *n,
+                         const IterParams &ip, int &its) {
+  Lce<T> M;
+  M.mua = (T)m.mua;
+  M.beta = (T)m.beta;
+  M.kappa = (T)m.kappa;
+  M.mu = (T)m.mu;
+  int rc = -1;
+  for (int outer = 0; outer < ip.dir_max; ++outer) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M.n[k] = (T)n[k];
+    rc = newton<T, T>(E, At, M, (T)rho, ip.newton_max, ip.gtol, ip.step_tol);
+    its += rc >= 0 ? rc : ip.newton_max;
+    if (rc == -2) break;
+    double nn[3];
+    director_update(E, n, nn);
+    const double d0 = nn[0] - n[0], d1 = nn[1] - n[1], d2 = nn[2] - n[2];
+    n[0] = nn[0];
+    n[1] = nn[1];
+    n[2] = nn[2];
+    if (d0 * d0 + d1 * d1 + d2 * d2 <= ip.dir_tol * ip.dir_tol) break;
+  }
+  return rc;
+}
+
+template <typename T, bool ANY_LCE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
 void k_local(KernelArgs a, IterParams ip) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -135,10 +165,26 @@ void k_local(KernelArgs a, IterParams ip) {
     const int ph = D.phase[idx];
     if (ph < a.n_mat) {
       const Material m = a.mats[ph];
-      const int rc = nh_newton<T, T>(E, At, (T)rho, (T)m.mu, (T)m.lam, ip.newton_max, ip.gtol,
-                                     ip.step_tol);
+      int rc;
+      if (ANY_LCE && m.model == 1) {
+        T *dg = static_cast<T *>(D.dir);
+        double n[3] = {(double)dg[idx], (double)dg[V + idx], (double)dg[2 * V + idx]};
+        const double nn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        n[0] *= nn;
+        n[1] *= nn;
+        n[2] *= nn;
+        rc = lce_local<T>(E, At, m, rho, n, ip, n_its);
+        dg[idx] = (T)n[0];
+        dg[V + idx] = (T)n[1];
+        dg[2 * V + idx] = (T)n[2];
+      } else {
+        NeoHooke<T> M;
+        M.mu = (T)m.mu;
+        M.lam = (T)m.lam;
+        rc = newton<T, T>(E, At, M, (T)rho, ip.newton_max, ip.gtol, ip.step_tol);
+        n_its = rc >= 0 ? rc : ip.newton_max;
+      }
       n_fail = rc == -1;
-      n_its = rc >= 0 ? rc : ip.newton_max;
       if (rc == -2) atomicOr(&st->domain_err, 1);
 #pragma unroll
       for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
@@ -564,9 +610,32 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
       v[9 + c] += (double)Lg[c * V + idx];
     }
     const int ph = D.phase[idx];
-    NHPoint<double> s;
+    Point<double> s;
+    bool ok = false;
     // with rho = 0 the gradient of the prox objective is the stress P
-    if (ph < a.n_mat && nh_point<double>(E, E, 0.0, a.mats[ph].mu, a.mats[ph].lam, s)) {
+    if (ph < a.n_mat) {
+      const Material m = a.mats[ph];
+      if (m.model == 1) {
+        Lce<double> M;
+        M.mua = m.mua;
+        M.beta = m.beta;
+        M.kappa = m.kappa;
+        M.mu = m.mu;
+        const T *dg = static_cast<const T *>(D.dir);
+        const double n0 = dg[idx], n1v = dg[V + idx], n2v = dg[2 * V + idx];
+        const double nn = 1.0 / sqrt(n0 * n0 + n1v * n1v + n2v * n2v);
+        M.n[0] = n0 * nn;
+        M.n[1] = n1v * nn;
+        M.n[2] = n2v * nn;
+        ok = M.point(E, E, 0.0, s);
+      } else {
+        NeoHooke<double> M;
+        M.mu = m.mu;
+        M.lam = m.lam;
+        ok = M.point(E, E, 0.0, s);
+      }
+    }
+    if (ok) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) v[c] += s.g[c];
     } else {
@@ -625,7 +694,10 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
   switch (part) {
     case Part::Local: {
       Timed tm(L, K_LOCAL);
-      hipLaunchKernelGGL((k_local<T>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
+      if (L.any_lce)
+        hipLaunchKernelGGL((k_local<T, true>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
+      else
+        hipLaunchKernelGGL((k_local<T, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
       break;
     }
     case Part::Project: {

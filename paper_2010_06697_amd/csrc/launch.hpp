@@ -44,6 +44,7 @@ struct LaunchCfg {
   int nblk_x, nblk_y, nblk_z, nblk_u;
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
+  bool any_lce;  // some phase uses the LCE energy
 };
 
 enum class Part { Local, Project, Update, MeanStress };

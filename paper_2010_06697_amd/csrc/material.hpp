@@ -1,17 +1,20 @@
-// material.hpp -- per-voxel local problem (Step 1 of Sec. 2.1) for the
-// compressible neo-Hookean energy
-//     W(F) = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 (ln J)^2,
-// written in the displacement gradient E = F - I so that nothing cancels at
-// small strain:
+// material.hpp -- per-voxel local problem (Step 1 of Sec. 2.1): minimise
+//     phi(F) = W(F) + rho/2 |F - A|^2,   A = grad u + Lambda/rho,
+// for two stored energies, written in the displacement gradient E = F - I so
+// that nothing cancels at small strain:
+//   neo-Hookean      W = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 (ln J)^2
+//   neo-classical    W = mu/2 [a^(1/3) (|F|^2 + (1/a - 1) |F^T n|^2) - 3]
+//   (LCE, Sec. 5.1)      + kappa/2 (J - 1)^2,  at a fixed unit director n
+// with
 //     J - 1 = tr E + s2(E) + det E          (s2: sum of principal 2x2 minors)
-//     cof F = (1 + tr E) I - E^T + cof E
-//     J (F - F^-T) = (s2 + det E) I + J E + E^T - cof E
-//     P = mu (F - F^-T) + lambda ln J F^-T,   ln J = log1p(J - 1).
-// The local problem minimises phi(E) = W(I + E) + rho/2 |E - A|^2 by Newton's
-// method on the 9-vector E with the analytic tangent
-//     dP_iJ/dF_kL = mu d_ik d_JL + (mu - lambda ln J) Fi_Jk Fi_Li
-//                   + lambda Fi_Ji Fi_Lk        (Fi = F^-1)
-// plus rho I, a Cholesky factorisation (steepest descent when it is not
+//     cof F = J F^-T = (1 + tr E) I - E^T + cof E
+//     J (F - F^-T) = (s2 + det E) I + J E + E^T - cof E.
+// Newton's method on the 9-vector E with the analytic tangent plus rho I:
+//     neo-Hookean   mu d_ik d_JL + (mu - lambda ln J) Fi_Jk Fi_Li
+//                   + lambda Fi_Ji Fi_Lk
+//     LCE           mu a^(1/3) (d_ik + (1/a - 1) n_i n_k) d_JL
+//                   - kappa (J - 1) J Fi_Jk Fi_Li + kappa (2J - 1) J Fi_Ji Fi_Lk
+// (Fi = F^-1), a Cholesky factorisation (steepest descent when it is not
 // positive definite) and backtracking (Armijo on phi, or on |grad phi| once
 // the predicted decrease is below phi's rounding floor), rejecting det F <= 0.
 //
@@ -46,18 +49,20 @@ __device__ __forceinline__ double log1p_near1(double x) {
   return log1p(x);
 }
 
-template <typename TG> struct NHPoint {
-  double lnJ;   // ln J (double)
+// state of the local problem at one iterate
+template <typename TG> struct Point {
+  double jm1;   // J - 1
+  double lnJ;   // ln J (neo-Hookean only)
   TG gn2;       // |grad phi|^2
   TG G[9];      // F^-T
   TG g[9];      // grad phi = P + rho (E - A)
 };
 
-// state of the local problem at E; false when det F <= 0
+// J - 1 in double from the (exactly converted) components of E, and the
+// cofactor of E in TG. False when det F <= 0.
 template <typename TG>
-__device__ __forceinline__ bool nh_point(const TG *E, const TG *A, TG rho, TG mu, TG lam,
-                                         NHPoint<TG> &s) {
-  // J - 1 in double from the (exactly converted) components of E
+__device__ __forceinline__ bool kinematics(const TG *E, TG *cE, double &jm1, double &tr,
+                                           double &q) {
   double e[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) e[k] = (double)E[k];
@@ -66,14 +71,11 @@ __device__ __forceinline__ bool nh_point(const TG *E, const TG *A, TG rho, TG mu
   const double c2 = e[3] * e[7] - e[4] * e[6];
   const double c4 = e[0] * e[8] - e[2] * e[6];
   const double c8 = e[0] * e[4] - e[1] * e[3];
-  const double tr = e[0] + e[4] + e[8];
+  tr = e[0] + e[4] + e[8];
   const double s2 = c0 + c4 + c8;
   const double dE = e[0] * c0 + e[1] * c1 + e[2] * c2;
-  const double jm1 = tr + s2 + dE;
-  const double J = 1.0 + jm1;
-  if (!(J > 0.0)) return false;
-  s.lnJ = log1p_near1(jm1);
-  TG cE[9];
+  q = s2 + dE;
+  jm1 = tr + q;
   cE[0] = (TG)c0;
   cE[1] = (TG)c1;
   cE[2] = (TG)c2;
@@ -83,39 +85,138 @@ __device__ __forceinline__ bool nh_point(const TG *E, const TG *A, TG rho, TG mu
   cE[6] = E[1] * E[5] - E[2] * E[4];
   cE[7] = E[2] * E[3] - E[0] * E[5];
   cE[8] = (TG)c8;
-  const TG Jt = (TG)J, iJ = (TG)1 / Jt, q = (TG)(s2 + dE), trt = (TG)tr;
-  const TG lnJt = (TG)s.lnJ;
-  TG gn2 = (TG)0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int a = 3 * i + j;
-      const TG Et = E[3 * j + i];
-      const TG dia = (i == j) ? (TG)1 : (TG)0;
-      const TG G = (cE[a] - Et + dia * ((TG)1 + trt)) * iJ;
-      const TG P = mu * iJ * (dia * q + Jt * E[a] + Et - cE[a]) + lam * lnJt * G;
-      const TG g = P + rho * (E[a] - A[a]);
-      s.G[a] = G;
-      s.g[a] = g;
-      gn2 += g * g;
-    }
-  s.gn2 = gn2;
-  return true;
+  return 1.0 + jm1 > 0.0;
 }
 
-template <typename TG>
-__device__ __forceinline__ double nh_phi(const TG *E, const TG *A, double rho, double mu,
-                                         double lam, double lnJ) {
-  double tr = (double)E[0] + (double)E[4] + (double)E[8], e2 = 0.0, d2 = 0.0;
+template <typename TG> struct NeoHooke {
+  TG mu, lam;
+
+  __device__ double smod() const { return (double)mu + (double)lam; }
+
+  __device__ __forceinline__ bool point(const TG *E, const TG *A, TG rho, Point<TG> &s) const {
+    TG cE[9];
+    double tr, q;
+    if (!kinematics(E, cE, s.jm1, tr, q)) return false;
+    s.lnJ = log1p_near1(s.jm1);
+    const TG Jt = (TG)(1.0 + s.jm1), iJ = (TG)1 / Jt, qt = (TG)q, trt = (TG)tr;
+    const TG lnJt = (TG)s.lnJ;
+    TG gn2 = (TG)0;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const double ek = (double)E[k], dk = ek - (double)A[k];
-    e2 += ek * ek;
-    d2 += dk * dk;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int a = 3 * i + j;
+        const TG Et = E[3 * j + i];
+        const TG dia = (i == j) ? (TG)1 : (TG)0;
+        const TG G = (cE[a] - Et + dia * ((TG)1 + trt)) * iJ;
+        const TG P = mu * iJ * (dia * qt + Jt * E[a] + Et - cE[a]) + lam * lnJt * G;
+        const TG g = P + rho * (E[a] - A[a]);
+        s.G[a] = G;
+        s.g[a] = g;
+        gn2 += g * g;
+      }
+    s.gn2 = gn2;
+    return true;
   }
-  return 0.5 * mu * (2.0 * tr + e2) - mu * lnJ + 0.5 * lam * lnJ * lnJ + 0.5 * rho * d2;
-}
+
+  __device__ __forceinline__ double phi(const TG *E, const TG *A, double rho,
+                                        const Point<TG> &s) const {
+    double tr = (double)E[0] + (double)E[4] + (double)E[8], e2 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double ek = (double)E[k], dk = ek - (double)A[k];
+      e2 += ek * ek;
+      d2 += dk * dk;
+    }
+    const double m = (double)mu, l = (double)lam;
+    return 0.5 * m * (2.0 * tr + e2) - m * s.lnJ + 0.5 * l * s.lnJ * s.lnJ + 0.5 * rho * d2;
+  }
+
+  // coefficients of the tangent: dia d_ik d_JL + c1 Fi_Jk Fi_Li + c2 Fi_Ji Fi_Lk
+  template <typename TH>
+  __device__ __forceinline__ void coeffs(const Point<TG> &s, TG rho, TH &dia, TH &c1,
+                                         TH &c2) const {
+    dia = (TH)(mu + rho);
+    c1 = (TH)((double)mu - (double)lam * s.lnJ);
+    c2 = (TH)lam;
+  }
+  template <typename TH> __device__ __forceinline__ TH director_term(int, int) const {
+    return (TH)0;
+  }
+};
+
+template <typename TG> struct Lce {
+  TG mua;    // mu a^(1/3)
+  TG beta;   // 1/a - 1
+  TG kappa;
+  TG mu;
+  TG n[3];   // unit director
+
+  __device__ double smod() const { return (double)mua + (double)kappa; }
+
+  __device__ __forceinline__ bool point(const TG *E, const TG *A, TG rho, Point<TG> &s) const {
+    TG cE[9];
+    double tr, q;
+    if (!kinematics(E, cE, s.jm1, tr, q)) return false;
+    s.lnJ = 0.0;
+    const TG Jt = (TG)(1.0 + s.jm1), iJ = (TG)1 / Jt, trt = (TG)tr;
+    const TG kv = kappa * (TG)s.jm1;  // kappa (J - 1)
+    // F^T n = n + E^T n
+    TG ftn[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) ftn[l] = n[l] + E[l] * n[0] + E[3 + l] * n[1] + E[6 + l] * n[2];
+    TG gn2 = (TG)0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int a = 3 * i + j;
+        const TG dia = (i == j) ? (TG)1 : (TG)0;
+        const TG cof = cE[a] - E[3 * j + i] + dia * ((TG)1 + trt);  // J F^-T
+        const TG P = mua * (dia + E[a] + beta * n[i] * ftn[j]) + kv * cof;
+        const TG g = P + rho * (E[a] - A[a]);
+        s.G[a] = cof * iJ;
+        s.g[a] = g;
+        gn2 += g * g;
+      }
+    s.gn2 = gn2;
+    return true;
+  }
+
+  __device__ __forceinline__ double phi(const TG *E, const TG *A, double rho,
+                                        const Point<TG> &s) const {
+    double tr = (double)E[0] + (double)E[4] + (double)E[8], e2 = 0.0, d2 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double ek = (double)E[k], dk = ek - (double)A[k];
+      e2 += ek * ek;
+      d2 += dk * dk;
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double v = (double)n[l] + (double)E[l] * n[0] + (double)E[3 + l] * n[1] +
+                       (double)E[6 + l] * n[2];
+      t2 += v * v;
+    }
+    const double f2 = 3.0 + 2.0 * tr + e2;
+    return 0.5 * (double)mua * (f2 + (double)beta * t2) - 1.5 * (double)mu +
+           0.5 * (double)kappa * s.jm1 * s.jm1 + 0.5 * rho * d2;
+  }
+
+  template <typename TH>
+  __device__ __forceinline__ void coeffs(const Point<TG> &s, TG rho, TH &dia, TH &c1,
+                                         TH &c2) const {
+    const double J = 1.0 + s.jm1;
+    dia = (TH)(mua + rho);
+    c1 = (TH)(-(double)kappa * s.jm1 * J);
+    c2 = (TH)((double)kappa * (2.0 * J - 1.0) * J);
+  }
+  // mu a^(1/3) (1/a - 1) n_i n_k d_JL for the entry ((iJ), (kL))
+  template <typename TH> __device__ __forceinline__ TH director_term(int a, int b) const {
+    const int i = a / 3, J = a % 3, k = b / 3, L = b % 3;
+    return J == L ? (TH)(mua * beta * n[i] * n[k]) : (TH)0;
+  }
+};
 
 // |I + X|_F^2 from X
 template <typename TG> __device__ __forceinline__ TG norm2_ipx(const TG *X) {
@@ -130,18 +231,18 @@ __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 
 constexpr __host__ __device__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Newton solve of the local problem. E: warm start in, minimiser out.
-// Stops when |grad phi| <= gtol (mu + lambda + rho)(1 + |F| + |A|) before a
-// step, or after a full positive-definite Newton step with
+// Newton solve of the local problem at fixed material data M. E: warm start
+// in, minimiser out. Stops when |grad phi| <= gtol (moduli + rho)(1 + |F| + |A|)
+// before a step, or after a full positive-definite Newton step with
 // |dE| <= step_tol max(1, |F|) (which leaves an error of order |dE|^2).
 // Returns the iteration count (>= 0), -1 when the cap or the line search gave
 // up (E keeps the last accepted iterate), -2 when det F <= 0 at the start.
-template <typename TG, typename TH>
-__device__ int nh_newton(TG *E, const TG *A, TG rho, TG mu, TG lam, int maxit, double gtol,
-                         double step_tol) {
-  NHPoint<TG> s;
-  if (!nh_point(E, A, rho, mu, lam, s)) return -2;
-  const double smod = (double)mu + (double)lam + (double)rho;
+template <typename TG, typename TH, typename M>
+__device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
+                      double step_tol) {
+  Point<TG> s;
+  if (!m.point(E, A, rho, s)) return -2;
+  const double smod = m.smod() + (double)rho;
   const double nA = sqrt((double)norm2_ipx(A));
   const double tol_step2 = step_tol * step_tol;
   for (int it = 0; it < maxit; ++it) {
@@ -153,13 +254,15 @@ __device__ int nh_newton(TG *E, const TG *A, TG rho, TG mu, TG lam, int maxit, d
     TH L[45], Gh[9], id[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Gh[k] = (TH)s.G[k];
-    const TH c1 = (TH)((double)mu - (double)lam * s.lnJ), lh = (TH)lam, dia = (TH)(mu + rho);
+    TH dia, c1, c2;
+    m.coeffs(s, rho, dia, c1, c2);
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
       for (int b = 0; b <= a; ++b) {
         const int i = a / 3, J = a % 3, k = b / 3, l = b % 3;
-        TH v = c1 * Gh[3 * k + J] * Gh[3 * i + l] + lh * Gh[a] * Gh[b];
+        TH v = c1 * Gh[3 * k + J] * Gh[3 * i + l] + c2 * Gh[a] * Gh[b] +
+               m.template director_term<TH>(a, b);
         if (a == b) v += dia;
         L[tri(a, b)] = v;
       }
@@ -203,32 +306,33 @@ __device__ int nh_newton(TG *E, const TG *A, TG rho, TG mu, TG lam, int maxit, d
       for (int i = 0; i < 9; ++i) d[i] = -s.g[i];
     }
 
-    double slope = 0.0, nd2 = 0.0;
+    TG slope_t = (TG)0, nd2_t = (TG)0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      slope += (double)s.g[k] * (double)d[k];
-      nd2 += (double)d[k] * (double)d[k];
+      slope_t += s.g[k] * d[k];
+      nd2_t += d[k] * d[k];
     }
+    const double slope = (double)slope_t, nd2 = (double)nd2_t;
     const bool small = -slope <= 1e-12 * smod * (1.0 + nF2);
     // float iterate: a full Newton step already below the step tolerance is
     // taken as it is; the float gradient is at its rounding floor there and
     // no longer decides a line search
     const bool tiny = sizeof(TG) == 4 && pd && nd2 <= tol_step2 * fmax(1.0, nF2);
-    const double phi0 = small ? 0.0 : nh_phi(E, A, rho, mu, lam, s.lnJ);
+    const double phi0 = small ? 0.0 : m.phi(E, A, rho, s);
     double t = 1.0;
     bool acc = false;
-    NHPoint<TG> st;
+    Point<TG> st;
     TG Et[9];
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Et[k] = E[k] + (TG)t * d[k];
-      if (nh_point(Et, A, rho, mu, lam, st)) {
+      if (m.point(Et, A, rho, st)) {
         if (tiny) {
           acc = true;
           break;
         }
         if (!small) {
-          if (nh_phi(Et, A, rho, mu, lam, st.lnJ) <= phi0 + 1e-4 * t * slope) {
+          if (m.phi(Et, A, rho, st) <= phi0 + 1e-4 * t * slope) {
             acc = true;
             break;
           }
@@ -249,6 +353,95 @@ __device__ int nh_newton(TG *E, const TG *A, TG rho, TG mu, TG lam, int maxit, d
     if (pd && t == 1.0 && nd2 <= tol_step2 * fmax(1.0, (double)norm2_ipx(E))) return it + 1;
   }
   return -1;
+}
+
+// ---------------------------------------------------------------------------
+// director: the unit top eigenvector of F F^T (double), cyclic Jacobi on the
+// symmetric 3x3 matrix; sign chosen so that n . n_prev >= 0; when the top
+// eigenvalue is degenerate (relative gap <= 1e-12) every unit vector of the
+// top eigenspace minimises the energy and the projection of n_prev onto it is
+// kept.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void jacobi3(double *B, double *Vv) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Vv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    const double off = B[1] * B[1] + B[2] * B[2] + B[5] * B[5];
+    const double dia = B[0] * B[0] + B[4] * B[4] + B[8] * B[8];
+    if (off <= 1e-34 * dia || off == 0.0) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double bpq = B[3 * p + q];
+      if (bpq == 0.0) continue;
+      const double theta = (B[3 * q + q] - B[3 * p + p]) / (2.0 * bpq);
+      const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double bkp = B[3 * k + p], bkq = B[3 * k + q];
+        B[3 * k + p] = c * bkp - sn * bkq;
+        B[3 * k + q] = sn * bkp + c * bkq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double bpk = B[3 * p + k], bqk = B[3 * q + k];
+        B[3 * p + k] = c * bpk - sn * bqk;
+        B[3 * q + k] = sn * bpk + c * bqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = Vv[3 * k + p], vkq = Vv[3 * k + q];
+        Vv[3 * k + p] = c * vkp - sn * vkq;
+        Vv[3 * k + q] = sn * vkp + c * vkq;
+      }
+    }
+  }
+}
+
+template <typename TG>
+__device__ void director_update(const TG *E, const double *np, double *n) {
+  double F[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+  double B[9], Vv[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+  jacobi3(B, Vv);
+  const double w[3] = {B[0], B[4], B[8]};
+  int o0 = 0, o1 = 1, o2 = 2;  // descending order
+  if (w[o1] > w[o0]) { int t = o0; o0 = o1; o1 = t; }
+  if (w[o2] > w[o0]) { int t = o0; o0 = o2; o2 = t; }
+  if (w[o2] > w[o1]) { int t = o1; o1 = o2; o2 = t; }
+  const double top = w[o0], tie = 1e-12 * fabs(top);
+  double out[3];
+  const int ncl = (top - w[o1] <= tie) ? ((top - w[o2] <= tie) ? 3 : 2) : 1;
+  if (ncl == 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + o0];
+  } else {
+    const int ord[3] = {o0, o1, o2};
+    out[0] = out[1] = out[2] = 0.0;
+    for (int e = 0; e < ncl; ++e) {
+      const int c = ord[e];
+      const double pr = Vv[c] * np[0] + Vv[3 + c] * np[1] + Vv[6 + c] * np[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) out[k] += pr * Vv[3 * k + c];
+    }
+    if (out[0] * out[0] + out[1] * out[1] + out[2] * out[2] < 1e-16)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + o0];
+  }
+  if (out[0] * np[0] + out[1] * np[1] + out[2] * np[2] < 0.0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k] = -out[k];
+  const double inv = 1.0 / sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = out[k] * inv;
 }
 
 }  // namespace admm
