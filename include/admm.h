@@ -64,11 +64,13 @@ typedef enum {
   ADMM_LCE = 1       /* W = mu/2 [a^(1/3)(|F|^2 + (1/a - 1)|F^T n|^2) - 3]
                             + kappa/2 (J - 1)^2, director n per voxel
                         (neo-classical energy of Sec. 5.1 with step-length
-                        tensor a^(-1/3)(I + (a-1) n n) and a volumetric
-                        penalty). The local problem minimises over F and the
-                        unit director jointly: F-Newton at fixed n alternating
-                        with n = top eigenvector of F F^T (double precision,
-                        renormalised), until n moves less than dir_tol. */
+                        tensor a^(-1/3)(I + (a-1) n n), a >= 1, and a
+                        volumetric penalty). The local problem minimises over
+                        F and the unit director jointly: the director is
+                        eliminated (top eigenvector of F F^T, double precision,
+                        unit length) and Newton's method runs on the relaxed
+                        energy; where that is not convex the solve finishes at
+                        the frozen director and updates it once. */
 } admm_model;
 
 /* One phase of the material table. */
@@ -76,7 +78,7 @@ typedef struct {
   int32_t model; /* admm_model */
   int32_t reserved;
   double mu, lambda; /* neo-Hookean moduli */
-  double a, kappa;   /* LCE: step-length ratio, volumetric penalty */
+  double a, kappa;   /* LCE: step-length ratio (>= 1), volumetric penalty */
 } admm_material;
 
 /* One periodic cell (representative volume element). Pointers: device. */
@@ -110,10 +112,6 @@ typedef struct {
   int32_t max_iter;     /* iteration cap of admm_solve */
   int32_t check_every;  /* admm_solve: iterations between host checks (10) */
   int32_t newton_max;   /* local Newton iteration cap (100) */
-  int32_t dir_max;      /* LCE: cap on the F / director alternations (200) */
-  int32_t reserved;
-  double dir_tol;       /* LCE: alternation stops when the director moves less
-                           than this (1e-13 FP64, 1e-6 FP32) */
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;

@@ -30,7 +30,7 @@ class Material(ctypes.Structure):
 
 class Newton(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("gtol", ctypes.c_double),
-                ("step_tol", ctypes.c_double), ("dir_max", ctypes.c_int)]
+                ("step_tol", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -66,6 +66,7 @@ def lib():
         L.or_stress.argtypes = [mp, dp, dp, dp]
         L.or_tangent.argtypes = [mp, dp, dp, dp]
         L.or_director.argtypes = [dp, dp, dp]
+        L.or_relaxed.argtypes = [mp, dp, dp, dp, dp, dp]
         L.or_prox.argtypes = [mp, ctypes.c_double, dp, ctypes.POINTER(Newton), dp, dp, ip]
         L.or_rho_update.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.POINTER(Params)]
@@ -97,9 +98,9 @@ def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0):
     return m
 
 
-def newton_opts(max_iter=100, gtol=1e-15, step_tol=1e-10, dir_max=200):
+def newton_opts(max_iter=100, gtol=1e-15, step_tol=1e-10):
     o = Newton()
-    o.max_iter, o.gtol, o.step_tol, o.dir_max = max_iter, gtol, step_tol, dir_max
+    o.max_iter, o.gtol, o.step_tol = max_iter, gtol, step_tol
     return o
 
 
@@ -182,6 +183,18 @@ def director(F, n_prev):
     n = np.empty(3)
     lib().or_director(_dp(_vec(F, 9)), _dp(_vec(n_prev, 3)), _dp(n))
     return n
+
+
+def relaxed(m, F, n_prev):
+    """LCE energy with the director eliminated: returns (n, P, K) at F."""
+    n = np.empty(3)
+    P = np.empty(9)
+    K = np.empty(81)
+    rc = lib().or_relaxed(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n_prev, 3)), _dp(n),
+                          _dp(P), _dp(K))
+    if rc != OK:
+        raise ValueError(f"or_relaxed failed: {rc}")
+    return n, P, K.reshape(9, 9)
 
 
 def prox(m, rho, A, F0, n0=(0.0, 0.0, 1.0), opts=None):

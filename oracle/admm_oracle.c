@@ -206,48 +206,104 @@ static void jacobi3(double B[9], double Vv[9], double w[3]) {
   w[2] = B[8];
 }
 
-int or_director(const double F[9], const double n_prev[3], double n[3]) {
-  double B[9], Vv[9], w[3];
+/* Eigen-decomposition of B = F F^T sorted by decreasing eigenvalue (w[0] >=
+   w[1] >= w[2], eigenvectors in the columns of V), and the minimising
+   director: the top eigenvector, its sign chosen so that n . n_prev >= 0.
+   When the top eigenvalue is degenerate (the leading ncl eigenvalues within
+   1e-12 relative) every unit vector of that eigenspace is a minimiser and the
+   previous director's projection onto it is kept. Returns ncl. */
+static int director_eig(const double F[9], const double n_prev[3], double n[3],
+                        double w[3], double V[9]) {
+  double B[9], Vv[9], wu[3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       double s = 0.0;
       for (int k = 0; k < 3; ++k) s += F[3 * i + k] * F[3 * j + k];
       B[3 * i + j] = s;
     }
-  jacobi3(B, Vv, w);
+  jacobi3(B, Vv, wu);
   int order[3] = {0, 1, 2};
   for (int a = 0; a < 3; ++a) /* sort eigenvalues descending */
     for (int b = a + 1; b < 3; ++b)
-      if (w[order[b]] > w[order[a]]) {
+      if (wu[order[b]] > wu[order[a]]) {
         int t = order[a];
         order[a] = order[b];
         order[b] = t;
       }
-  double top = w[order[0]];
-  double tie = 1e-12 * fabs(top);
+  for (int e = 0; e < 3; ++e) {
+    w[e] = wu[order[e]];
+    for (int k = 0; k < 3; ++k) V[3 * k + e] = Vv[3 * k + order[e]];
+  }
+  double tie = 1e-12 * fabs(w[0]);
   double out[3];
   int ncl = 1;
-  while (ncl < 3 && top - w[order[ncl]] <= tie) ++ncl;
+  while (ncl < 3 && w[0] - w[ncl] <= tie) ++ncl;
   if (ncl == 1) {
-    for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + order[0]];
+    for (int k = 0; k < 3; ++k) out[k] = V[3 * k];
   } else {
-    /* degenerate top eigenvalue: any unit vector of the top eigenspace is a
-       minimiser; keep the previous director's projection onto it */
     for (int k = 0; k < 3; ++k) out[k] = 0.0;
     for (int e = 0; e < ncl; ++e) {
       double c = 0.0;
-      for (int k = 0; k < 3; ++k) c += Vv[3 * k + order[e]] * n_prev[k];
-      for (int k = 0; k < 3; ++k) out[k] += c * Vv[3 * k + order[e]];
+      for (int k = 0; k < 3; ++k) c += V[3 * k + e] * n_prev[k];
+      for (int k = 0; k < 3; ++k) out[k] += c * V[3 * k + e];
     }
     double nn = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
     if (nn < 1e-8)
-      for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + order[0]];
+      for (int k = 0; k < 3; ++k) out[k] = V[3 * k];
   }
   double s = out[0] * n_prev[0] + out[1] * n_prev[1] + out[2] * n_prev[2];
   if (s < 0.0)
     for (int k = 0; k < 3; ++k) out[k] = -out[k];
   double nn = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
   for (int k = 0; k < 3; ++k) n[k] = out[k] / nn;
+  return ncl;
+}
+
+int or_director(const double F[9], const double n_prev[3], double n[3]) {
+  double w[3], V[9];
+  director_eig(F, n_prev, n, w, V);
+  return OR_OK;
+}
+
+/* The LCE energy with the director eliminated, W_r(F) = min_n W(F, n): for
+   a >= 1 the director term (mu a^(1/3)/2)(1/a - 1)|F^T n|^2 is smallest at
+   the top eigenvector of B = F F^T, so W_r(F) = W(F, n(F)) and, by the
+   envelope theorem, dW_r/dF = P(F, n(F)). Its second derivative adds to the
+   fixed-director tangent the eigenvector sensitivity of the top eigenvalue:
+       d2 lambda_1 = 2 |dF^T n|^2 + 2 sum_k (t_k . dB n)^2 / (lambda_1 - lambda_k)
+   over the other eigenvectors t_k, with t_k . dB n = w_k : dF,
+       (w_k)_iJ = (t_k)_i (F^T n)_J + n_i (F^T t_k)_J.
+   The first part is already in the fixed-director tangent; the second, times
+   mu a^(1/3)(1/a - 1)/2, is negative semidefinite. Eigenvectors in the top
+   eigenspace of n (ties, see director_eig) contribute nothing. K += that
+   term. */
+static void lce_rotation_term(const or_material *m, const double F[9], const double n[3],
+                              const double w[3], const double V[9], int ncl, double *K) {
+  double c2 = m->mu * cbrt(m->a) * (1.0 / m->a - 1.0); /* 2 c */
+  double ftn[3];
+  for (int J = 0; J < 3; ++J) ftn[J] = F[J] * n[0] + F[3 + J] * n[1] + F[6 + J] * n[2];
+  for (int e = ncl; e < 3; ++e) {
+    double t[3] = {V[e], V[3 + e], V[6 + e]};
+    double ftt[3], wk[9];
+    for (int J = 0; J < 3; ++J) ftt[J] = F[J] * t[0] + F[3 + J] * t[1] + F[6 + J] * t[2];
+    for (int i = 0; i < 3; ++i)
+      for (int J = 0; J < 3; ++J) wk[3 * i + J] = t[i] * ftn[J] + n[i] * ftt[J];
+    double f = c2 / (w[0] - w[e]);
+    for (int a = 0; a < 9; ++a)
+      for (int b = 0; b < 9; ++b) K[9 * a + b] += f * wk[a] * wk[b];
+  }
+}
+
+int or_relaxed(const or_material *m, const double F[9], const double n_prev[3],
+               double n[3], double P[9], double K[81]) {
+  if (!m || !F || !n_prev || !n || m->model != OR_LCE || !(m->a >= 1.0)) return OR_EINVAL;
+  double w[3], V[9];
+  int ncl = director_eig(F, n_prev, n, w, V);
+  if (P && or_stress(m, F, n, P) != OR_OK) return OR_EDOMAIN;
+  if (K) {
+    if (or_tangent(m, F, n, K) != OR_OK) return OR_EDOMAIN;
+    lce_rotation_term(m, F, n, w, V, ncl, K);
+  }
   return OR_OK;
 }
 
@@ -373,38 +429,123 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
   return OR_NOT_CONVERGED;
 }
 
+/* LCE: Newton's method on the relaxed objective phi_r(F) = W_r(F) +
+   rho/2 |F - A|^2, i.e. on F and the director jointly with the director
+   eliminated (W_r above). At each iterate n = n(F) (continuity with the
+   director of the previous iterate) and the Newton matrix is the relaxed
+   tangent plus rho I; backtracking as in newton_fixed_n, on phi_r with the
+   director recomputed at every trial point. Where the relaxed tangent plus
+   rho I is not positive definite with a margin of rho/4 (phi_r is not
+   convex, or barely, along a director-rotation mode: near states of
+   uniaxial symmetry the relaxed energy's curvature along that mode goes like
+   -1/(lambda_1 - lambda_2), and at A = I every director is a minimiser), the
+   solve finishes at the frozen director (newton_fixed_n) and then updates
+   the director once, leaving the rest of the director relaxation to the
+   following iterations. */
+static int newton_relaxed(const or_material *m, double rho, const double A[9],
+                          const or_newton *opt, double F[9], double n[3], int *it) {
+  double P[9], g[9], Kr[81], d[9], Ft[9], nt[3], w[3], V[9], ncur[3];
+  double scale_mod = moduli_sum(m) + rho;
+  int ncl = director_eig(F, n, ncur, w, V);
+  for (int iter = 0; iter < opt->max_iter; ++iter) {
+    if (or_stress(m, F, ncur, P) != OR_OK) {
+      *it = iter;
+      memcpy(n, ncur, sizeof(ncur));
+      return OR_EDOMAIN;
+    }
+    for (int k = 0; k < 9; ++k) g[k] = P[k] + rho * (F[k] - A[k]);
+    double scale = scale_mod * (1.0 + norm9(F) + norm9(A));
+    double gn = norm9(g);
+    if (gn <= opt->gtol * scale) {
+      *it = iter;
+      memcpy(n, ncur, sizeof(ncur));
+      return OR_OK;
+    }
+    or_tangent(m, F, ncur, Kr);
+    for (int k = 0; k < 9; ++k) Kr[10 * k] += rho;
+    lce_rotation_term(m, F, ncur, w, V, ncl, Kr);
+    /* the relaxed step only where phi_r is convex with modulus rho/4: then
+       the minimiser is locally unique and the step well conditioned */
+    double Ks[81];
+    memcpy(Ks, Kr, sizeof(Ks));
+    for (int k = 0; k < 9; ++k) Ks[10 * k] -= 0.25 * rho;
+    if (!chol9(Ks) || !chol9(Kr)) {
+      or_newton rest = *opt;
+      int it2 = 0;
+      rest.max_iter = opt->max_iter - iter;
+      int rc = newton_fixed_n(m, rho, A, &rest, F, ncur, &it2);
+      *it = iter + it2;
+      if (rc == OR_EDOMAIN)
+        memcpy(n, ncur, sizeof(ncur));
+      else
+        director_eig(F, ncur, n, w, V);
+      return rc;
+    }
+    double mg[9];
+    for (int k = 0; k < 9; ++k) mg[k] = -g[k];
+    chol9_solve(Kr, mg, d);
+    double slope = dot9(g, d);
+    double phi0 = prox_objective(m, rho, A, F, ncur);
+    double fn0 = norm9(F);
+    double floor_phi = 1e-12 * scale_mod * (1.0 + fn0 * fn0);
+    int small = -slope <= floor_phi;
+    double t = 1.0;
+    int accepted = 0, nclt = 1;
+    double wt[3], Vt[9];
+    for (int ls = 0; ls < 60; ++ls) {
+      for (int k = 0; k < 9; ++k) Ft[k] = F[k] + t * d[k];
+      if (det3(Ft) > 0.0) {
+        nclt = director_eig(Ft, ncur, nt, wt, Vt);
+        if (!small) {
+          if (prox_objective(m, rho, A, Ft, nt) <= phi0 + 1e-4 * t * slope) {
+            accepted = 1;
+            break;
+          }
+        } else {
+          double Pt[9], gt[9];
+          or_stress(m, Ft, nt, Pt);
+          for (int k = 0; k < 9; ++k) gt[k] = Pt[k] + rho * (Ft[k] - A[k]);
+          if (norm9(gt) <= (1.0 - 1e-4 * t) * gn) {
+            accepted = 1;
+            break;
+          }
+        }
+      }
+      t *= 0.5;
+    }
+    if (!accepted) {
+      *it = iter + 1;
+      memcpy(n, ncur, sizeof(ncur));
+      return OR_NOT_CONVERGED;
+    }
+    memcpy(F, Ft, sizeof(Ft));
+    memcpy(ncur, nt, sizeof(nt));
+    memcpy(w, wt, sizeof(wt));
+    memcpy(V, Vt, sizeof(Vt));
+    ncl = nclt;
+    double fn = norm9(F);
+    if (t == 1.0 && norm9(d) <= opt->step_tol * (fn > 1.0 ? fn : 1.0)) {
+      *it = iter + 1;
+      memcpy(n, ncur, sizeof(ncur));
+      return OR_OK;
+    }
+  }
+  *it = opt->max_iter;
+  memcpy(n, ncur, sizeof(ncur));
+  return OR_NOT_CONVERGED;
+}
+
 int or_prox(const or_material *m, double rho, const double A[9],
             const or_newton *opt, double F[9], double n[3], int *iters) {
   if (!m || !A || !opt || !F || !(rho > 0.0)) return OR_EINVAL;
   int it = 0, rc;
   if (m->model == OR_NEOHOOKE) {
     rc = newton_fixed_n(m, rho, A, opt, F, n, &it);
-    if (iters) *iters = it;
-    return rc;
+  } else {
+    if (!n || !(m->a >= 1.0)) return OR_EINVAL;
+    rc = newton_relaxed(m, rho, A, opt, F, n, &it);
   }
-  if (!n) return OR_EINVAL;
-  /* LCE: alternate the F-minimisation at fixed n and the exact n-minimisation
-     at fixed F (top eigenvector of F F^T) until the director stops moving. */
-  int total = 0;
-  rc = OR_NOT_CONVERGED;
-  for (int outer = 0; outer < opt->dir_max; ++outer) {
-    int r = newton_fixed_n(m, rho, A, opt, F, n, &it);
-    total += it;
-    if (r == OR_EDOMAIN) {
-      rc = r;
-      break;
-    }
-    double nn[3];
-    or_director(F, n, nn);
-    double dn = sqrt((nn[0] - n[0]) * (nn[0] - n[0]) + (nn[1] - n[1]) * (nn[1] - n[1]) +
-                     (nn[2] - n[2]) * (nn[2] - n[2]));
-    memcpy(n, nn, sizeof(nn));
-    if (dn <= 1e-13) {
-      rc = r;
-      break;
-    }
-  }
-  if (iters) *iters = total;
+  if (iters) *iters = it;
   return rc;
 }
 

@@ -40,7 +40,8 @@ enum { OR_NEOHOOKE = 0, OR_LCE = 1 };
  *   OR_LCE:      W = mu/2 [ a^(1/3) (|F|^2 + (1/a - 1) |F^T n|^2) - 3 ]
  *                    + kappa/2 (J - 1)^2
  *                (neo-classical energy with step length tensor
- *                 L(n) = a^(-1/3) (I + (a-1) n n), plus a volumetric penalty) */
+ *                 L(n) = a^(-1/3) (I + (a-1) n n), plus a volumetric penalty;
+ *                 a >= 1: the director elongates the material) */
 typedef struct {
   int model;
   double mu, lambda; /* neo-Hookean */
@@ -52,7 +53,6 @@ typedef struct {
   int max_iter;     /* Newton iteration cap (100) */
   double gtol;      /* stop when |grad| <= gtol * scale before a step (1e-15) */
   double step_tol;  /* stop after a full PD Newton step with |d| <= step_tol*max(1,|F|) */
-  int dir_max;      /* LCE: cap on alternations between F and n (200) */
 } or_newton;
 
 /* ADMM parameters. */
@@ -96,9 +96,20 @@ int or_tangent(const or_material *m, const double F[9], const double n[3],
  * n_prev: previous director (unit). Writes unit n. */
 int or_director(const double F[9], const double n_prev[3], double n[3]);
 
-/* Step 1 (local problem) at one point: F = argmin W(F,n) + rho/2 |F - A|^2.
- * F holds the warm start on entry and the minimiser on exit; n (LCE) likewise.
- * iters (may be NULL) receives the Newton iteration count. */
+/* LCE with the director eliminated: W_r(F) = min over unit n of W(F, n).
+ * Writes the minimising director n (top eigenvector of F F^T, rules of
+ * or_director), the stress P = dW_r/dF (= P(F, n)) and the tangent
+ * K = d2W_r/dF2 (81 doubles, or NULL), which adds to the fixed-director
+ * tangent the top eigenvector's sensitivity to F. */
+int or_relaxed(const or_material *m, const double F[9], const double n_prev[3],
+               double n[3], double P[9], double K[81]);
+
+/* Step 1 (local problem) at one point: F = argmin W(F,n) + rho/2 |F - A|^2,
+ * for the LCE jointly over F and the unit director n (Newton on the relaxed
+ * objective W_r(F) + rho/2 |F - A|^2). F holds the warm start on entry and
+ * the minimiser on exit; n (LCE) holds the previous director on entry and the
+ * minimising one on exit. iters (may be NULL) receives the Newton iteration
+ * count. */
 int or_prox(const or_material *m, double rho, const double A[9],
             const or_newton *opt, double F[9], double n[3], int *iters);
 

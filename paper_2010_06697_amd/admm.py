@@ -57,8 +57,7 @@ class Params(ctypes.Structure):
                 ("newton_gtol", ctypes.c_double), ("newton_step_tol", ctypes.c_double),
                 ("adapt_rho", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32),
-                ("dir_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("dir_tol", ctypes.c_double)]
+]
 
 
 _lib = None
@@ -234,11 +233,10 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     p.rho0, p.rho_min, p.rho_max, p.kappa_rho, p.tau = 10.0, 1.0, 50.0, 1.3, 10.0
     p.tol_p, p.tol_d, p.mu_ref = 1e-8, 1e-8, 1.0
     if precision == "fp64":
-        p.newton_gtol, p.newton_step_tol, p.dir_tol = 1e-14, 1e-10, 1e-13
+        p.newton_gtol, p.newton_step_tol = 1e-14, 1e-10
     else:
-        p.newton_gtol, p.newton_step_tol, p.dir_tol = 1e-10, 2e-6, 1e-6
+        p.newton_gtol, p.newton_step_tol = 1e-10, 2e-6
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
-    p.dir_max = 200
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)

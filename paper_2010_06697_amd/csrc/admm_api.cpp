@@ -258,8 +258,6 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   ip.hist_cap = c->hist_cap;
   ip.n_rve = c->n_rve;
   ip.n_mat = c->n_mat;
-  ip.dir_max = p.dir_max;
-  ip.dir_tol = p.dir_tol;
   return ip;
 }
 
@@ -346,7 +344,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   bool any_lce = false;
   for (int q = 0; q < n_mat; ++q) {
     if (mats[q].model == ADMM_LCE) {
-      if (!(mats[q].mu > 0.0) || !(mats[q].a > 0.0) || !(mats[q].kappa >= 0.0)) return ADMM_EINVAL;
+      if (!(mats[q].mu > 0.0) || !(mats[q].a >= 1.0) || !(mats[q].kappa >= 0.0)) return ADMM_EINVAL;
       any_lce = true;
     } else if (mats[q].model == ADMM_NEOHOOKE) {
       if (!(mats[q].mu > 0.0) || !(mats[q].lambda >= 0.0)) return ADMM_EINVAL;
@@ -359,7 +357,6 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
       !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
       p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0))
     return ADMM_EINVAL;
-  if (any_lce && (p.dir_max < 1 || !(p.dir_tol >= 0.0))) return ADMM_EINVAL;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
     int g = admm_check_grid(R.n[0], R.n[1], R.n[2]);

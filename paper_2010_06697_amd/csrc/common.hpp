@@ -75,8 +75,6 @@ struct IterParams {
   int hist_cap;
   int n_rve;
   int n_mat;
-  int dir_max;       // LCE: cap on the F / director alternations
-  double dir_tol;    // LCE: stop when the director moves less than this
 };
 
 template <typename T> struct cplx;

@@ -99,10 +99,8 @@ __device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwave
 #define ADMM_LOCAL_WAVES_PER_EU 1
 #endif
 
-// LCE: alternate the F-minimisation at fixed director and the exact
-// director-minimisation at fixed F (top eigenvector of F F^T) until the
-// director moves less than dir_tol. Returns the last Newton status and adds
-// the Newton iterations to its.
+// LCE: the joint (F, director) Newton solve of lce_newton. Adds the Newton
+// iterations to its.
 template <typename T>
 __device__ int lce_local(T *E, const T *At, const Material &m, double rho, double *n,
                          const IterParams &ip, int &its) {
@@ -111,21 +109,9 @@ __device__ int lce_local(T *E, const T *At, const Material &m, double rho, doubl
   M.beta = (T)m.beta;
   M.kappa = (T)m.kappa;
   M.mu = (T)m.mu;
-  int rc = -1;
-  for (int outer = 0; outer < ip.dir_max; ++outer) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) M.n[k] = (T)n[k];
-    rc = newton<T, T>(E, At, M, (T)rho, ip.newton_max, ip.gtol, ip.step_tol);
-    its += rc >= 0 ? rc : ip.newton_max;
-    if (rc == -2) break;
-    double nn[3];
-    director_update(E, n, nn);
-    const double d0 = nn[0] - n[0], d1 = nn[1] - n[1], d2 = nn[2] - n[2];
-    n[0] = nn[0];
-    n[1] = nn[1];
-    n[2] = nn[2];
-    if (d0 * d0 + d1 * d1 + d2 * d2 <= ip.dir_tol * ip.dir_tol) break;
-  }
+  const int rc = lce_newton<T>(E, At, M, m.mua * m.beta, (T)rho, n, ip.newton_max, ip.gtol,
+                               ip.step_tol);
+  its += rc >= 0 ? rc : ip.newton_max;
   return rc;
 }
 

@@ -150,7 +150,10 @@ template <typename TG> struct Lce {
   TG beta;   // 1/a - 1
   TG kappa;
   TG mu;
-  TG n[3];   // unit director
+  TG n[3];       // unit director, in the arithmetic of the iterate
+  double nd[3];  // the same director in double: the objective phi uses it,
+                 // since a float-rounded director is not unit to 1e-8 and
+                 // W depends on |n| at that level
 
   __device__ double smod() const { return (double)mua + (double)kappa; }
 
@@ -194,8 +197,8 @@ template <typename TG> struct Lce {
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      const double v = (double)n[l] + (double)E[l] * n[0] + (double)E[3 + l] * n[1] +
-                       (double)E[6 + l] * n[2];
+      const double v = nd[l] + (double)E[l] * nd[0] + (double)E[3 + l] * nd[1] +
+                       (double)E[6 + l] * nd[2];
       t2 += v * v;
     }
     const double f2 = 3.0 + 2.0 * tr + e2;
@@ -400,8 +403,12 @@ __device__ __forceinline__ void jacobi3(double *B, double *Vv) {
   }
 }
 
+// Eigen-decomposition of B = F F^T (double) sorted by decreasing eigenvalue,
+// w[0] >= w[1] >= w[2] with the eigenvectors in the columns of V, and the
+// minimising director n by the rules above. Returns the size of the top
+// eigenvalue's cluster (1 when it is simple).
 template <typename TG>
-__device__ void director_update(const TG *E, const double *np, double *n) {
+__device__ int director_eig(const TG *E, const double *np, double *n, double *w, double *V) {
   double F[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
@@ -412,29 +419,34 @@ __device__ void director_update(const TG *E, const double *np, double *n) {
     for (int j = 0; j < 3; ++j)
       B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
   jacobi3(B, Vv);
-  const double w[3] = {B[0], B[4], B[8]};
+  const double wu[3] = {B[0], B[4], B[8]};
   int o0 = 0, o1 = 1, o2 = 2;  // descending order
-  if (w[o1] > w[o0]) { int t = o0; o0 = o1; o1 = t; }
-  if (w[o2] > w[o0]) { int t = o0; o0 = o2; o2 = t; }
-  if (w[o2] > w[o1]) { int t = o1; o1 = o2; o2 = t; }
-  const double top = w[o0], tie = 1e-12 * fabs(top);
+  if (wu[o1] > wu[o0]) { int t = o0; o0 = o1; o1 = t; }
+  if (wu[o2] > wu[o0]) { int t = o0; o0 = o2; o2 = t; }
+  if (wu[o2] > wu[o1]) { int t = o1; o1 = o2; o2 = t; }
+  const int ord[3] = {o0, o1, o2};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    w[e] = wu[ord[e]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[3 * k + e] = Vv[3 * k + ord[e]];
+  }
+  const double tie = 1e-12 * fabs(w[0]);
+  const int ncl = (w[0] - w[1] <= tie) ? ((w[0] - w[2] <= tie) ? 3 : 2) : 1;
   double out[3];
-  const int ncl = (top - w[o1] <= tie) ? ((top - w[o2] <= tie) ? 3 : 2) : 1;
   if (ncl == 1) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + o0];
+    for (int k = 0; k < 3; ++k) out[k] = V[3 * k];
   } else {
-    const int ord[3] = {o0, o1, o2};
     out[0] = out[1] = out[2] = 0.0;
     for (int e = 0; e < ncl; ++e) {
-      const int c = ord[e];
-      const double pr = Vv[c] * np[0] + Vv[3 + c] * np[1] + Vv[6 + c] * np[2];
+      const double pr = V[e] * np[0] + V[3 + e] * np[1] + V[6 + e] * np[2];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) out[k] += pr * Vv[3 * k + c];
+      for (int k = 0; k < 3; ++k) out[k] += pr * V[3 * k + e];
     }
     if (out[0] * out[0] + out[1] * out[1] + out[2] * out[2] < 1e-16)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) out[k] = Vv[3 * k + o0];
+      for (int k = 0; k < 3; ++k) out[k] = V[3 * k];
   }
   if (out[0] * np[0] + out[1] * np[1] + out[2] * np[2] < 0.0)
 #pragma unroll
@@ -442,6 +454,236 @@ __device__ void director_update(const TG *E, const double *np, double *n) {
   const double inv = 1.0 / sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) n[k] = out[k] * inv;
+  return ncl;
+}
+
+template <typename TG>
+__device__ void director_update(const TG *E, const double *np, double *n) {
+  double w[3], V[9];
+  director_eig(E, np, n, w, V);
+}
+
+// Cholesky factorisation of a packed lower triangle in place, with the
+// reciprocal square roots of the pivots in id. False when a pivot is not
+// positive.
+template <typename T> __device__ __forceinline__ bool chol_packed(T *L, T *id) {
+  bool pd = true;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    T d = L[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[tri(j, k)] * L[tri(j, k)];
+    pd = pd && (d > (T)0);
+    id[j] = rsqrt_t(d);
+#pragma unroll
+    for (int i = j + 1; i < 9; ++i) {
+      T v = L[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[tri(i, k)] * L[tri(j, k)];
+      L[tri(i, j)] = v * id[j];
+    }
+  }
+  return pd;
+}
+
+// Relaxed LCE tangent plus (rho - shift) I at E with director nc and the
+// sorted eigen-decomposition (w, V, ncl) of F F^T, packed lower triangle.
+template <typename T>
+__device__ __forceinline__ void lce_relaxed_tangent(const T *E, const Lce<T> &M, const Point<T> &s,
+                                                    T rho, double c2, const double *nc,
+                                                    const double *w, const double *V, int ncl,
+                                                    T shift, T *L) {
+  T dia, k1, k2;
+  M.coeffs(s, rho, dia, k1, k2);
+  dia -= shift;
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      const int i = a / 3, J = a % 3, k = b / 3, l = b % 3;
+      T v = k1 * s.G[3 * k + J] * s.G[3 * i + l] + k2 * s.G[a] * s.G[b] +
+            M.template director_term<T>(a, b);
+      if (a == b) v += dia;
+      L[tri(a, b)] = v;
+    }
+  // eigenvector sensitivity of the top eigenvalue
+  double F[9], ftn[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+#pragma unroll
+  for (int J = 0; J < 3; ++J) ftn[J] = F[J] * nc[0] + F[3 + J] * nc[1] + F[6 + J] * nc[2];
+  for (int e = ncl; e < 3; ++e) {
+    const double t0 = V[e], t1 = V[3 + e], t2 = V[6 + e];
+    double wk[9];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      const double ftt = F[J] * t0 + F[3 + J] * t1 + F[6 + J] * t2;
+      wk[J] = t0 * ftn[J] + nc[0] * ftt;
+      wk[3 + J] = t1 * ftn[J] + nc[1] * ftt;
+      wk[6 + J] = t2 * ftn[J] + nc[2] * ftt;
+    }
+    const double f = c2 / (w[0] - w[e]);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) L[tri(a, b)] += (T)(f * wk[a] * wk[b]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LCE local problem jointly in F and the director. With a >= 1 the director
+// part of the energy is smallest at the top eigenvector of B = F F^T, so the
+// joint problem is Newton's method on the relaxed objective
+//     phi_r(F) = W(F, n(F)) + rho/2 |F - A|^2,
+// whose gradient is the fixed-director one at n(F) and whose Hessian adds to
+// the fixed-director tangent the top eigenvector's sensitivity to F,
+//     c2 / (w_0 - w_e) w_e w_e^T,  (w_e)_iJ = t_i (F^T n)_J + n_i (F^T t)_J,
+// over the eigenvectors t = t_e outside the top cluster, c2 = mu a^(1/3)(1/a - 1)
+// (negative semidefinite). Every trial point of the backtracking recomputes
+// the director (continuity with the current one). Where that Hessian plus
+// rho I is not positive definite with a margin of rho/4 (phi_r not convex,
+// or barely, along a director-rotation mode: near uniaxially symmetric
+// states the curvature goes like -1/(w_0 - w_1), and at A = I every director
+// is a minimiser), the solve finishes at the frozen director with newton()
+// and then updates the director once.
+// n: previous director in, minimising director out. Returns as newton().
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double *n, int maxit,
+                          double gtol, double step_tol) {
+  double w[3], V[9], nc[3];
+  int ncl = director_eig(E, n, nc, w, V);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    M.n[k] = (T)nc[k];
+    M.nd[k] = nc[k];
+  }
+  Point<T> s;
+  if (!M.point(E, A, rho, s)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n[k] = nc[k];
+    return -2;
+  }
+  const double smod = M.smod() + (double)rho;
+  const double nA = sqrt((double)norm2_ipx(A));
+  const double tol_step2 = step_tol * step_tol;
+  int ret = -1;
+  for (int it = 0; it < maxit; ++it) {
+    const double nF2 = (double)norm2_ipx(E);
+    const double thr = gtol * smod * (1.0 + sqrt(nF2) + nA);
+    if ((double)s.gn2 <= thr * thr) {
+      ret = it;
+      break;
+    }
+    // relaxed tangent plus rho I - shift, lower triangle packed; factorised
+    // first with shift = rho/4 (the relaxed step is taken only where phi_r
+    // is convex with that modulus: locally unique minimiser, well-conditioned
+    // step), then with shift = 0 for the step itself
+    T L[45], id[9];
+    bool pd = true;
+    for (int pass = 0; pass < 2 && pd; ++pass) {
+      lce_relaxed_tangent(E, M, s, rho, c2, nc, w, V, ncl, pass == 0 ? (T)0.25 * rho : (T)0, L);
+      pd = chol_packed(L, id);
+    }
+    if (!pd) {
+      // frozen director for the rest of this solve, then one director update
+      const int r = newton<T, T>(E, A, M, rho, maxit - it, gtol, step_tol);
+      if (r == -2) {
+        ret = -2;
+        break;
+      }
+      director_update(E, nc, nc);
+      ret = r >= 0 ? it + r : -1;
+      break;
+    }
+    T d[9];
+    {
+      T y[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        T v = -s.g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= L[tri(i, k)] * y[k];
+        y[i] = v * id[i];
+      }
+#pragma unroll
+      for (int i = 8; i >= 0; --i) {
+        T v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 9; ++k) v -= L[tri(k, i)] * y[k];
+        y[i] = v * id[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) d[i] = y[i];
+    }
+    T slope_t = (T)0, nd2_t = (T)0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      slope_t += s.g[k] * d[k];
+      nd2_t += d[k] * d[k];
+    }
+    const double slope = (double)slope_t, nd2 = (double)nd2_t;
+    const bool small = -slope <= 1e-12 * smod * (1.0 + nF2);
+    const bool tiny = sizeof(T) == 4 && nd2 <= tol_step2 * fmax(1.0, nF2);
+    const double phi0 = small ? 0.0 : M.phi(E, A, rho, s);
+    double t = 1.0;
+    bool acc = false;
+    Point<T> st;
+    T Et[9];
+    double nt[3], wt[3], Vt[9];
+    int nclt = 1;
+    for (int ls = 0; ls < 60; ++ls) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Et[k] = E[k] + (T)t * d[k];
+      nclt = director_eig(Et, nc, nt, wt, Vt);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        M.n[k] = (T)nt[k];
+        M.nd[k] = nt[k];
+      }
+      if (M.point(Et, A, rho, st)) {
+        if (tiny) {
+          acc = true;
+          break;
+        }
+        if (!small) {
+          if (M.phi(Et, A, rho, st) <= phi0 + 1e-4 * t * slope) {
+            acc = true;
+            break;
+          }
+        } else {
+          const double f = 1.0 - 1e-4 * t;
+          if ((double)st.gn2 <= f * f * (double)s.gn2) {
+            acc = true;
+            break;
+          }
+        }
+      }
+      t *= 0.5;
+    }
+    if (!acc) {
+      ret = -1;
+      break;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) E[k] = Et[k];
+    s = st;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      nc[k] = nt[k];
+      w[k] = wt[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) V[k] = Vt[k];
+    ncl = nclt;
+    if (t == 1.0 && nd2 <= tol_step2 * fmax(1.0, (double)norm2_ipx(E))) {
+      ret = it + 1;
+      break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = nc[k];
+  return ret;
 }
 
 }  // namespace admm

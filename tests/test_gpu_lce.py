@@ -42,10 +42,10 @@ def lce_solver(phase, n0, Fbar, precision, **kw):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("stretched", [True, False])
 def test_lce_local_step_matches_oracle(precision, stretched):
-    """Per-voxel local solves. With a clear stretch the top eigenvalue of
-    F F^T is well separated and the F / director alternation converges on
-    both sides; with a random small distortion it contracts slowly and may
-    stop at its cap, the same alternation on both sides."""
+    """Per-voxel joint (F, director) local solves from random states: with a
+    clear stretch (top eigenvalue of F F^T well separated, the relaxed
+    problem convex) and with a random small distortion (near-degenerate
+    eigenvalues, where the solve may finish at a frozen director)."""
     shape = (6, 8, 12)
     say("lce local", precision, "stretched" if stretched else "random")
     phase = np.zeros(shape, np.uint8)
@@ -59,7 +59,7 @@ def test_lce_local_step_matches_oracle(precision, stretched):
     else:
         Fbar = M.uniaxial_lce(1.03)
     rho = 10.0
-    s = lce_solver(phase, n0, Fbar, precision, rho0=rho, dir_max=400)
+    s = lce_solver(phase, n0, Fbar, precision, rho0=rho)
     s.set_state(0, u=u, F=F, Lambda=L)
     st0 = s.state(0)
     s.local_step()
@@ -74,63 +74,78 @@ def test_lce_local_step_matches_oracle(precision, stretched):
         sl = (slice(None),) + x
         nstart = st0["director"][sl] / np.linalg.norm(st0["director"][sl])
         Fx, nx, _, rc = O.prox(m, rho, A[sl], st0["F"][sl], nstart,
-                               opts=O.newton_opts(dir_max=400, **NEWTON64))
+                               opts=O.newton_opts(**NEWTON64))
         capped += rc != O.OK
         errF = max(errF, np.max(np.abs(out["F"][sl] - Fx)))
         errn = max(errn, np.max(np.abs(out["director"][sl] - nx)))
     say("  max |dF|", errF, "max |dn|", errn, "oracle capped", capped)
-    if stretched:
-        assert capped == 0
+    assert capped == 0
     if precision == "fp64":
         assert errF <= 1e-10 and errn <= 1e-9
     else:
         assert errF <= 5e-5 and errn <= (2e-3 if stretched else 5e-2)
 
 
-@pytest.mark.parametrize("stretch", [1.0, 1.2])
-def test_lce_iterations_match_oracle_fp64(stretch):
-    """Whole iterations on a 16^3 polydomain. At stretch 1.0 (relaxation of
-    the grains' directors at zero macroscopic strain) both sides run the same
-    capped alternations; at 1.2 the top eigenvalue of F F^T is well separated
-    and every local problem is convex. Stretches just above 1 (about
-    1.01-1.05) are left out: there the relaxed energy's curvature along the
-    director-rotation mode scales like -1/(l1 - l2), the local problems have
-    saddles, and which side of a saddle a voxel leaves by is decided by
-    rounding."""
+def iteration_case(name):
+    """16^3 polydomain of 6 grains: relaxation of the grains' directors at
+    zero macroscopic strain ('relax'); a small uniaxial stretch 1.02 where
+    the aligned state is a saddle of the relaxed local problems and the
+    solves finish at a frozen director ('small'); and a stretch 1.2 of the
+    polydomain with a stiff neo-Hookean spherical inclusion (radius 4), where
+    the LCE local problems are convex and the field is not homogeneous
+    ('composite')."""
     phase, n0 = polydomain(16, 6, seed=7)
-    Fbar = M.uniaxial_lce(stretch)
-    say("lce iterations", stretch)
-    n_iter, rho = 4, 10.0
-    s = lce_solver(phase, n0, Fbar, "fp64", rho0=rho, mu_ref=1.0)
+    mats = list(LCE)
+    if name == "relax":
+        Fbar = M.uniaxial_lce(1.0)
+    elif name == "small":
+        Fbar = M.uniaxial_lce(1.02)
+    else:
+        Fbar = M.uniaxial_lce(1.2)
+        z, y, x = np.indices(phase.shape)
+        phase[(x - 7.5) ** 2 + (y - 7.5) ** 2 + (z - 7.5) ** 2 <= 16.0] = 1
+        mats.append(M.neohooke(10.0, 100.0))
+    return phase, n0, Fbar, mats
+
+
+def run_both(name, precision, n_iter, rho=10.0):
+    phase, n0, Fbar, mats = iteration_case(name)
+    p = admm.default_params(precision, rho0=rho, mu_ref=1.0)
+    s = admm.Solver([phase], mats, [Fbar], p, precision=precision, directors=[n0])
     rc, rp, rd, _ = s.step(n_iter)
     st = s.state(0)
-    P, Lm = s.homogenized_stress(0)
-    s.close()
-    u, F, L = O.initial_state(phase.shape)
-    n = n0.copy()
-    p = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=1.0, newton=O.newton_opts(**NEWTON64))
-    O.admm_run(phase, omats(LCE), Fbar.ravel(), p, u, F, L, rho, director_field=n)
-    Po = O.mean_stress(phase, omats(LCE), F, director_field=n)
-    say("  rel u F L n P", rel(st["u"], u), rel(st["F"], F), rel(st["Lambda"], L),
-        rel(st["director"], n), rel(P, Po))
-    assert rc == admm.OK
-    assert rel(st["u"], u) <= 1e-10 and rel(st["F"], F) <= 1e-10
-    assert rel(st["Lambda"], L) <= 1e-10 and rel(st["director"], n) <= 1e-9
-    assert rel(P, Po) <= 1e-10
-
-
-def test_lce_fp32_homogenized_stress_within_1e5():
-    phase, n0 = polydomain(16, 6, seed=7)
-    Fbar = M.uniaxial_lce(1.2)
-    n_iter, rho = 6, 10.0
-    s = lce_solver(phase, n0, Fbar, "fp32", rho0=rho, mu_ref=1.0)
-    s.step(n_iter)
     P, _ = s.homogenized_stress(0)
     s.close()
     u, F, L = O.initial_state(phase.shape)
     n = n0.copy()
-    p = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=1.0, newton=O.newton_opts(**NEWTON64))
-    O.admm_run(phase, omats(LCE), Fbar.ravel(), p, u, F, L, rho, director_field=n)
-    Po = O.mean_stress(phase, omats(LCE), F, director_field=n)
-    say("lce fp32 rel P", rel(P, Po))
-    assert rel(P, Po) <= 1e-5
+    op = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=1.0, newton=O.newton_opts(**NEWTON64))
+    O.admm_run(phase, omats(mats), Fbar.ravel(), op, u, F, L, rho, director_field=n)
+    Po = O.mean_stress(phase, omats(mats), F, director_field=n)
+    return rc, st, P, dict(u=u, F=F, Lambda=L, director=n), Po
+
+
+@pytest.mark.parametrize("name", ["relax", "small", "composite"])
+def test_lce_iterations_match_oracle_fp64(name):
+    """Whole iterations (Steps 1-4) on the cases of iteration_case. Near
+    saddles of the local problems differences of rounding grow by a bounded
+    factor per iteration, so the comparison runs 4 iterations."""
+    say("lce iterations", name)
+    rc, st, P, o, Po = run_both(name, "fp64", 4)
+    errs = {k: rel(st[k], o[k]) for k in ("u", "F", "Lambda", "director")}
+    say("  rel", errs, "P", rel(P, Po), "max|u|", np.abs(o["u"]).max())
+    assert rc == admm.OK
+    assert errs["u"] <= 1e-10 and errs["F"] <= 1e-10 and errs["Lambda"] <= 1e-10
+    assert errs["director"] <= 1e-9
+    assert rel(P, Po) <= 1e-10
+
+
+@pytest.mark.parametrize("name,tol", [("composite", 1e-5), ("small", 1e-4)])
+def test_lce_fp32_homogenized_stress(name, tol):
+    """Float form against the double oracle after 6 iterations. 1e-5 where
+    the LCE local problems are convex; near the saddles of the small-stretch
+    case the director's sensitivity to F goes like 1/(w_0 - w_1) (about 1/0.06
+    here), which multiplies the float rounding, and the stated bound is
+    1e-4."""
+    rc, st, P, o, Po = run_both(name, "fp32", 6)
+    say("lce fp32", name, "rel P", rel(P, Po))
+    assert rel(P, Po) <= tol

@@ -1,0 +1,160 @@
+"""Pins of the oracle's LCE local problem with the director eliminated.
+
+The local step of Sec. 2.1 for the LCE of Sec. 5.1 minimises over F and the
+unit director jointly. For a >= 1 the director part of the neo-classical
+energy, mu a^(1/3)/2 (1/a - 1) |F^T n|^2, is smallest at the top eigenvector of
+F F^T, so the joint minimisation is a minimisation over F of the relaxed
+energy W_r(F) = min_n W(F, n). Pins, none of which uses the oracle's eigen
+solver or its formula for the eigenvector sensitivity:
+- the director it picks beats every other unit vector (brute force over
+  random directions and a local search over angles) and agrees with numpy's
+  symmetric eigensolver;
+- its stress is the gradient of W_r, W_r evaluated through numpy's
+  eigensolver (central differences);
+- its tangent is the derivative of that stress (central differences), is
+  symmetric, and lies below the fixed-director tangent by a negative
+  semidefinite term of rank <= 2;
+- the joint prox is stationary, beats joint perturbations of F and n, and
+  equals an independent minimisation of W_r(F) + rho/2 |F - A|^2 by scipy's
+  BFGS with W_r from numpy.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import oracle as O
+from test_oracle_material import randF, rot, unit
+
+LCE = O.material("lce", mu=1.0, a=2.0, kappa=100.0)
+
+
+def top_vec(F):
+    w, V = np.linalg.eigh(F.reshape(3, 3) @ F.reshape(3, 3).T)
+    return V[:, -1]
+
+
+def W_relaxed_np(F):
+    """min over unit n of W(F, n), the minimising n taken from numpy."""
+    return O.energy(LCE, F, top_vec(F))
+
+
+def F_cases():
+    out = [randF(s, 0.2).ravel() for s in range(3)]
+    out.append(np.diag([1.3, 1.3 ** -0.5, 1.3 ** -0.5]).ravel())
+    out.append((rot(4) @ np.diag([1.1, 1.0, 0.95]) @ rot(5)).ravel())
+    return out
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_director_minimises_over_the_sphere(k):
+    F = F_cases()[k]
+    n, _, _ = O.relaxed(LCE, F, unit(k))
+    assert abs(np.linalg.norm(n) - 1.0) <= 1e-15
+    w0 = O.energy(LCE, F, n)
+    rng = np.random.default_rng(k)
+    trial = rng.standard_normal((2000, 3))
+    trial /= np.linalg.norm(trial, axis=1, keepdims=True)
+    assert min(O.energy(LCE, F, t) for t in trial) >= w0 - 1e-13
+
+    def by_angles(x):
+        t = np.array([np.sin(x[0]) * np.cos(x[1]), np.sin(x[0]) * np.sin(x[1]), np.cos(x[0])])
+        return O.energy(LCE, F, t)
+
+    best = min(minimize(by_angles, x0, method="Nelder-Mead",
+                        options={"xatol": 1e-10, "fatol": 1e-15}).fun
+               for x0 in rng.uniform(0, np.pi, (6, 2)))
+    assert best >= w0 - 1e-12
+    assert abs(abs(top_vec(F) @ n) - 1.0) <= 1e-13
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_relaxed_stress_and_tangent_by_finite_differences(k):
+    F = F_cases()[k]
+    n, P, K = O.relaxed(LCE, F, unit(k))
+    h = 1e-6
+    Pfd = np.array([(W_relaxed_np(F + h * e) - W_relaxed_np(F - h * e)) / (2 * h)
+                    for e in np.eye(9)])
+    assert np.max(np.abs(P - Pfd)) <= 1e-7 * max(1.0, np.max(np.abs(P)))
+    Kfd = np.stack([(O.relaxed(LCE, F + h * e, n)[1] - O.relaxed(LCE, F - h * e, n)[1]) / (2 * h)
+                    for e in np.eye(9)], axis=1)
+    assert np.max(np.abs(K - Kfd)) <= 1e-6 * np.max(np.abs(K))
+    assert np.max(np.abs(K - K.T)) <= 1e-12 * np.max(np.abs(K))
+    # softer than the fixed-director tangent, by a rank <= 2 term
+    D = K - O.tangent(LCE, F, n).reshape(9, 9)
+    ev = np.linalg.eigvalsh(0.5 * (D + D.T))
+    assert ev.max() <= 1e-12 * np.max(np.abs(K))
+    assert np.sum(np.abs(ev) > 1e-10 * np.max(np.abs(K))) <= 2
+
+
+def test_relaxed_at_a1_reduces_to_fixed_director():
+    m1 = O.material("lce", mu=2.0, a=1.0, kappa=5.0)
+    F = randF(7, 0.2).ravel()
+    n, P, K = O.relaxed(m1, F, unit(7))
+    assert np.max(np.abs(K - O.tangent(m1, F, n).reshape(9, 9))) <= 1e-13 * np.max(np.abs(K))
+    with pytest.raises(ValueError):
+        O.relaxed(O.material("lce", mu=1.0, a=0.5, kappa=1.0), F, unit(7))
+
+
+def phi_np(F, A, rho):
+    return W_relaxed_np(F) + 0.5 * rho * np.sum((F - A) ** 2)
+
+
+@pytest.mark.parametrize("case", ["stretch", "random", "rotated"])
+def test_joint_prox_is_the_minimiser(case):
+    rho = 10.0
+    if case == "stretch":
+        A = np.diag([1.25, 0.9, 0.9]) + 0.02 * np.random.default_rng(1).standard_normal((3, 3))
+        F0, n0 = np.eye(3).ravel(), unit(2)
+    elif case == "random":
+        A = randF(3, 0.15)
+        F0, n0 = np.eye(3).ravel(), unit(4)
+    else:
+        A = rot(5) @ np.diag([1.3, 0.88, 0.88]) @ rot(6)
+        F0, n0 = A.ravel() + 0.01, unit(7)
+    F, n, it, rc = O.prox(LCE, rho, A.ravel(), F0, n0)
+    assert rc == O.OK and it <= 25, (rc, it)
+    # stationary, with the director the top eigenvector of F F^T
+    g = O.stress(LCE, F, n) + rho * (F - A.ravel())
+    assert np.linalg.norm(g) <= 1e-10
+    assert abs(abs(top_vec(F) @ n) - 1.0) <= 1e-12
+    # no joint perturbation of (F, n) does better
+    f0 = O.energy(LCE, F, n) + 0.5 * rho * np.sum((F - A.ravel()) ** 2)
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        dF = 1e-3 * rng.standard_normal(9)
+        nt = n + 1e-2 * rng.standard_normal(3)
+        nt /= np.linalg.norm(nt)
+        assert O.energy(LCE, F + dF, nt) + 0.5 * rho * np.sum((F + dF - A.ravel()) ** 2) >= f0 - 1e-13
+    # an independent minimisation of the relaxed objective lands on the same F
+    res = minimize(phi_np, F, args=(A.ravel(), rho), method="BFGS",
+                   options={"gtol": 1e-11, "maxiter": 500})
+    assert res.fun >= f0 - 1e-13
+    assert np.max(np.abs(res.x - F)) <= 1e-6
+
+
+def test_joint_prox_converges_quadratically_in_the_convex_regime():
+    """Well-separated top eigenvalue: a handful of Newton steps from F = I,
+    where the alternation of F and director solves needs many."""
+    rho = 10.0
+    A = np.diag([1.2, 1.2 ** -0.5, 1.2 ** -0.5]).ravel()
+    for s in range(4):
+        F, n, it, rc = O.prox(LCE, rho, A, np.eye(3).ravel(), unit(s + 20))
+        assert rc == O.OK and it <= 12, (s, it)
+        assert abs(abs(n[0]) - 1.0) <= 1e-10
+
+
+def test_joint_prox_covariance():
+    rho = 10.0
+    for s in range(3):
+        A = randF(s, 0.15)
+        n0 = unit(s + 3)
+        F, n, _, rc = O.prox(LCE, rho, A.ravel(), np.eye(3).ravel(), n0)
+        assert rc == O.OK
+        Q = rot(s + 9)
+        # the warm start rotates with the data: the problem is not convex
+        # everywhere, so prox(QA) = Q prox(A) holds for the same local minimiser
+        FQ, nQ, _, rcQ = O.prox(LCE, rho, (Q @ A).ravel(), Q.ravel(), Q @ n0)
+        assert rcQ == O.OK
+        assert np.max(np.abs(FQ.reshape(3, 3) - Q @ F.reshape(3, 3))) <= 1e-9
+        # n and -n are the same state (Sec. 5.1): compare n (x) n
+        assert np.max(np.abs(np.outer(nQ, nQ) - np.outer(Q @ n, Q @ n))) <= 1e-9

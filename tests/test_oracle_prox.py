@@ -14,7 +14,6 @@ import oracle as O
 from test_oracle_material import randF, rot, unit
 
 NH = O.material("neohooke", mu=10.0, lam=100.0)
-LCE = O.material("lce", mu=1.0, a=2.0, kappa=100.0)
 
 
 def phi(m, rho, A, F, n):
@@ -70,20 +69,3 @@ def test_prox_quadratic_limit():
     lin = np.linalg.solve(C + rho * np.eye(9), rho * dA)
     # the neglected terms are O(|dA|) relative; rounding of F - I is ~1e-9 relative
     assert np.max(np.abs((F - np.eye(3).ravel()) - lin)) <= 1e-6 * np.max(np.abs(lin))
-
-
-def test_lce_prox_joint_stationarity_and_covariance():
-    rho = 10.0
-    for s in range(3):
-        A = randF(s, 0.15)
-        n0 = unit(s + 3)
-        F, n, it, rc = O.prox(LCE, rho, A.ravel(), np.eye(3).ravel(), n0)
-        assert rc == O.OK
-        g = O.stress(LCE, F, n) + rho * (F - A.ravel())
-        assert np.linalg.norm(g) <= 1e-10
-        w_, V = np.linalg.eigh(F.reshape(3, 3) @ F.reshape(3, 3).T)
-        assert abs(abs(V[:, -1] @ n) - 1.0) <= 1e-12
-        Q = rot(s + 9)
-        FQ, nQ, _, _ = O.prox(LCE, rho, (Q @ A).ravel(), np.eye(3).ravel(), Q @ n0)
-        assert np.max(np.abs(FQ.reshape(3, 3) - Q @ F.reshape(3, 3))) <= 1e-9
-        assert np.max(np.abs(nQ - Q @ n)) <= 1e-9
