@@ -10,8 +10,10 @@ every field resident in HBM before it starts.
 
 Also reported on the same line: the all-double form at 256^3, the 128-cell
 batch (edges 32..96, one load step each to tol 1e-6) as cell solves/s, the
-per-kernel times from hipEvents on the library's stream, the roofline of the
-dominant kernel, and the CPU oracle timed on the host on a bounded sample.
+256^3 LCE polydomain, the 64^3 wavy laminate's 30-step compression path in
+double and in float, the per-kernel times from hipEvents on the library's
+stream, the roofline of the dominant kernel, and the CPU oracle timed on the
+host on a bounded sample.
 """
 import argparse
 import hashlib
@@ -165,6 +167,86 @@ def run_batch(count, steps_warm=2):
     return out
 
 
+def run_lce(steps, warmup):
+    """The LCE polydomain at 256^3 (1000 Voronoi grains, neo-classical a = 2,
+    kappa = 100), float with double reductions, first load increment of the
+    uniaxial path, rho0 = 10 adaptive in [1, 50]."""
+    import torch
+    from paper_2010_06697_amd import admm, microstructure as M
+
+    log("[bench] lce: generating the 256^3 polydomain")
+    case = M.lce_polydomain_case()
+    V = case["phase"].size
+    p = admm.default_params("fp32", rho0=case["rho0"], rho_min=1.0, rho_max=50.0, adapt_rho=1,
+                            mu_ref=case["mu_ref"])
+    s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
+                    precision="fp32", directors=[case["director0"]])
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.profile(True)
+    log(f"[bench] lce: timing {steps} iterations")
+    t0 = time.perf_counter()
+    rc, rp, rd, rho = s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = s.profile_read()
+    it, status, nfail, newton_its = s.info(0)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    out = {"workload": "lce256: 256^3 LCE polydomain, 1000 grains, a=2 mu=1 kappa=100, "
+                       "Fbar = diag(1.01, 1.01^-1/2, 1.01^-1/2), float with double reductions",
+           "value": V * steps / dt, "unit": "voxel-iterations/s", "ms_per_step": 1e3 * dt / steps,
+           "newton_iters_per_voxel_iteration": newton_its / float(V * (warmup + steps)),
+           "newton_fail": int(nfail), "r_p": float(rp[0]), "r_d": float(rd[0]),
+           "kernels_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}}
+    log(f"[bench] lce: {out['value']:.3e} voxel-it/s, {out['ms_per_step']:.3f} ms/it")
+    return out
+
+
+def run_wavy():
+    """The 64^3 wavy laminate under uniaxial compression to 0.85 in 30 load
+    steps, each solved to 1e-7, in double and in float with double
+    reductions: time per load path and the homogenised stress of both."""
+    import torch
+    from paper_2010_06697_amd import admm, microstructure as M
+
+    case = M.wavy_laminate64_case()
+    out = {"workload": "wavy64: 64^3 wavy laminate (stiff 4 / period 16, mu contrast 100, "
+                       "lambda = 10 mu), Fbar = diag(1, 1, s), s = 1 -> 0.85 in 30 steps, "
+                       "each to tol 1e-7, rho0 = 10 adaptive in [1, 100]"}
+    P = {}
+    for prec in ("fp64", "fp32"):
+        p = admm.default_params(prec, rho0=case["rho0"], rho_min=1.0, rho_max=100.0,
+                                adapt_rho=1, mu_ref=case["mu_ref"], tol_p=case["tol"],
+                                tol_d=case["tol"], max_iter=3000, check_every=10)
+        s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
+                        precision=prec)
+        torch.cuda.synchronize()
+        log(f"[bench] wavy64 {prec}: 30 load steps")
+        t0 = time.perf_counter()
+        iters, conv = [], 0
+        for k, Fb in enumerate(case["loads"]):
+            if k:
+                s.set_load(0, Fb)
+            rc, it, st = s.solve()
+            iters.append(int(it[0]))
+            conv += int(st[0] == admm.OK)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P[prec] = s.homogenized_stress(0)[0]
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        out[prec] = {"seconds": dt, "load_steps_converged": conv,
+                     "iterations_total": int(np.sum(iters)), "iterations_max": int(np.max(iters)),
+                     "P33_final": float(P[prec][8])}
+        log(f"[bench] wavy64 {prec}: {dt:.2f} s, {np.sum(iters)} iterations, {conv}/30 converged")
+    out["P_rel_diff_fp32_vs_fp64"] = float(np.abs(P["fp32"] - P["fp64"]).max() /
+                                           np.abs(P["fp64"]).max())
+    return out
+
+
 def cpu_baseline(case):
     """The oracle (plain C, all host threads) on one ADMM iteration of the same
     256^3 cell from the same start."""
@@ -214,6 +296,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lce", action="store_true")
+    ap.add_argument("--no-wavy", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed region "
                          "(reference kernel for the HBM counters)")
@@ -248,6 +332,8 @@ def main():
     f32 = run_single(case, "fp32", args.steps, args.warmup)
     f64 = None if args.no_fp64 else run_single(case, "fp64", args.steps, args.warmup)
     batch = None if args.no_batch else run_batch(128)
+    lce = None if args.no_lce else run_lce(10, 3)
+    wavy = None if args.no_wavy else run_wavy()
 
     # roofline of the dominant kernel (by total time in the timed region)
     kb = kernel_bytes_per_voxel(4, c)
@@ -311,6 +397,8 @@ def main():
                                           "kernels_ms": f64["kernels_ms"]},
         "fp32_over_fp64": None if f64 is None else f32["value"] / f64["value"],
         "rve_batch": batch,
+        "lce256": lce,
+        "wavy64": wavy,
         "roofline": roof,
         "iteration_roofline": it_roof,
         "kernels": per_kernel,

@@ -110,8 +110,15 @@ typedef struct {
                            |dF| <= step_tol * max(1, |F|) (1e-10 FP64, 2e-6 FP32) */
   int32_t adapt_rho;    /* 1: adaptive penalty after each test */
   int32_t max_iter;     /* iteration cap of admm_solve */
-  int32_t check_every;  /* admm_solve: iterations between host checks (10) */
+  int32_t check_every;  /* admm_solve: iterations between host checks; also
+                           the length of the captured graph (10) */
   int32_t newton_max;   /* local Newton iteration cap (100) */
+  int32_t use_graph;    /* 1: admm_step / admm_solve replay check_every
+                           iterations as one captured hipGraph (built on
+                           first use, kept by the context); 0: launch every
+                           kernel. Profiling (admm_profile_enable) launches
+                           every kernel. (1) */
+  int32_t reserved;
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;
@@ -215,6 +222,33 @@ int admm_profile_enable(admm_ctx *ctx, int32_t on);
 /* Sum of the measured durations (ms) and number of launches of one kernel
  * since profiling was enabled. Synchronises the stream. */
 int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *launches);
+
+/* Launch configuration of Step 2 (Sec. 3 runs the Fourier-space solve with
+ * a vendor FFT; here the transforms are the library's own, and these are
+ * their free parameters). */
+typedef struct {
+  int32_t tile_y, tile_z;   /* columns per workgroup of the x2 / x3 passes */
+  int32_t n_len;            /* distinct edge lengths of the context's cells */
+  int32_t reserved;
+  int32_t len[24];          /* those lengths, ascending */
+  int32_t radix[24][8];     /* radix sequence of each length (2, 3, 4, 8),
+                               0-terminated */
+  double ms_default;        /* Step 2 over all cells, ms per call, before */
+  double ms_tuned;          /* and after tuning */
+} admm_tuning;
+
+/* Autotuner (a performance control with no counterpart in the method): times
+ * Step 2 over all cells on the context's stream, `reps` calls per candidate
+ * (best of three), and keeps the fastest tile width of the x2 pass, then of
+ * the x3 pass (half, default or double width, LDS <= 64 KiB), then the
+ * fastest radix sequence of each transform length in turn (every order of
+ * the radix-8/4/2/3 splits, at most 24 per length). Results change only by
+ * rounding (the transforms' operation order). Step 2 writes each cell's
+ * second displacement buffer (u_prev) and the workspace; u, F, Lambda, the
+ * director and the iteration state are unchanged. reps = 0 only reports the
+ * current configuration. The choice stays with the context; captured graphs
+ * are rebuilt. Not thread-safe with other calls on the same context. */
+int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out);
 
 /* Static description of an error code. */
 const char *admm_strerror(int code);

@@ -28,11 +28,18 @@ ENTRY_POINTS = (
     "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_rho",
     "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
     "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
-    "admm_profile_read", "admm_strerror", "admm_destroy",
+    "admm_profile_read", "admm_autotune", "admm_strerror", "admm_destroy",
 )
 
 KERNELS = ("local", "div_fwdx", "fft_y_fwd", "poisson_z", "fft_y_inv", "inv_x", "update",
            "finalize", "mean_stress")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("n_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("len", ctypes.c_int32 * 24), ("radix", (ctypes.c_int32 * 8) * 24),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
 
 
 class Material(ctypes.Structure):
@@ -57,6 +64,7 @@ class Params(ctypes.Structure):
                 ("newton_gtol", ctypes.c_double), ("newton_step_tol", ctypes.c_double),
                 ("adapt_rho", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
 ]
 
 
@@ -91,6 +99,7 @@ def lib():
         L.admm_cell_info.argtypes = [vp, i32, ip, ip, ip, ctypes.POINTER(ctypes.c_int64)]
         L.admm_profile_enable.argtypes = [vp, i32]
         L.admm_profile_read.argtypes = [vp, i32, dp, ip]
+        L.admm_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
         L.admm_strerror.argtypes = [ctypes.c_int]
         L.admm_strerror.restype = ctypes.c_char_p
         L.admm_destroy.argtypes = [vp]
@@ -222,6 +231,18 @@ def admm_profile_read(ctx):
     return out
 
 
+def admm_autotune(ctx, reps):
+    """Tunes (reps > 0) or reports (reps = 0) the Step 2 launch configuration:
+    {"tile_y", "tile_z", "plans": {length: [radices]}, "ms_default", "ms_tuned"}."""
+    t = Tuning()
+    _check(lib().admm_autotune(ctx, reps, ctypes.byref(t)), "admm_autotune")
+    plans = {}
+    for k in range(t.n_len):
+        plans[t.len[k]] = [r for r in t.radix[k] if r]
+    return {"tile_y": t.tile_y, "tile_z": t.tile_z, "plans": plans,
+            "ms_default": t.ms_default, "ms_tuned": t.ms_tuned}
+
+
 def admm_destroy(ctx) -> None:
     lib().admm_destroy(ctx)
 
@@ -237,6 +258,7 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     else:
         p.newton_gtol, p.newton_step_tol = 1e-10, 2e-6
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
+    p.use_graph = 1
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -355,6 +377,9 @@ class Solver:
 
     def profile_read(self):
         return admm_profile_read(self.ctx)
+
+    def autotune(self, reps=5):
+        return admm_autotune(self.ctx, reps)
 
     # -- state as float64 numpy (F as F itself) --
     def state(self, rve=0):

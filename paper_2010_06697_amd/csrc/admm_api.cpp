@@ -98,6 +98,48 @@ size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
 
 int rows_per_block(int n1) { return std::max(1, kThreads / n1); }
 
+// Radix sequences for a length n = 2^a 3^b that the autotuner tries: the
+// powers of two split into radix-8, -4 and at most one radix-2 stage, the
+// threes into radix-3 stages, every distinct order of each split (at most
+// kMaxStages stages, at most `cap` sequences, the default plan first).
+std::vector<Plan1D> plan_candidates(int n, size_t cap = 24) {
+  std::vector<Plan1D> out;
+  out.push_back(make_plan(n));
+  int m = n, twos = 0, threes = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++twos;
+  }
+  while (m % 3 == 0) {
+    m /= 3;
+    ++threes;
+  }
+  for (int e8 = twos / 3; e8 >= 0; --e8)
+    for (int e2 = 0; e2 <= 1; ++e2) {
+      const int left = twos - 3 * e8 - e2;
+      if (left < 0 || left % 2) continue;
+      std::vector<int> r;
+      r.insert(r.end(), e8, 8);
+      r.insert(r.end(), left / 2, 4);
+      r.insert(r.end(), e2, 2);
+      r.insert(r.end(), threes, 3);
+      if ((int)r.size() > kMaxStages || r.empty()) continue;
+      std::sort(r.begin(), r.end());
+      do {
+        Plan1D p{};
+        p.n = n;
+        p.nst = (int)r.size();
+        for (int k = 0; k < p.nst; ++k) p.rad[k] = r[k];
+        bool dup = false;
+        for (const Plan1D &q : out)
+          dup = dup || (q.nst == p.nst && std::equal(q.rad, q.rad + q.nst, p.rad));
+        if (!dup) out.push_back(p);
+      } while (out.size() < cap && std::next_permutation(r.begin(), r.end()));
+    }
+  if (out.size() > cap) out.resize(cap);
+  return out;
+}
+
 }  // namespace
 
 // hipEvent pairs around every launch on the context's stream; elapsed times
@@ -191,6 +233,15 @@ struct admm_ctx {
   LaunchCfg L{};
   KernelArgs A{};
   EventTimer *timer = nullptr;
+  // captured iteration sequences, one per convergence-test mode: `iters`
+  // iterations recorded on cap_stream, replayed on `stream`
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int iters = 0;
+  } graph[2];
+  hipStream_t cap_stream = nullptr;
+  // per-cell workgroup counts of the x2 / x3 passes depend on the tile widths
+  std::vector<int> blk_h;
 };
 
 namespace {
@@ -261,6 +312,54 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   return ip;
 }
 
+void drop_graphs(admm_ctx *c) {
+  for (auto &g : c->graph) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.iters = 0;
+  }
+}
+
+// tile widths of the x2 / x3 passes: workgroup prefix tables (blk_h holds
+// the x, y, z and u tables, n_rve + 1 entries each), grid sizes, upload
+int set_tiles(admm_ctx *c, int ty, int tz) {
+  const int n = c->n_rve;
+  int *by = c->blk_h.data() + (n + 1), *bz = c->blk_h.data() + 2 * (n + 1);
+  by[0] = bz[0] = 0;
+  for (int r = 0; r < n; ++r) {
+    const RveDesc &D = c->desc_h[r];
+    by[r + 1] = by[r] + D.n3 * ((D.m1 + ty - 1) / ty);
+    bz[r + 1] = bz[r] + (D.n2 * D.m1 + tz - 1) / tz;
+  }
+  c->L.tile_y = ty;
+  c->L.tile_z = tz;
+  c->L.nblk_y = by[n];
+  c->L.nblk_z = bz[n];
+  HIP_TRY(hipMemcpyAsync(c->blk_d, c->blk_h.data(), sizeof(int) * c->blk_h.size(),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  return ADMM_OK;
+}
+
+// radix plan of every transform of length len (the twiddle table stays)
+int set_plan(admm_ctx *c, const Plan1D &p) {
+  for (auto &D : c->desc_h) {
+    Plan1D *q[3] = {&D.p1, &D.p2, &D.p3};
+    for (Plan1D *x : q)
+      if (x->n == p.n) {
+        const int tw = x->tw;
+        *x = p;
+        x->tw = tw;
+      }
+  }
+  HIP_TRY(hipMemcpyAsync(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * c->n_rve,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  return ADMM_OK;
+}
+
 int launch(admm_ctx *c, Part part, const IterParams &ip) {
   hipError_t e = launch_part(c->L, c->A, ip, part, c->fp64);
   return e == hipSuccess ? ADMM_OK : ADMM_EHIP;
@@ -270,6 +369,53 @@ int one_iteration(admm_ctx *c, const IterParams &ip) {
   int rc = launch(c, Part::Local, ip);
   if (rc == ADMM_OK) rc = launch(c, Part::Project, ip);
   if (rc == ADMM_OK) rc = launch(c, Part::Update, ip);
+  return rc;
+}
+
+// Records k iterations into a graph. Every launch argument (buffers, grids,
+// iteration parameters) is fixed for the context's lifetime and all
+// iteration state lives in device memory, so the graph stays valid across
+// calls. Capture needs a stream of its own (the caller's may be the null
+// stream); the graph is then launched on the caller's stream.
+int build_graph(admm_ctx *c, const IterParams &ip, int k, admm_ctx::Graph &g) {
+  if (g.exec) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.iters = 0;
+  }
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const hipStream_t saved = c->L.stream;
+  c->L.stream = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  int rc = ADMM_OK;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = ADMM_EHIP;
+  } else {
+    for (int it = 0; it < k && rc == ADMM_OK; ++it) rc = one_iteration(c, ip);
+    if (hipStreamEndCapture(c->cap_stream, &graph) != hipSuccess) rc = ADMM_EHIP;
+  }
+  c->L.stream = saved;
+  if (rc == ADMM_OK && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    g.exec = nullptr;
+    rc = ADMM_EHIP;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc == ADMM_OK) g.iters = k;
+  return rc;
+}
+
+// n iterations: whole graphs of check_every iterations, the rest launched
+// kernel by kernel (also everything while profiling)
+int run_iterations(admm_ctx *c, const IterParams &ip, int n) {
+  const int k = c->params.check_every;
+  int done = 0, rc = ADMM_OK;
+  if (c->params.use_graph && !c->timer && k >= 2 && n >= k) {
+    admm_ctx::Graph &g = c->graph[ip.test_conv ? 1 : 0];
+    if (!g.exec || g.iters != k) rc = build_graph(c, ip, k, g);
+    for (; rc == ADMM_OK && done + k <= n; done += k)
+      if (hipGraphLaunch(g.exec, c->stream) != hipSuccess) rc = ADMM_EHIP;
+  }
+  for (; rc == ADMM_OK && done < n; ++done) rc = one_iteration(c, ip);
   return rc;
 }
 
@@ -293,8 +439,124 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->mean_d);
   (void)hipFree(c->hist_d);
   if (c->own_workspace) (void)hipFree(c->workspace);
+  for (auto &g : c->graph)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c->timer;
   delete c;
+}
+
+}  // namespace
+
+namespace {
+
+// Step 2 (all cells) per call, best of three runs of `reps` calls, on the
+// context's stream
+int time_project(admm_ctx *c, int reps, double *ms) {
+  const IterParams ip = iter_params(c, 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return ADMM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ADMM_EHIP;
+  }
+  int rc = launch(c, Part::Project, ip);
+  double best = 1e300;
+  for (int trial = 0; trial < 3 && rc == ADMM_OK; ++trial) {
+    if (hipEventRecord(e0, c->stream) != hipSuccess) rc = ADMM_EHIP;
+    for (int k = 0; k < reps && rc == ADMM_OK; ++k) rc = launch(c, Part::Project, ip);
+    if (rc == ADMM_OK && hipEventRecord(e1, c->stream) != hipSuccess) rc = ADMM_EHIP;
+    if (rc == ADMM_OK && hipEventSynchronize(e1) != hipSuccess) rc = ADMM_EHIP;
+    float t = 0.0f;
+    if (rc == ADMM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = ADMM_EHIP;
+    if (rc == ADMM_OK) best = std::min(best, (double)t / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return rc;
+}
+
+std::vector<int> lengths_of(const admm_ctx *c) {
+  std::vector<int> n;
+  for (const auto &D : c->desc_h)
+    for (int v : {D.n1, D.n2, D.n3})
+      if (std::find(n.begin(), n.end(), v) == n.end()) n.push_back(v);
+  std::sort(n.begin(), n.end());
+  return n;
+}
+
+void report_tuning(const admm_ctx *c, admm_tuning *out) {
+  out->tile_y = c->L.tile_y;
+  out->tile_z = c->L.tile_z;
+  const std::vector<int> n = lengths_of(c);
+  out->n_len = (int32_t)std::min<size_t>(n.size(), 24);
+  for (int k = 0; k < out->n_len; ++k) {
+    out->len[k] = n[k];
+    for (int s = 0; s < 8; ++s) out->radix[k][s] = 0;
+    for (const auto &D : c->desc_h) {
+      const Plan1D *q = D.p1.n == n[k] ? &D.p1 : D.p2.n == n[k] ? &D.p2 : D.p3.n == n[k] ? &D.p3
+                                                                                           : nullptr;
+      if (q) {
+        for (int s = 0; s < q->nst && s < 8; ++s) out->radix[k][s] = q->rad[s];
+        break;
+      }
+    }
+  }
+}
+
+int tune(admm_ctx *c, int reps, admm_tuning *out) {
+  const size_t csz = c->fp64 ? sizeof(double2) : sizeof(float2);
+  const int d = tile_b(c->fp64);
+  double best = 0.0;
+  int rc = time_project(c, reps, &best);
+  if (rc != ADMM_OK) return rc;
+  out->ms_default = best;
+  const int cand[3] = {d / 2, d, 2 * d};
+  // tile width of the x2 pass, then of the x3 pass (LDS <= 64 KiB)
+  for (int pass = 0; pass < 2 && rc == ADMM_OK; ++pass) {
+    const int nmax = pass == 0 ? c->L.n2max : c->L.n3max;
+    int keep = pass == 0 ? c->L.tile_y : c->L.tile_z;
+    for (int B : cand) {
+      if (B == keep || 2 * (size_t)nmax * B * csz > 65536) continue;
+      rc = pass == 0 ? set_tiles(c, B, c->L.tile_z) : set_tiles(c, c->L.tile_y, B);
+      double t = 0.0;
+      if (rc == ADMM_OK) rc = time_project(c, reps, &t);
+      if (rc != ADMM_OK) break;
+      if (t < best) {
+        best = t;
+        keep = B;
+      }
+    }
+    if (rc == ADMM_OK)
+      rc = pass == 0 ? set_tiles(c, keep, c->L.tile_z) : set_tiles(c, c->L.tile_y, keep);
+  }
+  // radix plan of each transform length in turn
+  for (int n : lengths_of(c)) {
+    if (rc != ADMM_OK) break;
+    const std::vector<Plan1D> cands = plan_candidates(n);
+    Plan1D keep{};
+    for (const auto &D : c->desc_h) {
+      if (D.p1.n == n) keep = D.p1;
+      else if (D.p2.n == n) keep = D.p2;
+      else if (D.p3.n == n) keep = D.p3;
+      if (keep.n == n) break;
+    }
+    for (const Plan1D &p : cands) {
+      if (p.nst == keep.nst && std::equal(p.rad, p.rad + p.nst, keep.rad)) continue;
+      rc = set_plan(c, p);
+      double t = 0.0;
+      if (rc == ADMM_OK) rc = time_project(c, reps, &t);
+      if (rc != ADMM_OK) break;
+      if (t < best) {
+        best = t;
+        keep = p;
+      }
+    }
+    if (rc == ADMM_OK) rc = set_plan(c, keep);
+  }
+  if (rc == ADMM_OK) rc = time_project(c, reps, &out->ms_tuned);
+  return rc;
 }
 
 }  // namespace
@@ -355,7 +617,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   const admm_params &p = *params;
   if (!(p.rho0 > 0.0) || !(p.rho_min > 0.0) || !(p.rho_max >= p.rho_min) || !(p.kappa_rho > 1.0) ||
       !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
-      p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0))
+      p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0) ||
+      (p.use_graph != 0 && p.use_graph != 1))
     return ADMM_EINVAL;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
@@ -466,8 +729,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
-    const int rows_u = D.rows * kVoxelsPerThread;
-    bu[r + 1] = bu[r] + (nrows + rows_u - 1) / rows_u;
+    bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) * ((D.n3 + kZChunk - 1) / kZChunk);
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
     lds_x = std::max(lds_x, 2 * ((3 * D.rows + 1) / 2) * D.n1);
@@ -479,6 +741,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   c->L.nblk_x = bx[n_rve];
   c->L.nblk_y = by[n_rve];
   c->L.nblk_z = bz[n_rve];
+  c->L.tile_y = c->L.tile_z = B;
   c->L.nblk_u = bu[n_rve];
   c->L.n2max = n2max;
   c->L.n3max = n3max;
@@ -487,7 +750,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
   INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
   INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 4 * (n_rve + 1)));
-  std::vector<int> blk_h;
+  std::vector<int> &blk_h = c->blk_h;
+  blk_h.clear();
   blk_h.insert(blk_h.end(), bx.begin(), bx.end());
   blk_h.insert(blk_h.end(), by.begin(), by.end());
   blk_h.insert(blk_h.end(), bz.begin(), bz.end());
@@ -599,7 +863,7 @@ int admm_step(admm_ctx *ctx, int32_t n_iter, double *r_p, double *r_d, double *r
   int rc = activate_all(ctx);
   if (rc != ADMM_OK) return rc;
   const IterParams ip = iter_params(ctx, 0);
-  for (int it = 0; it < n_iter && rc == ADMM_OK; ++it) rc = one_iteration(ctx, ip);
+  rc = run_iterations(ctx, ip, n_iter);
   if (rc != ADMM_OK) return rc;
   rc = settle(ctx);
   if (rc != ADMM_OK) return rc;
@@ -622,7 +886,7 @@ int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out) {
     bool any = false;
     for (const auto &s : ctx->state_h) any = any || s.active;
     if (!any) break;
-    for (int k = 0; k < every && rc == ADMM_OK; ++k) rc = one_iteration(ctx, ip);
+    rc = run_iterations(ctx, ip, every);
     if (rc != ADMM_OK) return rc;
     rc = download_states(ctx);
     if (rc != ADMM_OK) return rc;
@@ -731,6 +995,28 @@ int admm_profile_enable(admm_ctx *ctx, int32_t on) {
     ctx->L.timer = nullptr;
   }
   return ADMM_OK;
+}
+
+int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out) {
+  if (!ctx || !out || reps < 0) return ADMM_EINVAL;
+  int rc = ADMM_OK;
+  if (reps > 0) {
+    KernelTimer *timer = ctx->L.timer;
+    ctx->L.timer = nullptr;
+    const std::vector<RveState> saved = ctx->state_h;
+    for (auto &s : ctx->state_h) s.active = 1;  // Step 2 skips inactive cells
+    rc = upload_states(ctx);
+    if (rc == ADMM_OK) rc = tune(ctx, reps, out);
+    ctx->state_h = saved;
+    const int rc2 = upload_states(ctx);
+    if (rc == ADMM_OK) rc = rc2;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == ADMM_OK) rc = ADMM_EHIP;
+    ctx->L.timer = timer;
+  } else {
+    out->ms_default = out->ms_tuned = 0.0;
+  }
+  report_tuning(ctx, out);
+  return rc;
 }
 
 int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *launches) {

@@ -461,8 +461,25 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
 }
 
 // ----------------------------------------------------------------------------
-// Step 3 + partial sums of Step 4 (kVoxelsPerThread groups of rows per block)
+// Step 3 + partial sums of Step 4. A workgroup owns a column of R x1-lines
+// by kZChunk planes and marches along x3, one voxel per thread and plane:
+// both u fields at the thread's own (x1, x2) for the planes z-1, z, z+1 stay
+// in registers, so every u value is read from HBM once per column (plus two
+// halo planes), and the +-x1 / +-x2 neighbours come from lines that this and
+// the adjacent workgroups read at the same time (cache hits).
 // ----------------------------------------------------------------------------
+
+__device__ __forceinline__ void column_tile(const RveDesc &D, int b, int &x2, int &z0, int &z1,
+                                            int &row, int &x1) {
+  const int R = D.rows, n1 = D.n1;
+  const int nty = (D.n2 + R - 1) / R;
+  const int zc = b / nty, ty = b - zc * nty;
+  row = threadIdx.x / n1;
+  x1 = threadIdx.x - row * n1;
+  x2 = ty * R + row;
+  z0 = zc * kZChunk;
+  z1 = min(z0 + kZChunk, D.n3);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
@@ -472,35 +489,70 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
-  const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
-  const int nrows = n2 * n3;
-  const double rho = st->rho;
-  const T *un = static_cast<const T *>(D.u[1 - st->cur]);
-  const T *uo = static_cast<const T *>(D.u[st->cur]);
-  const T *Eg = static_cast<const T *>(D.E);
-  T *Lg = static_cast<T *>(D.Lam);
-  const int t = threadIdx.x;
-  const int row = t / n1, x1 = t - row * n1;
+  int x2, z0, z1, row, x1;
+  column_tile(D, blk - a.blk_u[r], x2, z0, z1, row, x1);
   double v[2] = {0.0, 0.0};
+  if (row < R && x2 < n2) {
+    const double rho = st->rho;
+    const T *un = static_cast<const T *>(D.u[1 - st->cur]);
+    const T *uo = static_cast<const T *>(D.u[st->cur]);
+    const T *Eg = static_cast<const T *>(D.E);
+    T *Lg = static_cast<T *>(D.Lam);
+    const int x1p = x1 + 1 == n1 ? 0 : x1 + 1, x1m = x1 == 0 ? n1 - 1 : x1 - 1;
+    const int x2p = x2 + 1 == n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
+    const int plane = n1 * n2;
+    // own column: [0] plane z-1, [1] plane z, [2] plane z+1; components
+    // 0..2 of u_{i+1}, 3..5 of u_i
+    T cm[6], cc[6], cp[6];
+    {
+      const int zm = z0 == 0 ? n3 - 1 : z0 - 1;
+      const int om = zm * plane + x2 * n1 + x1, oc = z0 * plane + x2 * n1 + x1;
 #pragma unroll
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
-    const int grow = (b * kVoxelsPerThread + k) * R + row;
-    if (row >= R || grow >= nrows) continue;
-    const int x2 = grow % n2, x3 = grow / n2;
-    const int idx = grow * n1 + x1;
-    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
-    double Dn[9], Do[9];
-    grad_u(un, V, sn, Dn);
-    grad_u(uo, V, sn, Do);
+      for (int i = 0; i < 3; ++i) {
+        cm[i] = un[i * V + om];
+        cm[3 + i] = uo[i * V + om];
+        cc[i] = un[i * V + oc];
+        cc[3 + i] = uo[i * V + oc];
+      }
+    }
+    for (int z = z0; z < z1; ++z) {
+      const int zp = z + 1 == n3 ? 0 : z + 1;
+      const int idx = z * plane + x2 * n1 + x1;
+      const int op = zp * plane + x2 * n1 + x1;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const double e = D.Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
-      Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
-      const double dd = Dn[c] - Do[c];
-      v[0] += e * e;
-      v[1] += dd * dd;
+      for (int i = 0; i < 3; ++i) {
+        cp[i] = un[i * V + op];
+        cp[3 + i] = uo[i * V + op];
+      }
+      const int o1p = z * plane + x2 * n1 + x1p, o1m = z * plane + x2 * n1 + x1m;
+      const int o2p = z * plane + x2p * n1 + x1, o2m = z * plane + x2m * n1 + x1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T *ni = un + i * V;
+        const T *oi = uo + i * V;
+        const double dn[3] = {0.5 * ((double)ni[o1p] - (double)ni[o1m]),
+                              0.5 * ((double)ni[o2p] - (double)ni[o2m]),
+                              0.5 * ((double)cp[i] - (double)cm[i])};
+        const double dq[3] = {0.5 * ((double)oi[o1p] - (double)oi[o1m]),
+                              0.5 * ((double)oi[o2p] - (double)oi[o2m]),
+                              0.5 * ((double)cp[3 + i] - (double)cm[3 + i])};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const int c = 3 * i + j;
+          const double e = D.Ebar[c] + dn[j] - (double)Eg[c * V + idx];
+          Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
+          const double dd = dn[j] - dq[j];
+          v[0] += e * e;
+          v[1] += dd * dd;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        cm[k] = cc[k];
+        cc[k] = cp[k];
+      }
     }
   }
   block_sum<2>(v, red);
@@ -574,21 +626,19 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_u, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
-  const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
-  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3;
+  const int n1 = D.n1, n2 = D.n2, R = D.rows;
+  int x2, z0, z1, row, x1;
+  column_tile(D, blk - a.blk_u[r], x2, z0, z1, row, x1);
   const T *Eg = static_cast<const T *>(D.E);
   const T *Lg = static_cast<const T *>(D.Lam);
-  const int t = threadIdx.x;
-  const int row = t / n1, x1 = t - row * n1;
   double v[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) v[k] = 0.0;
   int bad = 0;
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
-    const int grow = (b * kVoxelsPerThread + k) * R + row;
-    if (row >= R || grow >= nrows) continue;
-    const int idx = grow * n1 + x1;
+  for (int z = z0; z < z1; ++z) {
+    if (row >= R || x2 >= n2) break;
+    const int idx = (z * n2 + x2) * n1 + x1;
     double E[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -670,13 +720,39 @@ struct Timed {
   }
 };
 
+// the x2 / x3 passes at a runtime tile width (one of three compiled widths)
+template <typename T, bool INV>
+static void launch_fft_y(const LaunchCfg &L, const KernelArgs &a) {
+  using C = typename cplx<T>::type;
+  constexpr int B = tileB<T>();
+  const dim3 blk(kThreads), grid(L.nblk_y, 3);
+  const size_t lds = 2 * (size_t)L.n2max * L.tile_y * sizeof(C);
+  if (L.tile_y == B / 2)
+    hipLaunchKernelGGL((k_fft_y<T, B / 2, INV>), grid, blk, lds, L.stream, a);
+  else if (L.tile_y == 2 * B)
+    hipLaunchKernelGGL((k_fft_y<T, 2 * B, INV>), grid, blk, lds, L.stream, a);
+  else
+    hipLaunchKernelGGL((k_fft_y<T, B, INV>), grid, blk, lds, L.stream, a);
+}
+
+template <typename T>
+static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
+  using C = typename cplx<T>::type;
+  constexpr int B = tileB<T>();
+  const dim3 blk(kThreads), grid(L.nblk_z, 3);
+  const size_t lds = 2 * (size_t)L.n3max * L.tile_z * sizeof(C);
+  if (L.tile_z == B / 2)
+    hipLaunchKernelGGL((k_poisson_z<T, B / 2>), grid, blk, lds, L.stream, a);
+  else if (L.tile_z == 2 * B)
+    hipLaunchKernelGGL((k_poisson_z<T, 2 * B>), grid, blk, lds, L.stream, a);
+  else
+    hipLaunchKernelGGL((k_poisson_z<T, B>), grid, blk, lds, L.stream, a);
+}
+
 template <typename T>
 static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
                                         const IterParams &ip, Part part) {
-  using C = typename cplx<T>::type;
-  constexpr int B = tileB<T>();
   const dim3 blk(kThreads);
-  const size_t lds_y = 2 * L.n2max * B * sizeof(C), lds_z = 2 * L.n3max * B * sizeof(C);
   switch (part) {
     case Part::Local: {
       Timed tm(L, K_LOCAL);
@@ -693,15 +769,15 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       }
       {
         Timed tm(L, K_FFT_Y_FWD);
-        hipLaunchKernelGGL((k_fft_y<T, B, false>), dim3(L.nblk_y, 3), blk, lds_y, L.stream, a);
+        launch_fft_y<T, false>(L, a);
       }
       {
         Timed tm(L, K_POISSON_Z);
-        hipLaunchKernelGGL((k_poisson_z<T, B>), dim3(L.nblk_z, 3), blk, lds_z, L.stream, a);
+        launch_poisson_z<T>(L, a);
       }
       {
         Timed tm(L, K_FFT_Y_INV);
-        hipLaunchKernelGGL((k_fft_y<T, B, true>), dim3(L.nblk_y, 3), blk, lds_y, L.stream, a);
+        launch_fft_y<T, true>(L, a);
       }
       {
         Timed tm(L, K_INV_X);
@@ -737,5 +813,10 @@ hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams
 }
 
 int tile_b(bool fp64) { return fp64 ? tileB<double>() : tileB<float>(); }
+
+bool tile_compiled(bool fp64, int B) {
+  const int d = tile_b(fp64);
+  return B == d / 2 || B == d || B == 2 * d;
+}
 
 }  // namespace admm

@@ -42,6 +42,7 @@ struct LaunchCfg {
   KernelTimer *timer;  // null unless profiling
   hipStream_t stream;
   int nblk_x, nblk_y, nblk_z, nblk_u;
+  int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
   bool any_lce;  // some phase uses the LCE energy
@@ -53,7 +54,10 @@ enum class Part { Local, Project, Update, MeanStress };
 hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, Part part,
                        bool fp64);
 
-// columns per tile of the FFT passes along x2 and x3 (128 bytes of complex)
+// columns per tile of the FFT passes along x2 and x3: the default (128 bytes
+// of complex per row) and whether a width is one of the compiled ones (half,
+// default, double)
 int tile_b(bool fp64);
+bool tile_compiled(bool fp64, int B);
 
 }  // namespace admm
