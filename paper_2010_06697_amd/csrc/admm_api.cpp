@@ -224,10 +224,11 @@ struct admm_ctx {
   int *blk_d = nullptr;
   Material *mats_d = nullptr;
   void *tw_d = nullptr;
-  double2 *partials_d = nullptr;
+  double4 *partials_d = nullptr;
   double *partials18_d = nullptr;
   double *mean_d = nullptr;
   double *hist_d = nullptr;
+  int2 *newton_part_d = nullptr;
   void *workspace = nullptr;
   bool own_workspace = false;
   LaunchCfg L{};
@@ -438,6 +439,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->partials18_d);
   (void)hipFree(c->mean_d);
   (void)hipFree(c->hist_d);
+  (void)hipFree(c->newton_part_d);
   if (c->own_workspace) (void)hipFree(c->workspace);
   for (auto &g : c->graph)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -729,7 +731,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
-    bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) * ((D.n3 + kZChunk - 1) / kZChunk);
+    const int rows_u = D.rows * kVoxelsPerThread;
+    bu[r + 1] = bu[r] + (nrows + rows_u - 1) / rows_u;
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
     lds_x = std::max(lds_x, 2 * ((3 * D.rows + 1) / 2) * D.n1);
@@ -768,10 +771,12 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->mats_d, sizeof(Material) * n_mat));
   INIT_TRY(hipMemcpy(c->mats_d, mh.data(), sizeof(Material) * n_mat, hipMemcpyHostToDevice));
 
-  INIT_TRY(hipMalloc(&c->partials_d, sizeof(double2) * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMalloc(&c->partials_d, sizeof(double4) * (size_t)c->L.nblk_u));
   INIT_TRY(hipMalloc(&c->partials18_d, sizeof(double) * 18 * (size_t)c->L.nblk_u));
   INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
   INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
+  INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_x));
 
   c->state_h.assign(n_rve, RveState{});
   for (int r = 0; r < n_rve; ++r) {
@@ -797,6 +802,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.partials18 = c->partials18_d;
   A.mean_out = c->mean_d;
   A.hist = c->hist_d;
+  A.newton_part = c->newton_part_d;
   A.n_rve = n_rve;
   A.n_mat = n_mat;
 #undef INIT_TRY

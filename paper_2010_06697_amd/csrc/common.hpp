@@ -52,13 +52,7 @@ struct RveState {
   unsigned long long newton_iters;  // Newton iterations summed over voxels and iterations
 };
 
-// The per-voxel reduction kernels (update, mean stress) tile a cell into
-// columns: R rows of x1-lines (R n1 <= kThreads voxels per plane) times
-// kZChunk planes along x3, one voxel per thread and plane.
-#ifndef ADMM_ZCHUNK
-#define ADMM_ZCHUNK 16
-#endif
-constexpr int kZChunk = ADMM_ZCHUNK;
+constexpr int kVoxelsPerThread = 4;  // grid-stride depth of the per-voxel reduction kernels
 
 struct Material {
   int model;  // 0 neo-Hookean, 1 LCE

@@ -178,15 +178,28 @@ void k_local(KernelArgs a, IterParams ip) {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
   }
-  // one atomic per wave for the Newton statistics
+  // Newton statistics: one entry per workgroup, folded into the cell's
+  // counters by k_finalize (atomics on one address per cell from every
+  // wave serialise the kernel's tail)
+  __shared__ int wsum[2 * (kThreads / 64)];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     n_fail += __shfl_xor(n_fail, off, 64);
     n_its += __shfl_xor(n_its, off, 64);
   }
+  const int wave = t >> 6, nw = (blockDim.x + 63) >> 6;
   if ((t & 63) == 0) {
-    if (n_fail) atomicAdd(&st->newton_fail, n_fail);
-    if (n_its) atomicAdd(&st->newton_iters, (unsigned long long)n_its);
+    wsum[wave] = n_fail;
+    wsum[nw + wave] = n_its;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int f = 0, s = 0;
+    for (int w = 0; w < nw; ++w) {
+      f += wsum[w];
+      s += wsum[nw + w];
+    }
+    a.newton_part[blk] = int2{f, s};
   }
 }
 
@@ -461,25 +474,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
 }
 
 // ----------------------------------------------------------------------------
-// Step 3 + partial sums of Step 4. A workgroup owns a column of R x1-lines
-// by kZChunk planes and marches along x3, one voxel per thread and plane:
-// both u fields at the thread's own (x1, x2) for the planes z-1, z, z+1 stay
-// in registers, so every u value is read from HBM once per column (plus two
-// halo planes), and the +-x1 / +-x2 neighbours come from lines that this and
-// the adjacent workgroups read at the same time (cache hits).
+// Step 3 + partial sums of Step 4 (kVoxelsPerThread groups of rows per block)
 // ----------------------------------------------------------------------------
-
-__device__ __forceinline__ void column_tile(const RveDesc &D, int b, int &x2, int &z0, int &z1,
-                                            int &row, int &x1) {
-  const int R = D.rows, n1 = D.n1;
-  const int nty = (D.n2 + R - 1) / R;
-  const int zc = b / nty, ty = b - zc * nty;
-  row = threadIdx.x / n1;
-  x1 = threadIdx.x - row * n1;
-  x2 = ty * R + row;
-  z0 = zc * kZChunk;
-  z1 = min(z0 + kZChunk, D.n3);
-}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
@@ -489,74 +485,49 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
+  const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
-  int x2, z0, z1, row, x1;
-  column_tile(D, blk - a.blk_u[r], x2, z0, z1, row, x1);
+  const int nrows = n2 * n3;
+  const double rho = st->rho;
+  const T *un = static_cast<const T *>(D.u[1 - st->cur]);
+  const T *uo = static_cast<const T *>(D.u[st->cur]);
+  const T *Eg = static_cast<const T *>(D.E);
+  T *Lg = static_cast<T *>(D.Lam);
+  const int t = threadIdx.x;
+  const int row = t / n1, x1 = t - row * n1;
   double v[2] = {0.0, 0.0};
-  if (row < R && x2 < n2) {
-    const double rho = st->rho;
-    const T *un = static_cast<const T *>(D.u[1 - st->cur]);
-    const T *uo = static_cast<const T *>(D.u[st->cur]);
-    const T *Eg = static_cast<const T *>(D.E);
-    T *Lg = static_cast<T *>(D.Lam);
-    const int x1p = x1 + 1 == n1 ? 0 : x1 + 1, x1m = x1 == 0 ? n1 - 1 : x1 - 1;
-    const int x2p = x2 + 1 == n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
-    const int plane = n1 * n2;
-    // own column: [0] plane z-1, [1] plane z, [2] plane z+1; components
-    // 0..2 of u_{i+1}, 3..5 of u_i
-    T cm[6], cc[6], cp[6];
-    {
-      const int zm = z0 == 0 ? n3 - 1 : z0 - 1;
-      const int om = zm * plane + x2 * n1 + x1, oc = z0 * plane + x2 * n1 + x1;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        cm[i] = un[i * V + om];
-        cm[3 + i] = uo[i * V + om];
-        cc[i] = un[i * V + oc];
-        cc[3 + i] = uo[i * V + oc];
-      }
-    }
-    for (int z = z0; z < z1; ++z) {
-      const int zp = z + 1 == n3 ? 0 : z + 1;
-      const int idx = z * plane + x2 * n1 + x1;
-      const int op = zp * plane + x2 * n1 + x1;
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int grow = (b * kVoxelsPerThread + k) * R + row;
+    if (row >= R || grow >= nrows) continue;
+    const int x2 = grow % n2, x3 = grow / n2;
+    const int idx = grow * n1 + x1;
+    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
+    double Dn[9], Do[9];
+    grad_u(un, V, sn, Dn);
+    grad_u(uo, V, sn, Do);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        cp[i] = un[i * V + op];
-        cp[3 + i] = uo[i * V + op];
-      }
-      const int o1p = z * plane + x2 * n1 + x1p, o1m = z * plane + x2 * n1 + x1m;
-      const int o2p = z * plane + x2p * n1 + x1, o2m = z * plane + x2m * n1 + x1;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const T *ni = un + i * V;
-        const T *oi = uo + i * V;
-        const double dn[3] = {0.5 * ((double)ni[o1p] - (double)ni[o1m]),
-                              0.5 * ((double)ni[o2p] - (double)ni[o2m]),
-                              0.5 * ((double)cp[i] - (double)cm[i])};
-        const double dq[3] = {0.5 * ((double)oi[o1p] - (double)oi[o1m]),
-                              0.5 * ((double)oi[o2p] - (double)oi[o2m]),
-                              0.5 * ((double)cp[3 + i] - (double)cm[3 + i])};
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const int c = 3 * i + j;
-          const double e = D.Ebar[c] + dn[j] - (double)Eg[c * V + idx];
-          Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
-          const double dd = dn[j] - dq[j];
-          v[0] += e * e;
-          v[1] += dd * dd;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        cm[k] = cc[k];
-        cc[k] = cp[k];
-      }
+    for (int c = 0; c < 9; ++c) {
+      const double e = D.Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
+      Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
+      const double dd = Dn[c] - Do[c];
+      v[0] += e * e;
+      v[1] += dd * dd;
     }
   }
   block_sum<2>(v, red);
-  if (threadIdx.x == 0) a.partials[blk] = double2{v[0], v[1]};
+  if (threadIdx.x == 0) {
+    // the local step's workgroups of these rows (R rows each, in order)
+    const int x0 = a.blk_x[r], nx = a.blk_x[r + 1] - x0;
+    int f = 0, its = 0;
+    for (int k = b * kVoxelsPerThread; k < (b + 1) * kVoxelsPerThread && k < nx; ++k) {
+      const int2 q = a.newton_part[x0 + k];
+      f += q.x;
+      its += q.y;
+    }
+    a.partials[blk] = double4{v[0], v[1], (double)f, (double)its};
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -564,19 +535,24 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
 // ----------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams ip) {
-  __shared__ double red[2 * (kThreads / 64)];
+  __shared__ double red[4 * (kThreads / 64)];
   const int r = blockIdx.x;
   RveState *st = a.state + r;
   if (!st->active) return;
   const int p0 = a.blk_u[r], nb = a.blk_u[r + 1] - p0;
-  double v[2] = {0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    const double2 q = a.partials[p0 + k];
+    const double4 q = a.partials[p0 + k];
     v[0] += q.x;
     v[1] += q.y;
+    v[2] += q.z;
+    v[3] += q.w;
   }
-  block_sum<2>(v, red);
+  block_sum<4>(v, red);
   if (threadIdx.x != 0) return;
+  // Newton statistics (integers, summed exactly in double)
+  st->newton_fail += (int)v[2];
+  st->newton_iters += (unsigned long long)v[3];
   const double V = (double)a.desc[r].V;
   const double rho = st->rho;
   const double rp = sqrt(v[0] / V);
@@ -626,19 +602,21 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_u, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
+  const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
-  const int n1 = D.n1, n2 = D.n2, R = D.rows;
-  int x2, z0, z1, row, x1;
-  column_tile(D, blk - a.blk_u[r], x2, z0, z1, row, x1);
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3;
   const T *Eg = static_cast<const T *>(D.E);
   const T *Lg = static_cast<const T *>(D.Lam);
+  const int t = threadIdx.x;
+  const int row = t / n1, x1 = t - row * n1;
   double v[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) v[k] = 0.0;
   int bad = 0;
-  for (int z = z0; z < z1; ++z) {
-    if (row >= R || x2 >= n2) break;
-    const int idx = (z * n2 + x2) * n1 + x1;
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int grow = (b * kVoxelsPerThread + k) * R + row;
+    if (row >= R || grow >= nrows) continue;
+    const int idx = grow * n1 + x1;
     double E[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {

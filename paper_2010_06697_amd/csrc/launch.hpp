@@ -16,10 +16,12 @@ struct KernelArgs {
   const int *blk_u;
   const Material *mats;
   const void *tw;       // twiddle pool (float2 or double2)
-  double2 *partials;    // per update workgroup: (sum e^2, sum dd^2)
+  double4 *partials;    // per update workgroup: sum e^2, sum dd^2, and the failed
+                        // solves and Newton iterations of its rows' local step
   double *partials18;   // per workgroup: sums of P and Lambda
   double *mean_out;     // per cell: <P>, <Lambda>
   double *hist;         // per cell, per iteration: r_p, r_d, rho
+  int2 *newton_part;    // per local-step workgroup: failed solves, Newton iterations
   int n_rve;
   int n_mat;
 };
