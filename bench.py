@@ -90,6 +90,9 @@ def run_single(case, precision, steps, warmup, profile=True):
     log(f"[bench] {precision}: warmup {warmup} iterations")
     if warmup:
         s.step(warmup)
+    tuning = s.autotune(reps=3)
+    log(f"[bench] {precision}: autotuned Step 2 {tuning['ms_default']:.3f} -> "
+        f"{tuning['ms_tuned']:.3f} ms (tiles {tuning['tile_y']}/{tuning['tile_z']})")
     torch.cuda.synchronize()
     if profile:
         s.profile(True)
@@ -116,6 +119,7 @@ def run_single(case, precision, steps, warmup, profile=True):
         "P_mean": [float(x) for x in P],
         "kernels_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()},
         "kernels_launches": {k: v[1] for k, v in prof.items()},
+        "autotune": tuning,
     }
     log(f"[bench] {precision}: {out['value']:.3e} voxel-it/s, {out['ms_per_step']:.3f} ms/it")
     return out
@@ -134,6 +138,7 @@ def run_batch(count, steps_warm=2):
     s = admm.Solver([c["phase"] for c in cells], mats, [c["Fbar"] for c in cells], p,
                     precision="fp32")
     s.step(steps_warm)  # loads the kernels; the state is reset below
+    tuning = s.autotune(reps=3)
     for k, c in enumerate(s.cells):
         for f in ("u", "u_prev", "F", "Lambda"):
             c[f].zero_()
@@ -161,6 +166,7 @@ def run_batch(count, steps_warm=2):
         "iterations_mean": float(iters.mean()),
         "iterations_max": int(iters.max()),
         "voxel_iterations_per_s": float(np.sum(vox * iters)) / dt,
+        "autotune": tuning,
     }
     log(f"[bench] batch: {out['rve_solves_per_s']:.2f} cell solves/s, "
         f"{out['voxel_iterations_per_s']:.3e} voxel-it/s")
@@ -182,6 +188,7 @@ def run_lce(steps, warmup):
     s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
                     precision="fp32", directors=[case["director0"]])
     s.step(warmup)
+    s.autotune(reps=3)
     torch.cuda.synchronize()
     s.profile(True)
     log(f"[bench] lce: timing {steps} iterations")
@@ -396,6 +403,7 @@ def main():
                                           "dtype": "f64",
                                           "kernels_ms": f64["kernels_ms"]},
         "fp32_over_fp64": None if f64 is None else f32["value"] / f64["value"],
+        "autotune": f32["autotune"],
         "rve_batch": batch,
         "lce256": lce,
         "wavy64": wavy,

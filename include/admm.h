@@ -240,7 +240,7 @@ typedef struct {
 /* Autotuner (a performance control with no counterpart in the method): times
  * Step 2 over all cells on the context's stream, `reps` calls per candidate
  * (best of three), and keeps the fastest tile width of the x2 pass, then of
- * the x3 pass (half, default or double width, LDS <= 64 KiB), then the
+ * the x3 pass (a quarter, half, default or double width, LDS <= 64 KiB), then the
  * fastest radix sequence of each transform length in turn (every order of
  * the radix-8/4/2/3 splits, at most 24 per length). Results change only by
  * rounding (the transforms' operation order). Step 2 writes each cell's

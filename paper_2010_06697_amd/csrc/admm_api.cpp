@@ -514,7 +514,7 @@ int tune(admm_ctx *c, int reps, admm_tuning *out) {
   int rc = time_project(c, reps, &best);
   if (rc != ADMM_OK) return rc;
   out->ms_default = best;
-  const int cand[3] = {d / 2, d, 2 * d};
+  const int cand[4] = {d / 4, d / 2, d, 2 * d};
   // tile width of the x2 pass, then of the x3 pass (LDS <= 64 KiB)
   for (int pass = 0; pass < 2 && rc == ADMM_OK; ++pass) {
     const int nmax = pass == 0 ? c->L.n2max : c->L.n3max;
@@ -731,8 +731,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
-    const int rows_u = D.rows * kVoxelsPerThread;
-    bu[r + 1] = bu[r] + (nrows + rows_u - 1) / rows_u;
+    bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) *
+                            ((D.n3 + kVoxelsPerThread - 1) / kVoxelsPerThread);
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
     lds_x = std::max(lds_x, 2 * ((3 * D.rows + 1) / 2) * D.n1);
@@ -775,8 +775,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->partials18_d, sizeof(double) * 18 * (size_t)c->L.nblk_u));
   INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
   INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
-  INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_x));
-  INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_u));
 
   c->state_h.assign(n_rve, RveState{});
   for (int r = 0; r < n_rve; ++r) {

@@ -178,9 +178,9 @@ void k_local(KernelArgs a, IterParams ip) {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
   }
-  // Newton statistics: one entry per workgroup, folded into the cell's
-  // counters by k_finalize (atomics on one address per cell from every
-  // wave serialise the kernel's tail)
+  // Newton statistics: summed per workgroup and added to one slot of the
+  // update kernel's tiling (atomics from every wave on one address per cell
+  // serialised the kernel's tail)
   __shared__ int wsum[2 * (kThreads / 64)];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -199,7 +199,13 @@ void k_local(KernelArgs a, IterParams ip) {
       f += wsum[w];
       s += wsum[nw + w];
     }
-    a.newton_part[blk] = int2{f, s};
+    // the update workgroup whose tile holds this workgroup's first line
+    // folds the counts into its residual partials (a few workgroups share a
+    // slot, so these atomics do not contend)
+    const int g = b * R, x2 = g % n2, x3 = g / n2;
+    const int slot = a.blk_u[r] + (x3 / kVoxelsPerThread) * ((n2 + R - 1) / R) + x2 / R;
+    if (f) atomicAdd(&a.newton_part[slot].x, f);
+    if (s) atomicAdd(&a.newton_part[slot].y, s);
   }
 }
 
@@ -474,8 +480,21 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
 }
 
 // ----------------------------------------------------------------------------
-// Step 3 + partial sums of Step 4 (kVoxelsPerThread groups of rows per block)
+// Step 3 + partial sums of Step 4. A workgroup owns R x1-lines (one x2 group)
+// on kVoxelsPerThread consecutive planes: the +-x3 neighbours of its planes
+// are its own lines or the two next to them, read within the workgroup's
+// lifetime instead of a plane of streamed fields apart (which an XCD's L2
+// does not hold); the +-x2 neighbours are lines of the adjacent workgroups,
+// which run at the same time.
 // ----------------------------------------------------------------------------
+
+// (x2, first x3) of workgroup b of a cell in the update / mean-stress tiling
+__device__ __forceinline__ void column_tile(const RveDesc &D, int b, int row, int &x2, int &z0) {
+  const int ny = (D.n2 + D.rows - 1) / D.rows;
+  const int zc = b / ny;
+  x2 = (b - zc * ny) * D.rows + row;
+  z0 = zc * kVoxelsPerThread;
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
@@ -488,21 +507,21 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
-  const int nrows = n2 * n3;
   const double rho = st->rho;
-  const T *un = static_cast<const T *>(D.u[1 - st->cur]);
-  const T *uo = static_cast<const T *>(D.u[st->cur]);
-  const T *Eg = static_cast<const T *>(D.E);
-  T *Lg = static_cast<T *>(D.Lam);
+  const T *__restrict__ un = static_cast<const T *>(D.u[1 - st->cur]);
+  const T *__restrict__ uo = static_cast<const T *>(D.u[st->cur]);
+  const T *__restrict__ Eg = static_cast<const T *>(D.E);
+  T *__restrict__ Lg = static_cast<T *>(D.Lam);
   const int t = threadIdx.x;
   const int row = t / n1, x1 = t - row * n1;
+  int x2, z0;
+  column_tile(D, b, row, x2, z0);
   double v[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < kVoxelsPerThread; ++k) {
-    const int grow = (b * kVoxelsPerThread + k) * R + row;
-    if (row >= R || grow >= nrows) continue;
-    const int x2 = grow % n2, x3 = grow / n2;
-    const int idx = grow * n1 + x1;
+    const int x3 = z0 + k;
+    if (row >= R || x2 >= n2 || x3 >= n3) continue;
+    const int idx = (x3 * n2 + x2) * n1 + x1;
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     double Dn[9], Do[9];
     grad_u(un, V, sn, Dn);
@@ -518,15 +537,10 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   }
   block_sum<2>(v, red);
   if (threadIdx.x == 0) {
-    // the local step's workgroups of these rows (R rows each, in order)
-    const int x0 = a.blk_x[r], nx = a.blk_x[r + 1] - x0;
-    int f = 0, its = 0;
-    for (int k = b * kVoxelsPerThread; k < (b + 1) * kVoxelsPerThread && k < nx; ++k) {
-      const int2 q = a.newton_part[x0 + k];
-      f += q.x;
-      its += q.y;
-    }
-    a.partials[blk] = double4{v[0], v[1], (double)f, (double)its};
+    // Newton statistics the local step's workgroups left in this slot
+    const int2 q = a.newton_part[blk];
+    a.newton_part[blk] = int2{0, 0};
+    a.partials[blk] = double4{v[0], v[1], (double)q.x, (double)q.y};
   }
 }
 
@@ -604,19 +618,21 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
   const RveDesc &D = a.desc[r];
   const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
-  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3;
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
   const T *Eg = static_cast<const T *>(D.E);
   const T *Lg = static_cast<const T *>(D.Lam);
   const int t = threadIdx.x;
   const int row = t / n1, x1 = t - row * n1;
+  int x2, z0;
+  column_tile(D, b, row, x2, z0);
   double v[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) v[k] = 0.0;
   int bad = 0;
   for (int k = 0; k < kVoxelsPerThread; ++k) {
-    const int grow = (b * kVoxelsPerThread + k) * R + row;
-    if (row >= R || grow >= nrows) continue;
-    const int idx = grow * n1 + x1;
+    const int x3 = z0 + k;
+    if (row >= R || x2 >= n2 || x3 >= n3) continue;
+    const int idx = (x3 * n2 + x2) * n1 + x1;
     double E[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -698,14 +714,16 @@ struct Timed {
   }
 };
 
-// the x2 / x3 passes at a runtime tile width (one of three compiled widths)
+// the x2 / x3 passes at a runtime tile width (one of four compiled widths)
 template <typename T, bool INV>
 static void launch_fft_y(const LaunchCfg &L, const KernelArgs &a) {
   using C = typename cplx<T>::type;
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_y, 3);
   const size_t lds = 2 * (size_t)L.n2max * L.tile_y * sizeof(C);
-  if (L.tile_y == B / 2)
+  if (L.tile_y == B / 4)
+    hipLaunchKernelGGL((k_fft_y<T, B / 4, INV>), grid, blk, lds, L.stream, a);
+  else if (L.tile_y == B / 2)
     hipLaunchKernelGGL((k_fft_y<T, B / 2, INV>), grid, blk, lds, L.stream, a);
   else if (L.tile_y == 2 * B)
     hipLaunchKernelGGL((k_fft_y<T, 2 * B, INV>), grid, blk, lds, L.stream, a);
@@ -719,7 +737,9 @@ static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_z, 3);
   const size_t lds = 2 * (size_t)L.n3max * L.tile_z * sizeof(C);
-  if (L.tile_z == B / 2)
+  if (L.tile_z == B / 4)
+    hipLaunchKernelGGL((k_poisson_z<T, B / 4>), grid, blk, lds, L.stream, a);
+  else if (L.tile_z == B / 2)
     hipLaunchKernelGGL((k_poisson_z<T, B / 2>), grid, blk, lds, L.stream, a);
   else if (L.tile_z == 2 * B)
     hipLaunchKernelGGL((k_poisson_z<T, 2 * B>), grid, blk, lds, L.stream, a);
@@ -794,7 +814,7 @@ int tile_b(bool fp64) { return fp64 ? tileB<double>() : tileB<float>(); }
 
 bool tile_compiled(bool fp64, int B) {
   const int d = tile_b(fp64);
-  return B == d / 2 || B == d || B == 2 * d;
+  return B == d / 4 || B == d / 2 || B == d || B == 2 * d;
 }
 
 }  // namespace admm

@@ -21,7 +21,8 @@ struct KernelArgs {
   double *partials18;   // per workgroup: sums of P and Lambda
   double *mean_out;     // per cell: <P>, <Lambda>
   double *hist;         // per cell, per iteration: r_p, r_d, rho
-  int2 *newton_part;    // per local-step workgroup: failed solves, Newton iterations
+  int2 *newton_part;    // per update workgroup: failed solves and Newton iterations
+                        // of the local-step workgroups in its tile
   int n_rve;
   int n_mat;
 };
@@ -57,8 +58,8 @@ hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams
                        bool fp64);
 
 // columns per tile of the FFT passes along x2 and x3: the default (128 bytes
-// of complex per row) and whether a width is one of the compiled ones (half,
-// default, double)
+// of complex per row) and whether a width is one of the compiled ones (a
+// quarter, half, default, double)
 int tile_b(bool fp64);
 bool tile_compiled(bool fp64, int B);
 
