@@ -229,7 +229,8 @@ int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *
 typedef struct {
   int32_t tile_y, tile_z;   /* columns per workgroup of the x2 / x3 passes */
   int32_t n_len;            /* distinct edge lengths of the context's cells */
-  int32_t reserved;
+  int32_t x_points;         /* points per workgroup of the x1 transforms
+                               (256, 512 or 1024; lines = points / n1) */
   int32_t len[24];          /* those lengths, ascending */
   int32_t radix[24][8];     /* radix sequence of each length (2, 3, 4, 8),
                                0-terminated */
@@ -239,7 +240,8 @@ typedef struct {
 
 /* Autotuner (a performance control with no counterpart in the method): times
  * Step 2 over all cells on the context's stream, `reps` calls per candidate
- * (best of three), and keeps the fastest tile width of the x2 pass, then of
+ * (best of three), and keeps the fastest number of points per workgroup of
+ * the x1 transforms, then the fastest tile width of the x2 pass, then of
  * the x3 pass (a quarter, half, default or double width, LDS <= 64 KiB), then the
  * fastest radix sequence of each transform length in turn (every order of
  * the radix-8/4/2/3 splits, at most 24 per length). Results change only by

@@ -37,7 +37,7 @@ KERNELS = ("local", "div_fwdx", "fft_y_fwd", "poisson_z", "fft_y_inv", "inv_x", 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-                ("n_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_len", ctypes.c_int32), ("x_points", ctypes.c_int32),
                 ("len", ctypes.c_int32 * 24), ("radix", (ctypes.c_int32 * 8) * 24),
                 ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
 
@@ -239,7 +239,7 @@ def admm_autotune(ctx, reps):
     plans = {}
     for k in range(t.n_len):
         plans[t.len[k]] = [r for r in t.radix[k] if r]
-    return {"tile_y": t.tile_y, "tile_z": t.tile_z, "plans": plans,
+    return {"x_points": t.x_points, "tile_y": t.tile_y, "tile_z": t.tile_z, "plans": plans,
             "ms_default": t.ms_default, "ms_tuned": t.ms_tuned}
 
 

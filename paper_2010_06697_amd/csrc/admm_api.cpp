@@ -98,6 +98,12 @@ size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
 
 int rows_per_block(int n1) { return std::max(1, kThreads / n1); }
 
+// x1-lines per workgroup of the x1 transforms, for about `points` points per
+// workgroup (more lines keep more of the workgroup busy in every radix stage;
+// fewer need less LDS); the autotuner picks `points`
+int rows_per_fft_block(int n1, int points) { return std::max(1, points / n1); }
+int default_fft_points(bool fp64) { return fp64 ? 256 : 1024; }
+
 // Radix sequences for a length n = 2^a 3^b that the autotuner tries: the
 // powers of two split into radix-8, -4 and at most one radix-2 stage, the
 // threes into radix-3 stages, every distinct order of each split (at most
@@ -243,6 +249,7 @@ struct admm_ctx {
   hipStream_t cap_stream = nullptr;
   // per-cell workgroup counts of the x2 / x3 passes depend on the tile widths
   std::vector<int> blk_h;
+  int xpoints = 0;  // points per workgroup of the x1 transforms
 };
 
 namespace {
@@ -322,7 +329,7 @@ void drop_graphs(admm_ctx *c) {
 }
 
 // tile widths of the x2 / x3 passes: workgroup prefix tables (blk_h holds
-// the x, y, z and u tables, n_rve + 1 entries each), grid sizes, upload
+// the x, y, z, u and f tables, n_rve + 1 entries each), grid sizes, upload
 int set_tiles(admm_ctx *c, int ty, int tz) {
   const int n = c->n_rve;
   int *by = c->blk_h.data() + (n + 1), *bz = c->blk_h.data() + 2 * (n + 1);
@@ -355,6 +362,31 @@ int set_plan(admm_ctx *c, const Plan1D &p) {
       }
   }
   HIP_TRY(hipMemcpyAsync(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * c->n_rve,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  return ADMM_OK;
+}
+
+// points per workgroup of the x1 transforms: lines per workgroup of every
+// cell, prefix table, grid size and LDS
+int set_xpoints(admm_ctx *c, int points) {
+  const int n = c->n_rve;
+  int *bf = c->blk_h.data() + 4 * (n + 1);
+  bf[0] = 0;
+  int lds = 0;
+  for (int r = 0; r < n; ++r) {
+    RveDesc &D = c->desc_h[r];
+    D.rows_f = rows_per_fft_block(D.n1, points);
+    bf[r + 1] = bf[r] + (D.n2 * D.n3 + D.rows_f - 1) / D.rows_f;
+    lds = std::max(lds, 2 * ((3 * D.rows_f + 1) / 2) * D.n1);
+  }
+  c->L.nblk_f = bf[n];
+  c->L.lds_x = (size_t)lds * (c->fp64 ? sizeof(double2) : sizeof(float2));
+  c->xpoints = points;
+  HIP_TRY(hipMemcpyAsync(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->blk_d, c->blk_h.data(), sizeof(int) * c->blk_h.size(),
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   drop_graphs(c);
@@ -491,6 +523,7 @@ std::vector<int> lengths_of(const admm_ctx *c) {
 void report_tuning(const admm_ctx *c, admm_tuning *out) {
   out->tile_y = c->L.tile_y;
   out->tile_z = c->L.tile_z;
+  out->x_points = c->xpoints;
   const std::vector<int> n = lengths_of(c);
   out->n_len = (int32_t)std::min<size_t>(n.size(), 24);
   for (int k = 0; k < out->n_len; ++k) {
@@ -515,6 +548,24 @@ int tune(admm_ctx *c, int reps, admm_tuning *out) {
   if (rc != ADMM_OK) return rc;
   out->ms_default = best;
   const int cand[4] = {d / 4, d / 2, d, 2 * d};
+  // points per workgroup of the x1 transforms (LDS <= 64 KiB)
+  {
+    int keep = c->xpoints;
+    for (int pts : {256, 512, 1024}) {
+      if (pts == keep || 2 * ((3 * (size_t)std::max(1, pts / 4) + 1) / 2) * 4 * csz > 65536)
+        continue;
+      rc = set_xpoints(c, pts);
+      double t = 0.0;
+      if (rc == ADMM_OK) rc = time_project(c, reps, &t);
+      if (rc != ADMM_OK) return rc;
+      if (t < best) {
+        best = t;
+        keep = pts;
+      }
+    }
+    rc = set_xpoints(c, keep);
+    if (rc != ADMM_OK) return rc;
+  }
   // tile width of the x2 pass, then of the x3 pass (LDS <= 64 KiB)
   for (int pass = 0; pass < 2 && rc == ADMM_OK; ++pass) {
     const int nmax = pass == 0 ? c->L.n2max : c->L.n3max;
@@ -697,8 +748,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   // descriptors and workgroup prefix tables
   const int B = tile_b(fp64);
   c->desc_h.resize(n_rve);
-  std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1);
-  bx[0] = by[0] = bz[0] = bu[0] = 0;
+  std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1), bf(n_rve + 1);
+  bx[0] = by[0] = bz[0] = bu[0] = bf[0] = 0;
   size_t spec_off = 0;
   int n2max = 0, n3max = 0, lds_x = 0;
   for (int r = 0; r < n_rve; ++r) {
@@ -712,6 +763,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.V = (long long)D.n1 * D.n2 * D.n3;
     D.S = (long long)D.n3 * D.n2 * D.m1;
     D.rows = rows_per_block(D.n1);
+    D.rows_f = rows_per_fft_block(D.n1, default_fft_points(fp64));
     D.p1 = make_plan(D.n1);
     D.p2 = make_plan(D.n2);
     D.p3 = make_plan(D.n3);
@@ -729,13 +781,14 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     for (int k = 0; k < 9; ++k) D.Ebar[k] = R.Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
     const int nrows = D.n2 * D.n3;
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
+    bf[r + 1] = bf[r] + (nrows + D.rows_f - 1) / D.rows_f;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
     bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) *
                             ((D.n3 + kVoxelsPerThread - 1) / kVoxelsPerThread);
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
-    lds_x = std::max(lds_x, 2 * ((3 * D.rows + 1) / 2) * D.n1);
+    lds_x = std::max(lds_x, 2 * ((3 * D.rows_f + 1) / 2) * D.n1);
   }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
@@ -746,19 +799,22 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   c->L.nblk_z = bz[n_rve];
   c->L.tile_y = c->L.tile_z = B;
   c->L.nblk_u = bu[n_rve];
+  c->L.nblk_f = bf[n_rve];
+  c->xpoints = default_fft_points(fp64);
   c->L.n2max = n2max;
   c->L.n3max = n3max;
   c->L.lds_x = (size_t)lds_x * csz;
 
   INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
   INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
-  INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 4 * (n_rve + 1)));
+  INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 5 * (n_rve + 1)));
   std::vector<int> &blk_h = c->blk_h;
   blk_h.clear();
   blk_h.insert(blk_h.end(), bx.begin(), bx.end());
   blk_h.insert(blk_h.end(), by.begin(), by.end());
   blk_h.insert(blk_h.end(), bz.begin(), bz.end());
   blk_h.insert(blk_h.end(), bu.begin(), bu.end());
+  blk_h.insert(blk_h.end(), bf.begin(), bf.end());
   INIT_TRY(hipMemcpy(c->blk_d, blk_h.data(), sizeof(int) * blk_h.size(), hipMemcpyHostToDevice));
 
   std::vector<Material> mh(n_mat);
@@ -796,6 +852,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.blk_y = c->blk_d + (n_rve + 1);
   A.blk_z = c->blk_d + 2 * (n_rve + 1);
   A.blk_u = c->blk_d + 3 * (n_rve + 1);
+  A.blk_f = c->blk_d + 4 * (n_rve + 1);
   A.mats = c->mats_d;
   A.tw = c->tw_d;
   A.partials = c->partials_d;

@@ -25,8 +25,8 @@ struct RveDesc {
   int n1, n2, n3, m1;       // m1 = n1/2 + 1 (half spectrum along x1)
   long long V;              // voxels
   long long S;              // complex entries of one spectral component
-  int rows;                 // x1-rows per workgroup of the x-pass kernels
-  int pad0;
+  int rows;                 // x1-lines per workgroup of the per-voxel kernels
+  int rows_f;               // x1-lines per workgroup of the x1 transforms
   Plan1D p1, p2, p3;
   const uint8_t *phase;
   void *u[2];               // displacement fluctuation, ping-pong

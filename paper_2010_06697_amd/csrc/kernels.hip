@@ -218,12 +218,12 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   using C = typename cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const int r = find_rve(a.blk_f, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   const RveState *st = a.state + r;
   if (!st->active) return;
-  const int b = blk - a.blk_x[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int b = blk - a.blk_f[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f, m1 = D.m1;
   const int nrows = n2 * n3;
   const int row0 = b * R;
   const int ncl = (3 * R + 1) / 2;
@@ -235,10 +235,11 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
 
   for (int w = t; w < ncl * n1; w += nthr) za[w] = C{(T)0, (T)0};
   __syncthreads();
-  const int row = t / n1, x1 = t - row * n1;
-  const int grow = row0 + row;
-  if (row < R && grow < nrows) {
-    const double irho = 1.0 / st->rho;
+  const double irho = 1.0 / st->rho;
+  for (int v = t; v < R * n1; v += nthr) {
+    const int row = v / n1, x1 = v - row * n1;
+    const int grow = row0 + row;
+    if (grow >= nrows) continue;
     const int x2 = grow % n2, x3 = grow / n2;
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     const T *Eg = static_cast<const T *>(D.E);
@@ -422,12 +423,12 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   using C = typename cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const int r = find_rve(a.blk_f, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   const RveState *st = a.state + r;
   if (!st->active) return;
-  const int b = blk - a.blk_x[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows, m1 = D.m1;
+  const int b = blk - a.blk_f[r];
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f, m1 = D.m1;
   const int nrows = n2 * n3;
   const int row0 = b * R;
   const int ncl = (3 * R + 1) / 2;
@@ -763,7 +764,7 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
     case Part::Project: {
       {
         Timed tm(L, K_DIV_FWDX);
-        hipLaunchKernelGGL((k_div_fwdx<T>), dim3(L.nblk_x), blk, L.lds_x, L.stream, a);
+        hipLaunchKernelGGL((k_div_fwdx<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
       }
       {
         Timed tm(L, K_FFT_Y_FWD);
@@ -779,7 +780,7 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       }
       {
         Timed tm(L, K_INV_X);
-        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_x), blk, L.lds_x, L.stream, a);
+        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
       }
       break;
     }

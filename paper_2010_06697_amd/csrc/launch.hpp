@@ -14,6 +14,7 @@ struct KernelArgs {
   const int *blk_y;
   const int *blk_z;
   const int *blk_u;
+  const int *blk_f;  // the x1-transform kernels (div_fwdx, inv_x)
   const Material *mats;
   const void *tw;       // twiddle pool (float2 or double2)
   double4 *partials;    // per update workgroup: sum e^2, sum dd^2, and the failed
@@ -44,7 +45,7 @@ struct KernelTimer {
 struct LaunchCfg {
   KernelTimer *timer;  // null unless profiling
   hipStream_t stream;
-  int nblk_x, nblk_y, nblk_z, nblk_u;
+  int nblk_x, nblk_y, nblk_z, nblk_u, nblk_f;
   int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels

@@ -36,6 +36,7 @@ def test_autotune_keeps_state_and_parity(precision):
     cfg = s.autotune(reps=2)
     say("  ", cfg)
     d = 16 if precision == "fp32" else 8
+    assert cfg["x_points"] in (256, 512, 1024)
     widths = (d // 4, d // 2, d, 2 * d)
     assert cfg["tile_y"] in widths and cfg["tile_z"] in widths
     assert sorted(cfg["plans"]) == sorted({n for sh in shapes for n in sh})
