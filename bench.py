@@ -42,7 +42,7 @@ ALU_PEAK_TFLOPS = 78.6
 LOCAL_FLOPS_BASE = 280
 LOCAL_FLOPS_PER_NEWTON = 1000
 # the 128-cell batch: penalty start and range
-BATCH_RHO0, BATCH_RHO_MIN, BATCH_RHO_MAX = 30.0, 1.0, 100.0
+BATCH_RHO0, BATCH_RHO_MIN, BATCH_RHO_MAX = 30.0, 30.0, 100.0
 
 
 def log(*a):

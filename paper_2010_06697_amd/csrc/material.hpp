@@ -366,9 +366,9 @@ __device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double 
 // kept.
 // ---------------------------------------------------------------------------
 
+// Vv holds the starting basis on entry (B already expressed in it) and the
+// eigenvectors on exit
 __device__ __forceinline__ void jacobi3(double *B, double *Vv) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Vv[k] = (k % 4 == 0) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 30; ++sweep) {
     const double off = B[1] * B[1] + B[2] * B[2] + B[5] * B[5];
     const double dia = B[0] * B[0] + B[4] * B[4] + B[8] * B[8];
@@ -408,7 +408,8 @@ __device__ __forceinline__ void jacobi3(double *B, double *Vv) {
 // minimising director n by the rules above. Returns the size of the top
 // eigenvalue's cluster (1 when it is simple).
 template <typename TG>
-__device__ int director_eig(const TG *E, const double *np, double *n, double *w, double *V) {
+__device__ int director_eig(const TG *E, const double *np, double *n, double *w, double *V,
+                            const double *V0 = nullptr) {
   double F[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
@@ -418,6 +419,26 @@ __device__ int director_eig(const TG *E, const double *np, double *n, double *w,
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+  if (V0) {
+    // start from a nearby eigenbasis (the current iterate's): B <- V0^T B V0
+    // is then almost diagonal and the sweeps converge at once
+    double T[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        T[3 * i + j] = B[3 * i] * V0[j] + B[3 * i + 1] * V0[3 + j] + B[3 * i + 2] * V0[6 + j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        B[3 * i + j] = V0[i] * T[j] + V0[3 + i] * T[3 + j] + V0[6 + i] * T[6 + j];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Vv[k] = V0[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Vv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  }
   jacobi3(B, Vv);
   const double wu[3] = {B[0], B[4], B[8]};
   int o0 = 0, o1 = 1, o2 = 2;  // descending order
@@ -635,7 +656,7 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Et[k] = E[k] + (T)t * d[k];
-      nclt = director_eig(Et, nc, nt, wt, Vt);
+      nclt = director_eig(Et, nc, nt, wt, Vt, V);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         M.n[k] = (T)nt[k];
