@@ -93,19 +93,31 @@ def run_single(case, precision, steps, warmup, profile=True):
     tuning = s.autotune(reps=3)
     log(f"[bench] {precision}: autotuned Step 2 {tuning['ms_default']:.3f} -> "
         f"{tuning['ms_tuned']:.3f} ms (tiles {tuning['tile_y']}/{tuning['tile_z']})")
+    # the tuner drops the captured graphs: capture them again outside the timing
+    s.step(p.check_every)
     torch.cuda.synchronize()
-    if profile:
-        s.profile(True)
     log(f"[bench] {precision}: timing {steps} iterations")
     t0 = time.perf_counter()
     rc, rp, rd, rho = s.step(steps)
     P, _ = s.homogenized_stress(0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = s.profile_read() if profile else {}
+    # per-kernel times: a further run with hipEvents around every launch
+    # (kept out of the timed region above, which replays captured graphs)
+    prof_steps = min(steps, 10) if profile else 0
+    prof = {}
+    newton_before = s.info(0)[3]
+    if profile:
+        s.profile(True)
+        s.step(prof_steps)
+        s.homogenized_stress(0)
+        prof = s.profile_read()
+        s.profile(False)
     it, status, nfail, newton_its = s.info(0)
-    newton_per_voxel_it = newton_its / float(V * (warmup + steps))
-    s.profile(False)
+    # Newton iterations per voxel over the profiled iterations, whose kernel
+    # times the roofline uses
+    newton_per_voxel_it = ((newton_its - newton_before) / float(V * prof_steps) if prof_steps
+                           else newton_its / float(V * (warmup + p.check_every + steps)))
     s.close()
     del s
     torch.cuda.empty_cache()

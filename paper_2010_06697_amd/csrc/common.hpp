@@ -52,7 +52,7 @@ struct RveState {
   unsigned long long newton_iters;  // Newton iterations summed over voxels and iterations
 };
 
-constexpr int kVoxelsPerThread = 4;  // grid-stride depth of the per-voxel reduction kernels
+constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
 
 struct Material {
   int model;  // 0 neo-Hookean, 1 LCE

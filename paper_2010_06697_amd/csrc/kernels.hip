@@ -213,6 +213,17 @@ void k_local(KernelArgs a, IterParams ip) {
 // b = D_h^T (F - Lambda/rho) and its forward FFT along x1
 // ----------------------------------------------------------------------------
 
+// Line rw of divergence workgroup b: its R lines are consecutive along x3
+// at one x2 (so the +-x3 neighbours of the divergence are mostly the
+// workgroup's own lines) when R divides n3, else consecutive rows.
+__device__ __forceinline__ int div_row(int b, int rw, int R, int n2, int n3) {
+  if (n3 % R == 0) {
+    const int zc = b / n2, x2 = b - zc * n2;
+    return (zc * R + rw) * n2 + x2;
+  }
+  return b * R + rw;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   using C = typename cplx<T>::type;
@@ -238,8 +249,8 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   const double irho = 1.0 / st->rho;
   for (int v = t; v < R * n1; v += nthr) {
     const int row = v / n1, x1 = v - row * n1;
-    const int grow = row0 + row;
-    if (grow >= nrows) continue;
+    if (row0 + row >= nrows) continue;
+    const int grow = div_row(b, row, R, n2, n3);
     const int x2 = grow % n2, x3 = grow / n2;
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     const T *Eg = static_cast<const T *>(D.E);
@@ -273,11 +284,13 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
     const int la = 2 * p, lb = 2 * p + 1;
     {
       const int c = la / R, rw = la - c * R;
-      if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Av;
+      if (row0 + rw < nrows)
+        spec[c * S + (long long)div_row(b, rw, R, n2, n3) * m1 + m] = Av;
     }
     if (lb < 3 * R) {
       const int c = lb / R, rw = lb - c * R;
-      if (row0 + rw < nrows) spec[c * S + (long long)(row0 + rw) * m1 + m] = Bv;
+      if (row0 + rw < nrows)
+        spec[c * S + (long long)div_row(b, rw, R, n2, n3) * m1 + m] = Bv;
     }
   }
 }
