@@ -149,3 +149,29 @@ def test_lce_fp32_homogenized_stress(name, tol):
     rc, st, P, o, Po = run_both(name, "fp32", 6)
     say("lce fp32", name, "rel P", rel(P, Po))
     assert rel(P, Po) <= tol
+
+
+def test_lce_load_path_matches_oracle_fp64():
+    """Two load increments of the uniaxial path through admm_set_load (u, F,
+    Lambda, the director and rho kept as the warm start), three iterations
+    each, against the oracle's two runs on the same state."""
+    phase, n0 = polydomain(16, 6, seed=7)
+    loads = [M.uniaxial_lce(1.05), M.uniaxial_lce(1.1)]
+    rho = 10.0
+    s = lce_solver(phase, n0, loads[0], "fp64", rho0=rho, mu_ref=1.0)
+    u, F, L = O.initial_state(phase.shape)
+    n = n0.copy()
+    for k, Fb in enumerate(loads):
+        say("lce load step", k)
+        if k:
+            s.set_load(0, Fb)
+        rc, _, _, _ = s.step(3)
+        assert rc == admm.OK
+        p = O.params(max_iter=3, fixed_iters=True, mu_ref=1.0, newton=O.newton_opts(**NEWTON64))
+        O.admm_run(phase, omats(LCE), Fb.ravel(), p, u, F, L, rho, director_field=n)
+    st = s.state(0)
+    s.close()
+    errs = {k: rel(st[k], o) for k, o in (("u", u), ("F", F), ("Lambda", L), ("director", n))}
+    say("  rel", errs)
+    assert errs["u"] <= 1e-10 and errs["F"] <= 1e-10 and errs["Lambda"] <= 1e-10
+    assert errs["director"] <= 1e-9
