@@ -1,0 +1,95 @@
+"""Writes the stored expected values under tests/golden/ from the CPU oracle.
+
+Every number here comes from oracle/ (the plain double-precision ADMM of
+Sec. 2.1 / Algorithm 1 with the Fourier-space Step 2 of Sec. 2.3) run on the
+seeded synthetic inputs of paper_2010_06697_amd.microstructure; nothing
+comes from the GPU library. Run from the repository root:
+
+    python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import oracle as O  # noqa: E402
+from paper_2010_06697_amd import microstructure as M  # noqa: E402
+
+NEWTON64 = dict(gtol=1e-14, step_tol=1e-10)
+
+
+def omats(mats):
+    return [O.material(m["model"], mu=m["mu"], lam=m["lam"], a=m["a"], kappa=m["kappa"])
+            for m in mats]
+
+
+def laminate16():
+    case = M.laminate16_case()
+    u, F, L = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=200, tol_p=1e-8, tol_d=1e-8, mu_ref=5.5, newton=O.newton_opts(**NEWTON64))
+    r = O.admm_run(case["phase"], omats(case["materials"]), case["loads"][0].ravel(), p, u, F, L, 5.0)
+    P = O.mean_stress(case["phase"], omats(case["materials"]), F)
+    return {"source": "oracle ADMM (Sec. 2.1, Algorithm 1; Step 2 as in Sec. 2.3) on the 16^3 "
+                      "laminate, stiff (10, 100) / soft (1, 10), Fbar = diag(1, 1, 0.95), rho = 5, "
+                      "200 iterations or r_p, r_d <= 1e-8, mu_ref = 5.5",
+            "iters": r["iters"], "rc": r["rc"], "r_p": r["r_p"][:20].tolist(),
+            "r_d": r["r_d"][:20].tolist(), "P_mean": P.tolist()}
+
+
+def lce16():
+    out = {"source": "oracle ADMM with the LCE local problem (neo-classical energy of Sec. 5.1, "
+                     "a = 2, mu = 1, kappa = 100, joint F / director minimisation) on a 16^3 "
+                     "polydomain of 6 Voronoi grains (seed 7), rho = 10, 4 iterations",
+           "cases": {}}
+    for stretch in (1.0, 1.02):
+        g, d = M.voronoi_grains(n=16, n_grains=6, seed=7)
+        n = M.director_field(g, d)
+        phase = np.zeros(g.shape, np.uint8)
+        mats = [M.lce(1.0, 2.0, 100.0)]
+        u, F, L = O.initial_state(phase.shape)
+        p = O.params(max_iter=4, fixed_iters=True, mu_ref=1.0, newton=O.newton_opts(**NEWTON64))
+        r = O.admm_run(phase, omats(mats), M.uniaxial_lce(stretch).ravel(), p, u, F, L, 10.0,
+                       director_field=n)
+        P = O.mean_stress(phase, omats(mats), F, director_field=n)
+        out["cases"][str(stretch)] = {"r_p": r["r_p"].tolist(), "r_d": r["r_d"].tolist(),
+                                      "P_mean": P.tolist()}
+    return out
+
+
+def wavy32():
+    phase = M.wavy_laminate(n=32, period=8, stiff=2, amp=0.5)
+    mats = [M.neohooke(100.0, 1000.0), M.neohooke(1.0, 10.0)]
+    mu_ref = 0.25 * 100.0 + 0.75
+    u, F, L = O.initial_state(phase.shape)
+    rho = 10.0
+    steps = []
+    for k in (1, 2, 3):
+        Fb = np.diag([1.0, 1.0, 1.0 - 0.005 * k])
+        p = O.params(max_iter=600, tol_p=1e-8, tol_d=1e-8, mu_ref=mu_ref, adapt_rho=True,
+                     rho_min=1.0, rho_max=100.0, newton=O.newton_opts(**NEWTON64))
+        r = O.admm_run(phase, omats(mats), Fb.ravel(), p, u, F, L, rho)
+        rho = r["rho"]
+        P = O.mean_stress(phase, omats(mats), F)
+        steps.append({"Fbar33": 1.0 - 0.005 * k, "iters": r["iters"], "rc": r["rc"], "rho": rho,
+                      "P_mean": P.tolist()})
+    return {"source": "oracle ADMM (Sec. 2.1, adaptive penalty, kappa 1.3, tau 10, rho in "
+                      "[1, 100]) on the 32^3 wavy laminate (stiff 2 / period 8, interface "
+                      "amplitude 0.5, mu contrast 100, lambda = 10 mu), three load steps "
+                      "Fbar = diag(1, 1, 1 - 0.005 k) each to 1e-8, warm-started",
+            "steps": steps,
+            "u_norm": float(np.linalg.norm(u)), "F_norm": float(np.linalg.norm(F))}
+
+
+if __name__ == "__main__":
+    for name, fn in (("oracle_laminate16", laminate16), ("oracle_lce16", lce16),
+                     ("oracle_wavy32", wavy32)):
+        rec = fn()
+        with open(os.path.join(HERE, name + ".json"), "w") as f:
+            json.dump(rec, f, indent=1)
+        print("wrote", name, flush=True)

@@ -316,3 +316,27 @@ def test_wavy_laminate_load_path_matches_oracle():
     st = s.state(0)
     s.close()
     assert rel(st["F"], F) <= 1e-9 and rel(st["u"], u) <= 1e-9
+
+
+def test_laminate16_config_matches_golden():
+    """The same configuration against the oracle's stored run
+    (tests/golden/oracle_laminate16.json): iteration count, the first
+    residuals and <P>."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "oracle_laminate16.json")) as f:
+        g = json.load(f)
+    case = M.laminate16_case()
+    s = gpu_solver([case["phase"]], case["materials"], case["loads"], "fp64",
+                   rho0=5.0, mu_ref=5.5, tol_p=1e-8, tol_d=1e-8, max_iter=200, check_every=10)
+    rc, it, status = s.solve()
+    P, _ = s.homogenized_stress(0)
+    hp, hd, _ = s.history(0)
+    s.close()
+    say("laminate16 golden: iters", it[0], g["iters"], "rel P", rel(P, g["P_mean"]))
+    assert it[0] == g["iters"]
+    assert rel(P, np.array(g["P_mean"])) <= 1e-10
+    n = len(g["r_p"])
+    assert np.allclose(hp[:n], g["r_p"], rtol=1e-9, atol=0)
+    assert np.allclose(hd[:n], g["r_d"], rtol=1e-9, atol=0)
