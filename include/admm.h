@@ -119,6 +119,25 @@ typedef struct {
                            kernel. Profiling (admm_profile_enable) launches
                            every kernel. (1) */
   int32_t reserved;
+  /* Inexact local step (Sec. 2.1, local residual r_l; Sec. 4, the two
+   * strategies compared there). Step 1 runs in passes of at most local_chunk
+   * Newton iterations per voxel, each pass continuing from the previous
+   * iterate (F and, for the LCE, the director), until the pass's test holds
+   * or local_passes passes ran. r_l is reduced inside the local kernel (one
+   * partial sum per workgroup) and tested on the device; the host is not
+   * involved. At most one of local_ratio and local_fraction is nonzero; both
+   * zero: every local problem solved to the Newton tolerances. With either
+   * strategy, admm_solve counts a cell as converged only when r_l <= tol_d
+   * as well (equilibrium needs the local residual small too). */
+  double local_ratio;   /* > 0: from the second iteration of a load step,
+                           stop once r_l = |P(F) - Lambda - rho (grad u - F)|
+                           / mu_ref (RMS over the cell) <= local_ratio * r_d
+                           of the previous iteration (0) */
+  int32_t local_chunk;  /* Newton iterations per voxel and pass (1) */
+  int32_t local_passes; /* passes per iteration at most (8) */
+  double local_fraction; /* in (0, 1]: every iteration, stop once the local
+                           Newton solves (their own stopping rule) have
+                           converged at >= local_fraction of the voxels (0) */
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;

@@ -39,7 +39,10 @@ class Params(ctypes.Structure):
                 ("adapt_rho", ctypes.c_int), ("tol_p", ctypes.c_double),
                 ("tol_d", ctypes.c_double), ("mu_ref", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("newton", Newton)]
+                ("newton", Newton), ("local_ratio", ctypes.c_double),
+                ("local_chunk", ctypes.c_int), ("local_passes", ctypes.c_int),
+                ("local_start_iter", ctypes.c_int), ("local_rd_prev", ctypes.c_double),
+                ("local_fraction", ctypes.c_double)]
 
 
 _lib = None
@@ -106,8 +109,12 @@ def newton_opts(max_iter=100, gtol=1e-15, step_tol=1e-10):
 
 def params(rho_min=1.0, rho_max=50.0, kappa_rho=1.3, tau=10.0, adapt_rho=False,
            tol_p=1e-8, tol_d=1e-8, mu_ref=1.0, max_iter=200, fixed_iters=False,
-           newton=None):
+           newton=None, local_ratio=0.0, local_chunk=1, local_passes=8, local_start_iter=0,
+           local_rd_prev=0.0, local_fraction=0.0):
     p = Params()
+    p.local_ratio, p.local_chunk, p.local_passes = local_ratio, local_chunk, local_passes
+    p.local_start_iter, p.local_rd_prev = local_start_iter, local_rd_prev
+    p.local_fraction = local_fraction
     p.rho_min, p.rho_max, p.kappa_rho, p.tau = rho_min, rho_max, kappa_rho, tau
     p.adapt_rho = int(bool(adapt_rho))
     p.tol_p, p.tol_d, p.mu_ref = tol_p, tol_d, mu_ref

@@ -752,31 +752,101 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
 
   int rc = p->fixed_iters ? OR_OK : OR_NOT_CONVERGED;
   int done = 0, fails = 0, dom = 0;
+  double rd_prev = p->local_rd_prev;
+  double *g2 = (double *)malloc(V * sizeof(double));
+  if (!g2) {
+    free(Gold); free(Gnew); free(H);
+    return OR_EINVAL;
+  }
+  if (p->local_ratio < 0.0 || p->local_fraction < 0.0 || p->local_fraction > 1.0 ||
+      (p->local_ratio > 0.0 && p->local_fraction > 0.0) ||
+      ((p->local_ratio > 0.0 || p->local_fraction > 0.0) &&
+       (p->local_chunk < 1 || p->local_passes < 1))) {
+    free(Gold); free(Gnew); free(H); free(g2);
+    return OR_EINVAL;
+  }
   for (int it = 0; it < p->max_iter; ++it) {
     double r = *rho;
-    /* Step 1: F_{i+1} = argmin W(F) + rho/2 |F - (grad u_i + Lambda_i / rho)|^2 */
-#pragma omp parallel for schedule(static) reduction(+ : fails, dom)
-    for (long xl = 0; xl < (long)V; ++xl) {
-      size_t x = (size_t)xl;
-      double A[9], Fx[9], nx[3] = {0.0, 0.0, 1.0};
-      for (int c = 0; c < 9; ++c) {
-        A[c] = Gold[c * V + x] + Lambda[c * V + x] / r;
-        Fx[c] = F[c * V + x];
+    double rl = 0.0; /* r_l after Step 1 (0 when solved exactly) */
+    const int inexact = p->local_fraction > 0.0 ||
+                        (p->local_ratio > 0.0 && p->local_start_iter + it > 0);
+    if (inexact) {
+      /* Step 1 solved inexactly: passes of at most local_chunk Newton
+         iterations per voxel until r_l <= local_ratio * r_d (previous), or
+         until the local solves have converged at local_fraction of the voxels */
+      or_newton chunk = p->newton;
+      chunk.max_iter = p->local_chunk;
+      for (int pass = 0; pass < p->local_passes; ++pass) {
+        long conv = 0;
+#pragma omp parallel for schedule(static) reduction(+ : dom, conv)
+        for (long xl = 0; xl < (long)V; ++xl) {
+          size_t x = (size_t)xl;
+          double A[9], Fx[9], nx[3] = {0.0, 0.0, 1.0}, P[9];
+          for (int c = 0; c < 9; ++c) {
+            A[c] = Gold[c * V + x] + Lambda[c * V + x] / r;
+            Fx[c] = F[c * V + x];
+          }
+          if (director)
+            for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
+          const or_material *m = &mats[phase[x]];
+          int its = 0;
+          int pr = or_prox(m, r, A, &chunk, Fx, nx, &its);
+          if (pr == OR_OK) conv += 1;
+          if (pr == OR_EDOMAIN || or_stress(m, Fx, nx, P) != OR_OK) {
+            dom += 1;
+            g2[x] = 0.0;
+          } else {
+            double s2 = 0.0;
+            for (int c = 0; c < 9; ++c) {
+              double gc = P[c] + r * (Fx[c] - A[c]);
+              s2 += gc * gc;
+            }
+            g2[x] = s2;
+          }
+          for (int c = 0; c < 9; ++c) F[c * V + x] = Fx[c];
+          if (director)
+            for (int c = 0; c < 3; ++c) director[c * V + x] = nx[c];
+        }
+        if (dom) break;
+        double sl = 0.0;
+        for (size_t x = 0; x < V; ++x) sl += g2[x];
+        rl = sqrt(sl / (double)V) / p->mu_ref;
+        if (p->local_fraction > 0.0) {
+          if ((double)conv >= p->local_fraction * (double)V) break;
+        } else {
+          if (rl <= p->local_ratio * rd_prev) break;
+        }
       }
-      if (director)
-        for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
-      int its = 0;
-      int pr = or_prox(&mats[phase[x]], r, A, &p->newton, Fx, nx, &its);
-      if (pr == OR_NOT_CONVERGED) fails += 1;
-      if (pr == OR_EDOMAIN) dom += 1;
-      for (int c = 0; c < 9; ++c) F[c * V + x] = Fx[c];
-      if (director)
-        for (int c = 0; c < 3; ++c) director[c * V + x] = nx[c];
-    }
-    if (dom) {
-      rc = OR_EDOMAIN;
-      done = it;
-      break;
+      if (dom) {
+        rc = OR_EDOMAIN;
+        done = it;
+        break;
+      }
+    } else {
+      /* Step 1: F_{i+1} = argmin W(F) + rho/2 |F - (grad u_i + Lambda_i / rho)|^2 */
+#pragma omp parallel for schedule(static) reduction(+ : fails, dom)
+      for (long xl = 0; xl < (long)V; ++xl) {
+        size_t x = (size_t)xl;
+        double A[9], Fx[9], nx[3] = {0.0, 0.0, 1.0};
+        for (int c = 0; c < 9; ++c) {
+          A[c] = Gold[c * V + x] + Lambda[c * V + x] / r;
+          Fx[c] = F[c * V + x];
+        }
+        if (director)
+          for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
+        int its = 0;
+        int pr = or_prox(&mats[phase[x]], r, A, &p->newton, Fx, nx, &its);
+        if (pr == OR_NOT_CONVERGED) fails += 1;
+        if (pr == OR_EDOMAIN) dom += 1;
+        for (int c = 0; c < 9; ++c) F[c * V + x] = Fx[c];
+        if (director)
+          for (int c = 0; c < 3; ++c) director[c * V + x] = nx[c];
+      }
+      if (dom) {
+        rc = OR_EDOMAIN;
+        done = it;
+        break;
+      }
     }
     /* Step 2: -Lap u_{i+1} = div(-F_{i+1} + Lambda_i / rho) */
     for (size_t k = 0; k < 9 * V; ++k) H[k] = F[k] - Lambda[k] / r;
@@ -798,6 +868,7 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
     if (hist_rp) hist_rp[it] = rp;
     if (hist_rd) hist_rd[it] = rd;
     if (hist_rho) hist_rho[it] = r;
+    rd_prev = rd;
     double *t = Gold;
     Gold = Gnew;
     Gnew = t;
@@ -806,7 +877,9 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
       rc = OR_EDOMAIN;
       break;
     }
-    if (!p->fixed_iters && rp <= p->tol_p && rd <= p->tol_d) {
+    /* with an inexact Step 1, equilibrium also needs a small local residual
+       (the appendix bounds it by the dual and local residuals together) */
+    if (!p->fixed_iters && rp <= p->tol_p && rd <= p->tol_d && rl <= p->tol_d) {
       rc = OR_OK;
       break;
     }
@@ -817,6 +890,7 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
   free(Gold);
   free(Gnew);
   free(H);
+  free(g2);
   return rc;
 }
 

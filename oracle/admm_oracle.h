@@ -65,6 +65,26 @@ typedef struct {
   int max_iter;            /* iteration cap */
   int fixed_iters;         /* 1: run exactly max_iter iterations, no test */
   or_newton newton;
+  /* Inexact local step (the two strategies of Sec. 2.1 and Sec. 4): Step 1
+   * runs in passes of at most local_chunk Newton iterations per voxel, each
+   * pass continuing from the previous iterate (F and, for the LCE, the
+   * director), until the pass's stopping test holds or local_passes passes
+   * have run.
+   *   local_ratio > 0 (the strategy the paper adopts): every iteration but
+   *     the first of a load step; the test is r_l <= local_ratio r_d, where
+   *     r_l = |P(F) - Lambda - rho (grad u - F)| / mu_ref (RMS over voxels)
+   *     and r_d is the previous iteration's dual residual.
+   *   local_fraction > 0: every iteration; the test is that the local Newton
+   *     solve has converged (its own stopping rule) at no fewer than
+   *     local_fraction V voxels.
+   * Both zero: exact local solves. At most one of them is nonzero. With an
+   * inexact Step 1 the convergence test also requires r_l <= tol_d. */
+  double local_ratio;
+  int local_chunk;
+  int local_passes;
+  int local_start_iter;    /* index of this call's first iteration in the load step */
+  double local_rd_prev;    /* r_d of the iteration before it (when local_start_iter > 0) */
+  double local_fraction;
 } or_params;
 
 /* ---- small pieces, exposed so that tests can pin each one ---- */

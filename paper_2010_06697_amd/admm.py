@@ -65,6 +65,8 @@ class Params(ctypes.Structure):
                 ("adapt_rho", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("newton_max", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("local_ratio", ctypes.c_double), ("local_chunk", ctypes.c_int32),
+                ("local_passes", ctypes.c_int32), ("local_fraction", ctypes.c_double),
 ]
 
 
@@ -259,6 +261,7 @@ def default_params(precision: str = "fp64", **kw) -> Params:
         p.newton_gtol, p.newton_step_tol = 1e-10, 2e-6
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
     p.use_graph = 1
+    p.local_ratio, p.local_chunk, p.local_passes, p.local_fraction = 0.0, 1, 8, 0.0
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)

@@ -234,6 +234,7 @@ struct admm_ctx {
   double *partials18_d = nullptr;
   double *mean_d = nullptr;
   double *hist_d = nullptr;
+  double2 *lpart_d = nullptr;
   int2 *newton_part_d = nullptr;
   void *workspace = nullptr;
   bool own_workspace = false;
@@ -317,6 +318,10 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   ip.hist_cap = c->hist_cap;
   ip.n_rve = c->n_rve;
   ip.n_mat = c->n_mat;
+  ip.local_ratio = p.local_ratio;
+  ip.local_chunk = p.local_chunk;
+  ip.local_passes = p.local_passes;
+  ip.local_fraction = p.local_fraction;
   return ip;
 }
 
@@ -472,6 +477,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->mean_d);
   (void)hipFree(c->hist_d);
   (void)hipFree(c->newton_part_d);
+  (void)hipFree(c->lpart_d);
   if (c->own_workspace) (void)hipFree(c->workspace);
   for (auto &g : c->graph)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -671,7 +677,11 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   if (!(p.rho0 > 0.0) || !(p.rho_min > 0.0) || !(p.rho_max >= p.rho_min) || !(p.kappa_rho > 1.0) ||
       !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
       p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0) ||
-      (p.use_graph != 0 && p.use_graph != 1))
+      (p.use_graph != 0 && p.use_graph != 1) || !(p.local_ratio >= 0.0) ||
+      !(p.local_fraction >= 0.0 && p.local_fraction <= 1.0) ||
+      (p.local_ratio > 0.0 && p.local_fraction > 0.0) ||
+      ((p.local_ratio > 0.0 || p.local_fraction > 0.0) &&
+       (p.local_chunk < 1 || p.local_passes < 1)))
     return ADMM_EINVAL;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
@@ -831,6 +841,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->partials18_d, sizeof(double) * 18 * (size_t)c->L.nblk_u));
   INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
   INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
+  INIT_TRY(hipMalloc(&c->lpart_d, sizeof(double2) * (size_t)c->L.nblk_x));
   INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_u));
   INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_u));
 
@@ -860,6 +871,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.mean_out = c->mean_d;
   A.hist = c->hist_d;
   A.newton_part = c->newton_part_d;
+  A.lpart = c->lpart_d;
   A.n_rve = n_rve;
   A.n_mat = n_mat;
 #undef INIT_TRY

@@ -48,8 +48,10 @@ struct RveState {
   int status;        // 0 running, 1 iteration cap, 2 converged, -5 domain error
   int newton_fail;   // local solves that hit the Newton cap
   int domain_err;    // set when det F <= 0 or NaN met
-  int pad0, pad1;
+  int local_done;    // inexact local step: r_l reached its target (or the pass cap)
+  int pad1;
   unsigned long long newton_iters;  // Newton iterations summed over voxels and iterations
+  double rl;         // local residual after the last inexact pass
 };
 
 constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
@@ -75,6 +77,10 @@ struct IterParams {
   int hist_cap;
   int n_rve;
   int n_mat;
+  double local_ratio;     // inexact local step, r_l <= ratio r_d (0: off)
+  int local_chunk;
+  int local_passes;
+  double local_fraction;  // inexact local step, converged fraction (0: off)
 };
 
 template <typename T> struct cplx;

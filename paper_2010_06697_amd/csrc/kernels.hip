@@ -103,26 +103,40 @@ __device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwave
 // iterations to its.
 template <typename T>
 __device__ int lce_local(T *E, const T *At, const Material &m, double rho, double *n,
-                         const IterParams &ip, int &its) {
+                         const IterParams &ip, int cap, int &its) {
   Lce<T> M;
   M.mua = (T)m.mua;
   M.beta = (T)m.beta;
   M.kappa = (T)m.kappa;
   M.mu = (T)m.mu;
-  const int rc = lce_newton<T>(E, At, M, m.mua * m.beta, (T)rho, n, ip.newton_max, ip.gtol,
-                               ip.step_tol);
-  its += rc >= 0 ? rc : ip.newton_max;
+  const int rc = lce_newton<T>(E, At, M, m.mua * m.beta, (T)rho, n, cap, ip.gtol, ip.step_tol);
+  its += rc >= 0 ? rc : cap;
   return rc;
 }
 
+// inexact local step in force for this cell and iteration: the ratio
+// strategy needs the previous iteration's r_d, so it starts at the second
+// iteration of a load step
+__device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveState *st) {
+  return ip.local_fraction > 0.0 || (ip.local_ratio > 0.0 && st->iter > 0);
+}
+
+// Step 1 for every voxel of the active cells. Exact: one pass, every local
+// problem solved to the Newton tolerances. Inexact: each pass runs at most
+// local_chunk Newton iterations per voxel from its current iterate (F and
+// the director) and writes the workgroup's sum of |local residual|^2 and
+// count of converged solves; passes after the first do nothing once
+// k_local_check has marked the cell done.
 template <typename T, bool ANY_LCE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
-void k_local(KernelArgs a, IterParams ip) {
+void k_local(KernelArgs a, IterParams ip, int pass) {
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_x, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
+  const bool inexact = local_inexact(ip, st);
+  if (pass > 0 && (!inexact || st->local_done)) return;
   const int b = blk - a.blk_x[r];
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
   const int nrows = n2 * n3;
@@ -131,6 +145,7 @@ void k_local(KernelArgs a, IterParams ip) {
   const int row = t / n1, x1 = t - row * n1;
   const int grow = b * R + row;
   int n_fail = 0, n_its = 0;
+  double lsum[2] = {0.0, 0.0};  // |local residual|^2, converged
   if (row < R && grow < nrows) {
     const double rho = st->rho;
     const double irho = 1.0 / rho;
@@ -151,6 +166,7 @@ void k_local(KernelArgs a, IterParams ip) {
     const int ph = D.phase[idx];
     if (ph < a.n_mat) {
       const Material m = a.mats[ph];
+      const int cap = inexact ? ip.local_chunk : ip.newton_max;
       int rc;
       if (ANY_LCE && m.model == 1) {
         T *dg = static_cast<T *>(D.dir);
@@ -159,24 +175,46 @@ void k_local(KernelArgs a, IterParams ip) {
         n[0] *= nn;
         n[1] *= nn;
         n[2] *= nn;
-        rc = lce_local<T>(E, At, m, rho, n, ip, n_its);
+        rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its);
         dg[idx] = (T)n[0];
         dg[V + idx] = (T)n[1];
         dg[2 * V + idx] = (T)n[2];
+        if (inexact && rc != -2) {
+          Lce<T> M;
+          M.mua = (T)m.mua;
+          M.beta = (T)m.beta;
+          M.kappa = (T)m.kappa;
+          M.mu = (T)m.mu;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            M.n[k] = (T)n[k];
+            M.nd[k] = n[k];
+          }
+          Point<T> sp;
+          if (M.point(E, At, (T)rho, sp)) lsum[0] = (double)sp.gn2;
+        }
       } else {
         NeoHooke<T> M;
         M.mu = (T)m.mu;
         M.lam = (T)m.lam;
-        rc = newton<T, T>(E, At, M, (T)rho, ip.newton_max, ip.gtol, ip.step_tol);
-        n_its = rc >= 0 ? rc : ip.newton_max;
+        rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol, &lsum[0]);
+        n_its = rc >= 0 ? rc : cap;
       }
-      n_fail = rc == -1;
+      lsum[1] = rc >= 0 ? 1.0 : 0.0;
+      n_fail = rc == -1 && !inexact;  // a pass that ends at its cap is no failure
       if (rc == -2) atomicOr(&st->domain_err, 1);
 #pragma unroll
       for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
     } else {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
+  }
+  // local residual of the inexact passes: one sum per workgroup
+  if (inexact) {
+    __shared__ double gred[2 * (kThreads / 64)];
+    block_sum<2>(lsum, gred);
+    if (t == 0) a.lpart[blk] = make_double2(lsum[0], lsum[1]);
+    __syncthreads();
   }
   // Newton statistics: summed per workgroup and added to one slot of the
   // update kernel's tiling (atomics from every wave on one address per cell
@@ -206,6 +244,43 @@ void k_local(KernelArgs a, IterParams ip) {
     const int slot = a.blk_u[r] + (x3 / kVoxelsPerThread) * ((n2 + R - 1) / R) + x2 / R;
     if (f) atomicAdd(&a.newton_part[slot].x, f);
     if (s) atomicAdd(&a.newton_part[slot].y, s);
+  }
+}
+
+// After inexact pass `pass`, from the workgroups' partial sums (fixed order):
+// the ratio strategy takes r_l = RMS |local residual| / mu_ref over the cell
+// and marks the cell done once r_l <= local_ratio r_d (r_d of the previous
+// iteration); the fraction strategy once the converged local solves number
+// at least local_fraction V. The last pass always ends Step 1. Exact local
+// steps mark every cell done.
+__global__ __launch_bounds__(kThreads) void k_local_check(KernelArgs a, IterParams ip, int pass) {
+  __shared__ double red[2 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  RveState *st = a.state + r;
+  if (!st->active) return;
+  if (!local_inexact(ip, st)) {
+    if (threadIdx.x == 0) {
+      st->local_done = 1;
+      st->rl = 0.0;
+    }
+    return;
+  }
+  if (pass > 0 && st->local_done) return;
+  const int x0 = a.blk_x[r], nx = a.blk_x[r + 1] - x0;
+  double v[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+    const double2 q = a.lpart[x0 + k];
+    v[0] += q.x;
+    v[1] += q.y;
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    const double Vc = (double)a.desc[r].V;
+    const double rl = sqrt(v[0] / Vc) / ip.mu_ref;
+    st->rl = rl;
+    const bool met = ip.local_fraction > 0.0 ? v[1] >= ip.local_fraction * Vc
+                                             : rl <= ip.local_ratio * st->rd;
+    st->local_done = (met || pass + 1 >= ip.local_passes) ? 1 : 0;
   }
 }
 
@@ -602,7 +677,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
     st->active = 0;
     return;
   }
-  if (ip.test_conv && rp <= ip.tol_p && rd <= ip.tol_d) {
+  // with an inexact local step, equilibrium also needs a small local
+  // residual (bounded, with r_d, by the appendix's identity)
+  const bool local_ok =
+      !(ip.local_ratio > 0.0 || ip.local_fraction > 0.0) || st->rl <= ip.tol_d;
+  if (ip.test_conv && rp <= ip.tol_p && rd <= ip.tol_d && local_ok) {
     st->status = 2;  // converged
     st->active = 0;
     return;
@@ -768,10 +847,16 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
   switch (part) {
     case Part::Local: {
       Timed tm(L, K_LOCAL);
-      if (L.any_lce)
-        hipLaunchKernelGGL((k_local<T, true>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
-      else
-        hipLaunchKernelGGL((k_local<T, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip);
+      const bool inexact = ip.local_ratio > 0.0 || ip.local_fraction > 0.0;
+      const int passes = inexact ? ip.local_passes : 1;
+      for (int pass = 0; pass < passes; ++pass) {
+        if (L.any_lce)
+          hipLaunchKernelGGL((k_local<T, true>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, pass);
+        else
+          hipLaunchKernelGGL((k_local<T, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, pass);
+        if (inexact)
+          hipLaunchKernelGGL(k_local_check, dim3(a.n_rve), blk, 0, L.stream, a, ip, pass);
+      }
       break;
     }
     case Part::Project: {

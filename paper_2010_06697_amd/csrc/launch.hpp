@@ -22,6 +22,8 @@ struct KernelArgs {
   double *partials18;   // per workgroup: sums of P and Lambda
   double *mean_out;     // per cell: <P>, <Lambda>
   double *hist;         // per cell, per iteration: r_p, r_d, rho
+  double2 *lpart;       // per local workgroup, inexact passes: (sum of |local
+                        // residual|^2, count of converged local solves)
   int2 *newton_part;    // per update workgroup: failed solves and Newton iterations
                         // of the local-step workgroups in its tile
   int n_rve;

@@ -234,17 +234,11 @@ __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 
 constexpr __host__ __device__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Newton solve of the local problem at fixed material data M. E: warm start
-// in, minimiser out. Stops when |grad phi| <= gtol (moduli + rho)(1 + |F| + |A|)
-// before a step, or after a full positive-definite Newton step with
-// |dE| <= step_tol max(1, |F|) (which leaves an error of order |dE|^2).
-// Returns the iteration count (>= 0), -1 when the cap or the line search gave
-// up (E keeps the last accepted iterate), -2 when det F <= 0 at the start.
+// The iterations of newton() from the point s at E; on exit s is the point
+// of the returned iterate.
 template <typename TG, typename TH, typename M>
-__device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
-                      double step_tol) {
-  Point<TG> s;
-  if (!m.point(E, A, rho, s)) return -2;
+__device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
+                           double step_tol, Point<TG> &s) {
   const double smod = m.smod() + (double)rho;
   const double nA = sqrt((double)norm2_ipx(A));
   const double tol_step2 = step_tol * step_tol;
@@ -356,6 +350,24 @@ __device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double 
     if (pd && t == 1.0 && nd2 <= tol_step2 * fmax(1.0, (double)norm2_ipx(E))) return it + 1;
   }
   return -1;
+}
+
+// Newton solve of the local problem at fixed material data M. E: warm start
+// in, minimiser out. Stops when |grad phi| <= gtol (moduli + rho)(1 + |F| + |A|)
+// before a step, or after a full positive-definite Newton step with
+// |dE| <= step_tol max(1, |F|) (which leaves an error of order |dE|^2).
+// Returns the iteration count (>= 0), -1 when the cap or the line search gave
+// up (E keeps the last accepted iterate; a second call with the remaining
+// budget continues the same iterates), -2 when det F <= 0 at the start.
+// g2 (optional) receives |grad phi|^2 at the returned iterate.
+template <typename TG, typename TH, typename M>
+__device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
+                      double step_tol, double *g2 = nullptr) {
+  Point<TG> s;
+  if (!m.point(E, A, rho, s)) return -2;
+  int ret = newton_loop<TG, TH>(E, A, m, rho, maxit, gtol, step_tol, s);
+  if (g2) *g2 = (double)s.gn2;
+  return ret;
 }
 
 // ---------------------------------------------------------------------------

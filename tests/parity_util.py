@@ -45,11 +45,13 @@ NEWTON64 = dict(gtol=1e-14, step_tol=1e-10)
 
 
 def oracle_iterations(phase, mats, Fbar, n_iter, rho, mu_ref, adapt=False, state=None,
-                      rho_min=1.0, rho_max=50.0):
+                      rho_min=1.0, rho_max=50.0, **local):
+    """n_iter fixed iterations of the oracle from `state` (default: the
+    initial state); `local` takes the inexact local step's local_* options."""
     u, F, L = state if state is not None else O.initial_state(phase.shape)
     u, F, L = u.copy(), F.copy(), L.copy()
     p = O.params(max_iter=n_iter, fixed_iters=True, mu_ref=mu_ref, adapt_rho=adapt,
-                 rho_min=rho_min, rho_max=rho_max, newton=O.newton_opts(**NEWTON64))
+                 rho_min=rho_min, rho_max=rho_max, newton=O.newton_opts(**NEWTON64), **local)
     r = O.admm_run(phase, omats(mats), np.asarray(Fbar).ravel(), p, u, F, L, rho)
     return u, F, L, r
 

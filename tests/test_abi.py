@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(admm.Material) == 40
     assert ctypes.sizeof(admm.Rve) == 16 + 6 * 8 + 72
-    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4
+    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4 + 8 + 2 * 4 + 8
 
 
 @pytest.mark.parametrize("n,ok", [((16, 16, 16), True), ((256, 256, 256), True),
@@ -88,6 +88,13 @@ def test_init_rejects_invalid_arguments_before_touching_the_gpu():
     assert _init(good, m, admm.default_params(kappa_rho=1.0)) == admm.EINVAL
     assert _init(good, m, admm.default_params(max_iter=0)) == admm.EINVAL
     assert _init(good, m, admm.default_params(use_graph=2)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_ratio=-0.1)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_ratio=0.3, local_chunk=0)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_ratio=0.3, local_passes=0)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_fraction=1.5)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_fraction=-0.5)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_fraction=0.5, local_chunk=0)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(local_ratio=0.3, local_fraction=0.5)) == admm.EINVAL
     assert _init(good, [admm.material(mu=-1.0)], p) == admm.EINVAL
     # an LCE phase needs a director field
     assert _init(good, [admm.material("lce", mu=1.0, a=2.0, kappa=1.0)], p) == admm.EINVAL

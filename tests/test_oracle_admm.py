@@ -257,3 +257,176 @@ def test_adaptive_penalty_recovers_from_a_poor_start():
         assert r["rc"] == O.OK
         iters[adapt] = r["iters"]
     assert iters[True] < 0.5 * iters[False]
+
+
+def test_inexact_local_step_limits():
+    """The inexact local step (Sec. 2.1, local residual held to a fraction of
+    r_d): with a vanishing ratio and enough passes it reproduces the exact
+    solves; with the paper's ratio 0.3 the iteration still converges to the
+    same fixed point, the laminate's exact finite-strain solution."""
+    case = M.laminate16_case()
+    mats = mats_of(case["materials"])
+    Fb = case["loads"][0].ravel()
+    newton = O.newton_opts(gtol=1e-14, step_tol=1e-10)
+    u0, F0, L0 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=12, fixed_iters=True, mu_ref=5.5, newton=newton)
+    O.admm_run(case["phase"], mats, Fb, p, u0, F0, L0, 5.0)
+    u1, F1, L1 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=12, fixed_iters=True, mu_ref=5.5, newton=newton,
+                 local_ratio=1e-30, local_chunk=1, local_passes=60)
+    O.admm_run(case["phase"], mats, Fb, p, u1, F1, L1, 5.0)
+    assert np.max(np.abs(F1 - F0)) <= 1e-12
+    assert np.max(np.abs(u1 - u0)) <= 1e-12 * max(1.0, np.max(np.abs(u0)))
+    # ratio 0.3, one Newton iteration per pass: same converged state
+    u2, F2, L2 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=400, tol_p=1e-10, tol_d=1e-10, mu_ref=5.5, newton=newton,
+                 local_ratio=0.3, local_chunk=1, local_passes=4)
+    r = O.admm_run(case["phase"], mats, Fb, p, u2, F2, L2, 5.0)
+    assert r["rc"] == O.OK
+    d, Pd = laminate_exact(10.0, 100.0, 1.0, 10.0, 0.95)
+    P2 = O.mean_stress(case["phase"], mats, F2)
+    assert np.max(np.abs(P2[[0, 4, 8]] - Pd)) <= 1e-8 * np.max(np.abs(Pd))
+
+
+def test_inexact_parity_cases_are_far_from_ties():
+    """The GPU parity cases of the inexact local step compare pass decisions
+    (r_l <= ratio r_d, or converged count >= fraction V) taken from sums in
+    different orders; on those cases the oracle's result does not move when
+    the ratio moves by 1e-9 relative or the fraction by 1.5 voxels, so
+    rounding of the sums (or one voxel counted differently) cannot flip a
+    decision."""
+    from parity_util import oracle_iterations
+    from test_gpu_inexact import CASES, N_ITER, inexact_case
+    for shape, loc, _ in CASES:
+        phase, Fbar, mats, rho, mu_ref = inexact_case(shape, loc)
+        V = phase.size
+        if "local_ratio" in loc:
+            moved = [dict(loc, local_ratio=loc["local_ratio"] * f) for f in (1 + 1e-9, 1 - 1e-9)]
+        else:
+            moved = [dict(loc, local_fraction=loc["local_fraction"] + f / V) for f in (1.5, -1.5)]
+        out = [oracle_iterations(phase, mats, Fbar, N_ITER, rho, mu_ref, **kw)[1]
+               for kw in [loc] + moved]
+        assert np.array_equal(out[1], out[0]) and np.array_equal(out[2], out[0]), (shape, loc)
+
+
+def nodal_stress(mats, phase, F, director=None):
+    shape = phase.shape
+    P = np.empty_like(F)
+    for x in np.ndindex(shape):
+        n = (0.0, 0.0, 1.0) if director is None else director[(slice(None),) + x]
+        P[(slice(None),) + x] = O.stress(mats[phase[x]], F[(slice(None),) + x], n)
+    return P
+
+
+@pytest.mark.parametrize("lce", [False, True])
+def test_truncated_local_step_satisfies_the_appendix_identity(lce):
+    """One iteration whose Step 1 is cut to one Newton iteration per voxel
+    (one pass; the previous r_d is taken huge so the ratio test passes at
+    once). With g = W_F(F_{i+1}) - Lambda_i - rho (grad u_i - F_{i+1}) the
+    local residual, Steps 2-3 give W_F(F_{i+1}) = g + Lambda_{i+1} -
+    rho (grad u_{i+1} - grad u_i), so (the appendix's identity)
+    D_h^T W_F(F_{i+1}) = D_h^T g - rho D_h^T (grad u_{i+1} - grad u_i), with g
+    far from zero. For the LCE, W_F is the stress at the updated director."""
+    shape = (6, 4, 8)
+    phase = M.random_two_phase(shape, 0.4, seed=5)
+    if lce:
+        mats = [O.material("lce", mu=1.0, a=2.0, kappa=50.0),
+                O.material("neohooke", mu=10.0, lam=40.0)]
+        Fbar = np.diag([1.15, 1.15 ** -0.5, 1.15 ** -0.5]).ravel()
+        rng = np.random.default_rng(9)
+        d = rng.standard_normal((3,) + shape)
+        d /= np.linalg.norm(d, axis=0, keepdims=True)
+    else:
+        mats = [O.material("neohooke", mu=10.0, lam=40.0), O.material("neohooke", mu=1.0, lam=4.0)]
+        Fbar = M.random_fbar(0.08, seed=2).ravel()
+        d = None
+    rho = 12.0
+    u, F, L = O.initial_state(shape)
+    O.admm_run(phase, mats, Fbar, O.params(max_iter=2, fixed_iters=True, mu_ref=4.0),
+               u, F, L, rho, director_field=d)
+    u0, L0 = u.copy(), L.copy()
+    p = O.params(max_iter=1, fixed_iters=True, mu_ref=4.0, local_ratio=0.3, local_chunk=1,
+                 local_passes=4, local_start_iter=2, local_rd_prev=1e30)
+    O.admm_run(phase, mats, Fbar, p, u, F, L, rho, director_field=d)
+    P = nodal_stress(mats, phase, F, d)
+    G0 = O.gradient(u0, Fbar)
+    G1 = O.gradient(u, Fbar)
+    g = P - L0 - rho * (G0 - F)
+    assert np.max(np.abs(g)) >= 1e-4
+    assert np.max(np.abs(div_h(L))) <= 1e-12 * max(1.0, np.max(np.abs(L)))
+    lhs = div_h(P)
+    rhs = div_h(g) - rho * div_h(G1 - G0)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-10 * max(1.0, np.max(np.abs(lhs)))
+
+
+def test_converged_fraction_strategy_limits():
+    """The converged-fraction strategy (Sec. 4: proceed once a given fraction
+    of points has converged): fraction 1 with enough passes is the exact
+    iteration; fraction 0.5 with two Newton iterations per pass converges to
+    the laminate's exact solution."""
+    case = M.laminate16_case()
+    mats = mats_of(case["materials"])
+    Fb = case["loads"][0].ravel()
+    newton = O.newton_opts(gtol=1e-14, step_tol=1e-10)
+    u0, F0, L0 = O.initial_state(case["phase"].shape)
+    O.admm_run(case["phase"], mats, Fb, O.params(max_iter=12, fixed_iters=True, mu_ref=5.5,
+                                                 newton=newton), u0, F0, L0, 5.0)
+    u1, F1, L1 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=12, fixed_iters=True, mu_ref=5.5, newton=newton,
+                 local_fraction=1.0, local_chunk=1, local_passes=60)
+    O.admm_run(case["phase"], mats, Fb, p, u1, F1, L1, 5.0)
+    assert np.max(np.abs(F1 - F0)) <= 1e-12
+    # one pass of one iteration: far from the exact iteration
+    u2, F2, L2 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=12, fixed_iters=True, mu_ref=5.5, newton=newton,
+                 local_fraction=1.0, local_chunk=1, local_passes=1)
+    O.admm_run(case["phase"], mats, Fb, p, u2, F2, L2, 5.0)
+    assert np.max(np.abs(F2 - F0)) >= 1e-6
+    u3, F3, L3 = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=600, tol_p=1e-10, tol_d=1e-10, mu_ref=5.5, newton=newton,
+                 local_fraction=0.5, local_chunk=2, local_passes=8)
+    r = O.admm_run(case["phase"], mats, Fb, p, u3, F3, L3, 5.0)
+    assert r["rc"] == O.OK
+    d, Pd = laminate_exact(10.0, 100.0, 1.0, 10.0, 0.95)
+    P3 = O.mean_stress(case["phase"], mats, F3)
+    assert np.max(np.abs(P3[[0, 4, 8]] - Pd)) <= 1e-8 * np.max(np.abs(Pd))
+
+
+def test_inexact_options_are_validated():
+    shape = (4, 4, 4)
+    phase = np.zeros(shape, np.uint8)
+    mats = [O.material("neohooke", mu=1.0, lam=1.0)]
+    for kw in (dict(local_ratio=-1.0), dict(local_fraction=1.5), dict(local_fraction=-0.1),
+               dict(local_ratio=0.3, local_fraction=0.5), dict(local_ratio=0.3, local_chunk=0),
+               dict(local_fraction=0.5, local_passes=0)):
+        u, F, L = O.initial_state(shape)
+        r = O.admm_run(phase, mats, np.eye(3).ravel(), O.params(max_iter=1, **kw), u, F, L, 1.0)
+        assert r["rc"] == O.EINVAL, kw
+
+
+def test_inexact_lce_reaches_the_exact_fixed_point():
+    """LCE polydomain with a stiff inclusion under a stretch 1.2: the
+    iteration with truncated joint (F, director) solves, r_l held to 0.3 r_d,
+    converges to the state the exact iteration converges to."""
+    shape = (8, 8, 8)
+    g, dirs = M.voronoi_grains(n=8, n_grains=4, seed=3)
+    d0 = M.director_field(g, dirs)
+    phase = np.zeros(shape, np.uint8)
+    z, y, x = np.indices(shape)
+    phase[(x - 3.5) ** 2 + (y - 3.5) ** 2 + (z - 3.5) ** 2 <= 4.0] = 1
+    mats = [O.material("lce", mu=1.0, a=2.0, kappa=50.0), O.material("neohooke", mu=10.0, lam=40.0)]
+    Fbar = np.diag([1.2, 1.2 ** -0.5, 1.2 ** -0.5]).ravel()
+    newton = O.newton_opts(gtol=1e-14, step_tol=1e-10)
+    out = []
+    for loc in ({}, dict(local_ratio=0.3, local_chunk=1, local_passes=4)):
+        u, F, L = O.initial_state(shape)
+        d = d0.copy()
+        p = O.params(max_iter=3000, tol_p=1e-9, tol_d=1e-9, mu_ref=1.0, newton=newton,
+                     adapt_rho=True, rho_min=1.0, rho_max=100.0, **loc)
+        r = O.admm_run(phase, mats, Fbar, p, u, F, L, 10.0, director_field=d)
+        assert r["rc"] == O.OK, loc
+        out.append((F, d, O.mean_stress(phase, mats, F, director_field=d)))
+    assert np.max(np.abs(out[1][0] - out[0][0])) <= 1e-7
+    assert np.max(np.abs(np.einsum("i...,j...->ij...", out[1][1], out[1][1])
+                         - np.einsum("i...,j...->ij...", out[0][1], out[0][1]))) <= 1e-7
+    assert np.max(np.abs(out[1][2] - out[0][2])) <= 1e-8
