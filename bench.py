@@ -11,7 +11,8 @@ every field resident in HBM before it starts.
 Also reported on the same line: the all-double form at 256^3, the 128-cell
 batch (edges 32..96, one load step each to tol 1e-6) as cell solves/s, the
 256^3 LCE polydomain, the 64^3 wavy laminate's 30-step compression path in
-double and in float, the per-kernel times from hipEvents on the library's
+double and in float, the inexact local step against exact local solves (on
+the fibre cell and the LCE polydomain), the per-kernel times from hipEvents on the library's
 stream, the roofline of the dominant kernel, and the CPU oracle timed on the
 host on a bounded sample.
 """
@@ -223,6 +224,84 @@ def run_lce(steps, warmup):
     return out
 
 
+INEXACT = dict(local_ratio=0.3, local_chunk=1, local_passes=4)
+
+
+def run_inexact(fibres, lce_steps=10, lce_warmup=3):
+    """The inexact local step (r_l <= 0.3 r_d, one Newton iteration per voxel
+    and pass, at most 4 passes) against exact local solves: on the 256^3
+    fibre cell the time to solve the second shear increment to tol 1e-6 in
+    float (after solving the first, which also captures the graphs), and on
+    the 256^3 LCE polydomain the time per iteration over fixed iterations
+    (that cell does not converge within a bench-sized budget) with the
+    residuals both reach."""
+    import torch
+    from paper_2010_06697_amd import admm, microstructure as M
+
+    out = {"options": dict(INEXACT)}
+    V = fibres["phase"].size
+    res = {}
+    for name, loc in (("exact", {}), ("inexact", INEXACT)):
+        p = admm.default_params("fp32", rho0=fibres["rho0"], rho_min=fibres["rho_min"],
+                                rho_max=fibres["rho_max"], adapt_rho=1, mu_ref=fibres["mu_ref"],
+                                tol_p=fibres["tol_fp32"], tol_d=fibres["tol_fp32"], max_iter=3000,
+                                **loc)
+        s = admm.Solver([fibres["phase"]], fibres["materials"], [fibres["loads"][0]], p,
+                        precision="fp32")
+        s.solve()
+        s.set_load(0, fibres["loads"][1])
+        torch.cuda.synchronize()
+        log(f"[bench] inexact: fibres256 fp32 {name}, second increment")
+        t0 = time.perf_counter()
+        rc, it, st = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P = s.homogenized_stress(0)[0]
+        n_its = s.info(0)[3]
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        res[name] = {"seconds": dt, "iterations": int(it[0]), "converged": int(st[0]) == admm.OK,
+                     "newton_iters_per_voxel_iteration": n_its / float(V * max(1, int(it[0]))),
+                     "P": P}
+    dP = float(np.abs(res["inexact"]["P"] - res["exact"]["P"]).max() /
+               np.abs(res["exact"]["P"]).max())
+    for r in res.values():
+        r.pop("P")
+    out["fibres256_fp32_increment2"] = dict(res, speedup=res["exact"]["seconds"] /
+                                            res["inexact"]["seconds"], P_rel_diff=dP)
+    log(f"[bench] inexact: fibres speedup {out['fibres256_fp32_increment2']['speedup']:.3f}")
+
+    case = M.lce_polydomain_case()
+    V = case["phase"].size
+    res = {}
+    for name, loc in (("exact", {}), ("inexact", INEXACT)):
+        p = admm.default_params("fp32", rho0=case["rho0"], rho_min=1.0, rho_max=50.0, adapt_rho=1,
+                                mu_ref=case["mu_ref"], **loc)
+        s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
+                        precision="fp32", directors=[case["director0"]])
+        s.step(lce_warmup)
+        s.step(p.check_every)  # captures the graphs outside the timing
+        torch.cuda.synchronize()
+        before = s.info(0)[3]
+        log(f"[bench] inexact: lce256 fp32 {name}, {lce_steps} iterations")
+        t0 = time.perf_counter()
+        rc, rp, rd, rho = s.step(lce_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_its = s.info(0)[3] - before
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        res[name] = {"ms_per_step": 1e3 * dt / lce_steps, "value": V * lce_steps / dt,
+                     "r_p": float(rp[0]), "r_d": float(rd[0]),
+                     "newton_iters_per_voxel_iteration": n_its / float(V * lce_steps)}
+    out["lce256_fp32"] = dict(res, speedup=res["exact"]["ms_per_step"] /
+                              res["inexact"]["ms_per_step"])
+    log(f"[bench] inexact: lce speedup {out['lce256_fp32']['speedup']:.3f}")
+    return out
+
+
 def run_wavy():
     """The 64^3 wavy laminate under uniaxial compression to 0.85 in 30 load
     steps, each solved to 1e-7, in double and in float with double
@@ -317,6 +396,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lce", action="store_true")
     ap.add_argument("--no-wavy", action="store_true")
+    ap.add_argument("--no-inexact", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed region "
                          "(reference kernel for the HBM counters)")
@@ -353,6 +433,7 @@ def main():
     batch = None if args.no_batch else run_batch(128)
     lce = None if args.no_lce else run_lce(10, 3)
     wavy = None if args.no_wavy else run_wavy()
+    inexact = None if args.no_inexact else run_inexact(case)
 
     # roofline of the dominant kernel (by total time in the timed region)
     kb = kernel_bytes_per_voxel(4, c)
@@ -418,6 +499,7 @@ def main():
         "autotune": f32["autotune"],
         "rve_batch": batch,
         "lce256": lce,
+        "inexact_local_step": inexact,
         "wavy64": wavy,
         "roofline": roof,
         "iteration_roofline": it_roof,

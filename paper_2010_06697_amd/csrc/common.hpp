@@ -55,6 +55,7 @@ struct RveState {
 };
 
 constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
+constexpr int kLocalPassGrid = 2048;  // workgroups of the later inexact local passes
 
 struct Material {
   int model;  // 0 neo-Hookean, 1 LCE

@@ -121,16 +121,15 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
   return ip.local_fraction > 0.0 || (ip.local_ratio > 0.0 && st->iter > 0);
 }
 
-// Step 1 for every voxel of the active cells. Exact: one pass, every local
-// problem solved to the Newton tolerances. Inexact: each pass runs at most
-// local_chunk Newton iterations per voxel from its current iterate (F and
-// the director) and writes the workgroup's sum of |local residual|^2 and
-// count of converged solves; passes after the first do nothing once
-// k_local_check has marked the cell done.
+// Step 1 on the voxels of logical workgroup `blk`. Exact: one pass, every
+// local problem solved to the Newton tolerances. Inexact: each pass runs at
+// most local_chunk Newton iterations per voxel from its current iterate (F
+// and the director) and stores the workgroup's sum of |local residual|^2 and
+// count of converged solves, which k_local_check reduces. Passes after the
+// first do nothing once the cell is done.
 template <typename T, bool ANY_LCE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
-void k_local(KernelArgs a, IterParams ip, int pass) {
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams &ip, int pass,
+                                           int blk) {
   const int r = find_rve(a.blk_x, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
@@ -209,7 +208,10 @@ void k_local(KernelArgs a, IterParams ip, int pass) {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
   }
-  // local residual of the inexact passes: one sum per workgroup
+  // local residual of the inexact passes: one sum per workgroup (a fence
+  // and arrival counter per workgroup, to let the last one decide, cost
+  // more than a separate one-workgroup-per-cell kernel: the agent-scope
+  // release writes back the XCD's L2)
   if (inexact) {
     __shared__ double gred[2 * (kThreads / 64)];
     block_sum<2>(lsum, gred);
@@ -247,12 +249,29 @@ void k_local(KernelArgs a, IterParams ip, int pass) {
   }
 }
 
+// Step 1. The first pass runs one logical workgroup per workgroup; later
+// inexact passes, which often find the cell done, run a smaller grid over
+// logical workgroups blockIdx.x, blockIdx.x + gridDim.x, ... (a multiple of
+// 8 workgroups, so each logical workgroup keeps its XCD).
+template <typename T, bool ANY_LCE, bool STRIDED>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
+void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
+  if (!STRIDED) {
+    local_tile<T, ANY_LCE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
+    return;
+  }
+  for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
+    local_tile<T, ANY_LCE>(a, ip, pass, xcd_remap(lb, nblk));
+    __syncthreads();  // LDS of this tile read before the next one writes it
+  }
+}
+
 // After inexact pass `pass`, from the workgroups' partial sums (fixed order):
 // the ratio strategy takes r_l = RMS |local residual| / mu_ref over the cell
-// and marks the cell done once r_l <= local_ratio r_d (r_d of the previous
+// and ends Step 1 once r_l <= local_ratio r_d (r_d of the previous
 // iteration); the fraction strategy once the converged local solves number
-// at least local_fraction V. The last pass always ends Step 1. Exact local
-// steps mark every cell done.
+// at least local_fraction V. The last pass always ends it. An exact local
+// step marks the cell done with r_l = 0.
 __global__ __launch_bounds__(kThreads) void k_local_check(KernelArgs a, IterParams ip, int pass) {
   __shared__ double red[2 * (kThreads / 64)];
   const int r = blockIdx.x;
@@ -850,10 +869,22 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       const bool inexact = ip.local_ratio > 0.0 || ip.local_fraction > 0.0;
       const int passes = inexact ? ip.local_passes : 1;
       for (int pass = 0; pass < passes; ++pass) {
-        if (L.any_lce)
-          hipLaunchKernelGGL((k_local<T, true>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, pass);
-        else
-          hipLaunchKernelGGL((k_local<T, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, pass);
+        if (pass == 0) {
+          if (L.any_lce)
+            hipLaunchKernelGGL((k_local<T, true, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip,
+                               0, L.nblk_x);
+          else
+            hipLaunchKernelGGL((k_local<T, false, false>), dim3(L.nblk_x), blk, 0, L.stream, a,
+                               ip, 0, L.nblk_x);
+        } else {
+          const int grid = std::min(L.nblk_x, kLocalPassGrid);
+          if (L.any_lce)
+            hipLaunchKernelGGL((k_local<T, true, true>), dim3(grid), blk, 0, L.stream, a, ip, pass,
+                               L.nblk_x);
+          else
+            hipLaunchKernelGGL((k_local<T, false, true>), dim3(grid), blk, 0, L.stream, a, ip,
+                               pass, L.nblk_x);
+        }
         if (inexact)
           hipLaunchKernelGGL(k_local_check, dim3(a.n_rve), blk, 0, L.stream, a, ip, pass);
       }
