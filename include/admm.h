@@ -171,6 +171,22 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve,
  * keeps u, F, Lambda and rho as warm start. Errors: EINVAL (det Fbar <= 0). */
 int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]);
 
+/* Mixed boundary conditions (Sec. 2.3: components of <F> prescribed and the
+ * complementary components of the average stress zero, as in the uniaxial
+ * stress and plane stress protocols of Sec. 5). Bit k (k = 3i + j, row-major)
+ * of free_mask leaves <F>_ij of cell `rve` free: Step 2 minimises over it as
+ * well as over u, which sets it to the average of F - Lambda/rho, and the
+ * multiplier update then keeps the average of Lambda_ij at zero, so that
+ * <P>_ij = 0 at convergence. Free components start from their current value
+ * (the load given to admm_init or admm_set_load, or the last iterate);
+ * admm_set_load afterwards changes only the prescribed components. 0 (the
+ * default): <F> prescribed. Errors: EINVAL (mask >= 512). */
+int admm_set_free(admm_ctx *ctx, int32_t rve, uint32_t free_mask);
+
+/* The current <F> of cell `rve` (row-major): the prescribed load and the free
+ * components' iterate. Synchronises the stream. */
+int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]);
+
 /* Sets the penalty of one cell (rve >= 0) or of all cells (rve < 0). */
 int admm_set_rho(admm_ctx *ctx, int32_t rve, double rho);
 

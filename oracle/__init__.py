@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("newton", Newton), ("local_ratio", ctypes.c_double),
                 ("local_chunk", ctypes.c_int), ("local_passes", ctypes.c_int),
                 ("local_start_iter", ctypes.c_int), ("local_rd_prev", ctypes.c_double),
-                ("local_fraction", ctypes.c_double)]
+                ("local_fraction", ctypes.c_double), ("free_mask", ctypes.c_uint)]
 
 
 _lib = None
@@ -110,11 +110,14 @@ def newton_opts(max_iter=100, gtol=1e-15, step_tol=1e-10):
 def params(rho_min=1.0, rho_max=50.0, kappa_rho=1.3, tau=10.0, adapt_rho=False,
            tol_p=1e-8, tol_d=1e-8, mu_ref=1.0, max_iter=200, fixed_iters=False,
            newton=None, local_ratio=0.0, local_chunk=1, local_passes=8, local_start_iter=0,
-           local_rd_prev=0.0, local_fraction=0.0):
+           local_rd_prev=0.0, local_fraction=0.0, free=()):
+    """free: indices k = 3i + j of the components of <F> left free (mixed
+    boundary conditions); the others are prescribed."""
     p = Params()
     p.local_ratio, p.local_chunk, p.local_passes = local_ratio, local_chunk, local_passes
     p.local_start_iter, p.local_rd_prev = local_start_iter, local_rd_prev
     p.local_fraction = local_fraction
+    p.free_mask = sum(1 << int(k) for k in set(free))
     p.rho_min, p.rho_max, p.kappa_rho, p.tau = rho_min, rho_max, kappa_rho, tau
     p.adapt_rho = int(bool(adapt_rho))
     p.tol_p, p.tol_d, p.mu_ref = tol_p, tol_d, mu_ref
@@ -222,7 +225,8 @@ def rho_update(rho, r_p, r_d, p):
 def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None):
     """Runs ADMM iterations in place on (u, F, Lam[, director_field]).
 
-    Returns a dict with rc, iters, rho, and the r_p / r_d / rho histories.
+    Returns a dict with rc, iters, rho, the r_p / r_d / rho histories and
+    Fbar (with its free components, if any, as the iteration left them).
     """
     phase = np.ascontiguousarray(phase, dtype=np.uint8)
     n3, n2, n1 = phase.shape
@@ -236,15 +240,17 @@ def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None):
     it = ctypes.c_int(0)
     nf = ctypes.c_int(0)
     marr = _mats(mats)
+    Fb = np.array(np.asarray(Fbar, dtype=np.float64).reshape(9))
     rc = lib().or_admm_run(n1, n2, n3,
                            phase.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
-                           marr, len(mats), _dp(_vec(Fbar, 9)), ctypes.byref(p),
+                           marr, len(mats), _dp(Fb), ctypes.byref(p),
                            _dp(u), _dp(F), _dp(Lam), _dp(director_field),
                            ctypes.byref(r), _dp(hp), _dp(hd), _dp(hr),
                            ctypes.byref(it), ctypes.byref(nf))
     k = it.value
     return {"rc": rc, "iters": k, "rho": r.value, "r_p": hp[:k].copy(),
-            "r_d": hd[:k].copy(), "rho_hist": hr[:k].copy(), "newton_fail": nf.value}
+            "r_d": hd[:k].copy(), "rho_hist": hr[:k].copy(), "newton_fail": nf.value,
+            "Fbar": Fb}
 
 
 def mean_stress(phase, mats, F, director_field=None, Lam=None):

@@ -728,7 +728,7 @@ double or_rho_update(double rho, double r_p, double r_d, const or_params *p) {
 }
 
 int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
-                const or_material *mats, int n_mat, const double Fbar[9],
+                const or_material *mats, int n_mat, double Fbar[9],
                 const or_params *p, double *u, double *F, double *Lambda,
                 double *director, double *rho, double *hist_rp, double *hist_rd,
                 double *hist_rho, int *iters, int *newton_fail) {
@@ -759,6 +759,7 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
     return OR_EINVAL;
   }
   if (p->local_ratio < 0.0 || p->local_fraction < 0.0 || p->local_fraction > 1.0 ||
+      p->free_mask >= 512u ||
       (p->local_ratio > 0.0 && p->local_fraction > 0.0) ||
       ((p->local_ratio > 0.0 || p->local_fraction > 0.0) &&
        (p->local_chunk < 1 || p->local_passes < 1))) {
@@ -848,9 +849,16 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
         break;
       }
     }
-    /* Step 2: -Lap u_{i+1} = div(-F_{i+1} + Lambda_i / rho) */
+    /* Step 2: -Lap u_{i+1} = div(-F_{i+1} + Lambda_i / rho); a free
+       component of <F> minimises |<F> + D_h u - H|^2 too: the mean of H */
     for (size_t k = 0; k < 9 * V; ++k) H[k] = F[k] - Lambda[k] / r;
     or_project(n1, n2, n3, H, u, NULL);
+    for (int c = 0; c < 9; ++c)
+      if (p->free_mask & (1u << c)) {
+        double sm = 0.0;
+        for (size_t x = 0; x < V; ++x) sm += H[c * V + x];
+        Fbar[c] = sm / (double)V;
+      }
     /* Step 3: Lambda_{i+1} = Lambda_i + rho (grad u_{i+1} - F_{i+1}) */
     or_gradient(n1, n2, n3, u, Fbar, Gnew);
     for (size_t k = 0; k < 9 * V; ++k) Lambda[k] += r * (Gnew[k] - F[k]);

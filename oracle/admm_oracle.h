@@ -85,6 +85,13 @@ typedef struct {
   int local_start_iter;    /* index of this call's first iteration in the load step */
   double local_rd_prev;    /* r_d of the iteration before it (when local_start_iter > 0) */
   double local_fraction;
+  /* Mixed boundary conditions (Sec. 2.3: some components of <F> prescribed,
+   * the complementary components of the average stress zero; the UNI, PE and
+   * EB protocols of Sec. 5): bit k (k = 3i + j) of free_mask leaves <F>_ij
+   * free. Step 2 then minimises the augmented Lagrangian over it as well as
+   * over u, which sets <F>_ij = <F_{i+1} - Lambda_i / rho>_ij, and Step 3
+   * then leaves <Lambda>_ij = 0, so <P>_ij = 0 at convergence. */
+  unsigned free_mask;
 } or_params;
 
 /* ---- small pieces, exposed so that tests can pin each one ---- */
@@ -139,13 +146,14 @@ double or_rho_update(double rho, double r_p, double r_d, const or_params *p);
 /* ---- the whole iteration ---- */
 
 /* Runs ADMM iterations on one periodic cell.
- *   phase: V bytes indexing mats; Fbar: macroscopic gradient (row-major);
+ *   phase: V bytes indexing mats; Fbar: macroscopic gradient (row-major; its
+ *   free components, see free_mask, are updated in place);
  *   u (3V), F (9V), Lambda (9V): state, updated in place; director (3V) or NULL;
  *   rho: in/out penalty; hist_* (max_iter doubles each, may be NULL) receive
  *   r_p, r_d and the rho used at each iteration; iters: iterations done.
  * Returns OR_OK (converged or fixed count done), OR_NOT_CONVERGED, or an error. */
 int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
-                const or_material *mats, int n_mat, const double Fbar[9],
+                const or_material *mats, int n_mat, double Fbar[9],
                 const or_params *p, double *u, double *F, double *Lambda,
                 double *director, double *rho, double *hist_rp,
                 double *hist_rd, double *hist_rho, int *iters,

@@ -25,7 +25,8 @@ NEOHOOKE, LCE = 0, 1
 
 # entry points declared in include/admm.h, in order
 ENTRY_POINTS = (
-    "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_rho",
+    "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_free",
+    "admm_get_fbar", "admm_set_rho",
     "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
     "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
     "admm_profile_read", "admm_autotune", "admm_strerror", "admm_destroy",
@@ -90,6 +91,8 @@ def lib():
                                 ctypes.POINTER(Material), i32, ctypes.POINTER(Params), i32,
                                 vp, ctypes.c_size_t, vp]
         L.admm_set_load.argtypes = [vp, i32, dp]
+        L.admm_set_free.argtypes = [vp, i32, ctypes.c_uint32]
+        L.admm_get_fbar.argtypes = [vp, i32, dp]
         L.admm_set_rho.argtypes = [vp, i32, ctypes.c_double]
         L.admm_step.argtypes = [vp, i32, dp, dp, dp]
         L.admm_solve.argtypes = [vp, ip, ip]
@@ -159,6 +162,22 @@ def admm_init(rves, mats, params: Params, precision: int, workspace_ptr=None,
 def admm_set_load(ctx, rve: int, Fbar) -> int:
     F = np.ascontiguousarray(np.asarray(Fbar, np.float64).reshape(9))
     return _check(lib().admm_set_load(ctx, rve, _dptr(F)), "admm_set_load")
+
+
+def free_mask(free) -> int:
+    """Bit mask of free components of <F> from indices k = 3i + j."""
+    return sum(1 << int(k) for k in set(free))
+
+
+def admm_set_free(ctx, rve: int, free) -> int:
+    """free: indices k = 3i + j of the components of <F> left free."""
+    return _check(lib().admm_set_free(ctx, rve, free_mask(free)), "admm_set_free")
+
+
+def admm_get_fbar(ctx, rve: int) -> np.ndarray:
+    F = np.zeros(9)
+    _check(lib().admm_get_fbar(ctx, rve, _dptr(F)), "admm_get_fbar")
+    return F
 
 
 def admm_set_rho(ctx, rve: int, rho: float) -> int:
@@ -347,6 +366,12 @@ class Solver:
     # -- iteration --
     def set_load(self, rve, Fbar):
         admm_set_load(self.ctx, rve, Fbar)
+
+    def set_free(self, rve, free):
+        admm_set_free(self.ctx, rve, free)
+
+    def fbar(self, rve=0):
+        return admm_get_fbar(self.ctx, rve)
 
     def set_rho(self, rho, rve=-1):
         admm_set_rho(self.ctx, rve, rho)

@@ -235,6 +235,7 @@ struct admm_ctx {
   double *mean_d = nullptr;
   double *hist_d = nullptr;
   double2 *lpart_d = nullptr;
+  double *fpart_d = nullptr;
   int2 *newton_part_d = nullptr;
   void *workspace = nullptr;
   bool own_workspace = false;
@@ -478,6 +479,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->hist_d);
   (void)hipFree(c->newton_part_d);
   (void)hipFree(c->lpart_d);
+  (void)hipFree(c->fpart_d);
   if (c->own_workspace) (void)hipFree(c->workspace);
   for (auto &g : c->graph)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -788,7 +790,6 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.dir = R.director;
     D.spec = static_cast<char *>(c->workspace) + spec_off;
     spec_off += spec_bytes(D.n1, D.n2, D.n3, fp64);
-    for (int k = 0; k < 9; ++k) D.Ebar[k] = R.Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
     const int nrows = D.n2 * D.n3;
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     bf[r + 1] = bf[r] + (nrows + D.rows_f - 1) / D.rows_f;
@@ -803,6 +804,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
   c->L.any_lce = any_lce;
+  c->L.any_free = false;
   c->L.stream = c->stream;
   c->L.nblk_x = bx[n_rve];
   c->L.nblk_y = by[n_rve];
@@ -842,6 +844,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
   INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
   INIT_TRY(hipMalloc(&c->lpart_d, sizeof(double2) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMalloc(&c->fpart_d, sizeof(double) * 9 * (size_t)c->L.nblk_x));
   INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_u));
   INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_u));
 
@@ -852,6 +855,10 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     s.rho_used = p.rho0;
     s.active = 1;
     s.status = ST_RUNNING;
+    for (int k = 0; k < 9; ++k) {
+      s.Ebar[k] = rves[r].Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+      s.Ebar_prev[k] = s.Ebar[k];
+    }
   }
   INIT_TRY(hipMalloc(&c->state_d, sizeof(RveState) * n_rve));
   INIT_TRY(hipMemcpy(c->state_d, c->state_h.data(), sizeof(RveState) * n_rve, hipMemcpyHostToDevice));
@@ -872,6 +879,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.hist = c->hist_d;
   A.newton_part = c->newton_part_d;
   A.lpart = c->lpart_d;
+  A.fpart = c->fpart_d;
   A.n_rve = n_rve;
   A.n_mat = n_mat;
 #undef INIT_TRY
@@ -888,13 +896,13 @@ void admm_destroy(admm_ctx *ctx) {
 int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
   if (!ctx || !Fbar || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
   if (!valid_fbar(Fbar)) return ADMM_EINVAL;
-  RveDesc &D = ctx->desc_h[rve];
+  RveState &s = ctx->state_h[rve];
+  // prescribed components take the new load; free ones keep their iterate
   for (int k = 0; k < 9; ++k) {
     ctx->rves[rve].Fbar[k] = Fbar[k];
-    D.Ebar[k] = Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+    if (!((s.free_mask >> k) & 1u)) s.Ebar[k] = Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+    s.Ebar_prev[k] = s.Ebar[k];
   }
-  HIP_TRY(hipMemcpyAsync(ctx->desc_d + rve, &D, sizeof(RveDesc), hipMemcpyHostToDevice, ctx->stream));
-  RveState &s = ctx->state_h[rve];
   s.iter = 0;
   s.active = 1;
   s.status = ST_RUNNING;
@@ -904,6 +912,32 @@ int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
   int rc = upload_states(ctx);
   if (rc != ADMM_OK) return rc;
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ADMM_OK;
+}
+
+int admm_set_free(admm_ctx *ctx, int32_t rve, uint32_t free_mask) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve || free_mask >= 512u) return ADMM_EINVAL;
+  RveState &s = ctx->state_h[rve];
+  s.free_mask = free_mask;
+  for (int k = 0; k < 9; ++k) s.Ebar_prev[k] = s.Ebar[k];
+  bool any = false;
+  for (const auto &q : ctx->state_h) any = any || q.free_mask != 0;
+  if (any != ctx->L.any_free) {
+    drop_graphs(ctx);  // the launch sequence changes
+    ctx->L.any_free = any;
+  }
+  int rc = upload_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ADMM_OK;
+}
+
+int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]) {
+  if (!ctx || !Fbar_out || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
+  int rc = download_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  for (int k = 0; k < 9; ++k)
+    Fbar_out[k] = ctx->state_h[rve].Ebar[k] + ((k % 4 == 0) ? 1.0 : 0.0);
   return ADMM_OK;
 }
 

@@ -34,7 +34,6 @@ struct RveDesc {
   void *Lam;                // multiplier
   void *dir;                // director (LCE) or null
   void *spec;               // 9 spectral components, layout [c][x3][x2][m1]
-  double Ebar[9];           // Fbar - I
 };
 
 // per-cell iteration state, updated on the device
@@ -52,6 +51,10 @@ struct RveState {
   int pad1;
   unsigned long long newton_iters;  // Newton iterations summed over voxels and iterations
   double rl;         // local residual after the last inexact pass
+  double Ebar[9];       // <F> - I of the current iterate (free components move)
+  double Ebar_prev[9];  // <F> - I of the previous iterate (r_d)
+  unsigned free_mask;   // bit k: component k of <F> free (mixed conditions)
+  int pad2;
 };
 
 constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling

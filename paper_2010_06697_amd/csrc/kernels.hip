@@ -160,7 +160,7 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       E[c] = Eg[c * V + idx];
-      At[c] = (T)(A[c] + D.Ebar[c] + (double)Lg[c * V + idx] * irho);
+      At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
     }
     const int ph = D.phase[idx];
     if (ph < a.n_mat) {
@@ -207,6 +207,29 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
     } else {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
+  }
+  // mixed conditions: this workgroup's sums of F_{i+1} - I - Lambda_i/rho,
+  // read back from memory (cache hits) after the solve rather than carried
+  // through it in registers
+  if (st->free_mask) {
+    __shared__ double hred[9 * (kThreads / 64)];
+    double hsum[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) hsum[c] = 0.0;
+    if (row < R && grow < nrows) {
+      const T *Eg = static_cast<const T *>(D.E);
+      const T *Lg = static_cast<const T *>(D.Lam);
+      const int idx = grow * n1 + x1;
+      const double irho = 1.0 / st->rho;
+#pragma unroll
+      for (int c = 0; c < 9; ++c)
+        hsum[c] = (double)Eg[c * V + idx] - (double)Lg[c * V + idx] * irho;
+    }
+    block_sum<9>(hsum, hred);
+    if (t == 0)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) a.fpart[(size_t)blk * 9 + c] = hsum[c];
+    __syncthreads();
   }
   // local residual of the inexact passes: one sum per workgroup (a fence
   // and arrival counter per workgroup, to let the last one decide, cost
@@ -263,6 +286,37 @@ void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
     local_tile<T, ANY_LCE>(a, ip, pass, xcd_remap(lb, nblk));
     __syncthreads();  // LDS of this tile read before the next one writes it
+  }
+}
+
+// Mixed conditions (Sec. 2.3; the UNI/PE/EB protocols of Sec. 5): Step 2
+// minimises over the free components of <F> as well as over u, which gives
+// <F>_k = <F_{i+1} - Lambda_i/rho>_k; the multiplier update then keeps
+// <Lambda>_k = 0 (zero average stress at convergence). One workgroup per
+// cell sums the local workgroups' partials in a fixed order; the previous
+// <F> is kept for r_d.
+__global__ __launch_bounds__(kThreads) void k_fbar(KernelArgs a) {
+  __shared__ double red[9 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  RveState *st = a.state + r;
+  if (!st->active) return;
+  const unsigned m = st->free_mask;
+  if (!m) return;
+  const int x0 = a.blk_x[r], nx = a.blk_x[r + 1] - x0;
+  double v[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) v[c] = 0.0;
+  for (int k = threadIdx.x; k < nx; k += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] += a.fpart[(size_t)(x0 + k) * 9 + c];
+  block_sum<9>(v, red);
+  if (threadIdx.x == 0) {
+    const double V = (double)a.desc[r].V;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      st->Ebar_prev[c] = st->Ebar[c];
+      if ((m >> c) & 1u) st->Ebar[c] = v[c] / V;
+    }
   }
 }
 
@@ -636,9 +690,9 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
     grad_u(uo, V, sn, Do);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const double e = D.Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
+      const double e = st->Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
       Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
-      const double dd = Dn[c] - Do[c];
+      const double dd = (Dn[c] - Do[c]) + (st->Ebar[c] - st->Ebar_prev[c]);
       v[0] += e * e;
       v[1] += dd * dd;
     }
@@ -893,6 +947,7 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
     case Part::Project: {
       {
         Timed tm(L, K_DIV_FWDX);
+        if (L.any_free) hipLaunchKernelGGL(k_fbar, dim3(a.n_rve), blk, 0, L.stream, a);
         hipLaunchKernelGGL((k_div_fwdx<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
       }
       {

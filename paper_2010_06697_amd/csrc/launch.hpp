@@ -24,6 +24,8 @@ struct KernelArgs {
   double *hist;         // per cell, per iteration: r_p, r_d, rho
   double2 *lpart;       // per local workgroup, inexact passes: (sum of |local
                         // residual|^2, count of converged local solves)
+  double *fpart;        // per local workgroup: sums of F - I - Lambda/rho (9), for
+                        // the free components of <F>
   int2 *newton_part;    // per update workgroup: failed solves and Newton iterations
                         // of the local-step workgroups in its tile
   int n_rve;
@@ -51,7 +53,8 @@ struct LaunchCfg {
   int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
-  bool any_lce;  // some phase uses the LCE energy
+  bool any_lce;   // some phase uses the LCE energy
+  bool any_free;  // some cell leaves components of <F> free
 };
 
 enum class Part { Local, Project, Update, MeanStress };
