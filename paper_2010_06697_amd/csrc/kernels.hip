@@ -54,13 +54,22 @@ __device__ __forceinline__ Stencil stencil(int n1, int n2, int n3, int x1, int x
   return s;
 }
 
+// Every field lives in global memory, but a pointer read from the descriptor
+// tables carries no address space: inside an inlined helper the compiler
+// cannot always prove it global and accesses it with flat instructions (the
+// local kernel ran 8% slower that way). Kernels access fields through these
+// global-address-space views.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> global_view(T *p) {
+  return (gptr<T>)p;
+}
+
 // central differences (u_i(x+e_j) - u_i(x-e_j))/2 of a 3-vector field; out[3i+j]
-template <typename T>
-__device__ __forceinline__ void grad_u(const T *__restrict__ u, int V, const Stencil &s,
-                                       double *out) {
+template <typename P>
+__device__ __forceinline__ void grad_u(P u, int V, const Stencil &s, double *out) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T *ui = u + i * V;
+    const auto ui = u + i * V;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       out[3 * i + j] = 0.5 * ((double)ui[s.o[2 * j]] - (double)ui[s.o[2 * j + 1]]);
@@ -127,15 +136,18 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // and the director) and stores the workgroup's sum of |local residual|^2 and
 // count of converged solves, which k_local_check reduces. Passes after the
 // first do nothing once the cell is done.
-template <typename T, bool ANY_LCE>
-__device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams &ip, int pass,
-                                           int blk) {
+// launch modes of the local step: every problem solved exactly (no inexact
+// strategy configured), the first pass of an inexact step, a later pass
+enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2 };
+
+template <typename T, bool ANY_LCE, int MODE>
+__device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass, int blk) {
   const int r = find_rve(a.blk_x, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
-  const bool inexact = local_inexact(ip, st);
-  if (pass > 0 && (!inexact || st->local_done)) return;
+  const bool inexact = MODE != kLocalExact && local_inexact(ip, st);
+  if (MODE == kLocalLater && (!inexact || st->local_done)) return;
   const int b = blk - a.blk_x[r];
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
   const int nrows = n2 * n3;
@@ -150,9 +162,9 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
     const double irho = 1.0 / rho;
     const int x2 = grow % n2, x3 = grow / n2;
     const int idx = grow * n1 + x1;
-    const T *u = static_cast<const T *>(D.u[st->cur]);
-    T *Eg = static_cast<T *>(D.E);
-    const T *Lg = static_cast<const T *>(D.Lam);
+    const auto u = global_view(static_cast<const T *>(D.u[st->cur]));
+    const auto Eg = global_view(static_cast<T *>(D.E));
+    const auto Lg = global_view(static_cast<const T *>(D.Lam));
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     T E[9], At[9];
     double A[9];
@@ -162,13 +174,13 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
       E[c] = Eg[c * V + idx];
       At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
     }
-    const int ph = D.phase[idx];
+    const int ph = global_view(D.phase)[idx];
     if (ph < a.n_mat) {
       const Material m = a.mats[ph];
       const int cap = inexact ? ip.local_chunk : ip.newton_max;
       int rc;
       if (ANY_LCE && m.model == 1) {
-        T *dg = static_cast<T *>(D.dir);
+        const auto dg = global_view(static_cast<T *>(D.dir));
         double n[3] = {(double)dg[idx], (double)dg[V + idx], (double)dg[2 * V + idx]};
         const double nn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         n[0] *= nn;
@@ -207,29 +219,6 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
     } else {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
-  }
-  // mixed conditions: this workgroup's sums of F_{i+1} - I - Lambda_i/rho,
-  // read back from memory (cache hits) after the solve rather than carried
-  // through it in registers
-  if (st->free_mask) {
-    __shared__ double hred[9 * (kThreads / 64)];
-    double hsum[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) hsum[c] = 0.0;
-    if (row < R && grow < nrows) {
-      const T *Eg = static_cast<const T *>(D.E);
-      const T *Lg = static_cast<const T *>(D.Lam);
-      const int idx = grow * n1 + x1;
-      const double irho = 1.0 / st->rho;
-#pragma unroll
-      for (int c = 0; c < 9; ++c)
-        hsum[c] = (double)Eg[c * V + idx] - (double)Lg[c * V + idx] * irho;
-    }
-    block_sum<9>(hsum, hred);
-    if (t == 0)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) a.fpart[(size_t)blk * 9 + c] = hsum[c];
-    __syncthreads();
   }
   // local residual of the inexact passes: one sum per workgroup (a fence
   // and arrival counter per workgroup, to let the last one decide, cost
@@ -275,18 +264,53 @@ __device__ __forceinline__ void local_tile(const KernelArgs &a, const IterParams
 // Step 1. The first pass runs one logical workgroup per workgroup; later
 // inexact passes, which often find the cell done, run a smaller grid over
 // logical workgroups blockIdx.x, blockIdx.x + gridDim.x, ... (a multiple of
-// 8 workgroups, so each logical workgroup keeps its XCD).
-template <typename T, bool ANY_LCE, bool STRIDED>
+// 8 workgroups, so each logical workgroup keeps its XCD). The exact mode
+// compiles without the inexact bookkeeping.
+template <typename T, bool ANY_LCE, int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
 void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
-  if (!STRIDED) {
-    local_tile<T, ANY_LCE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
+  if (MODE != kLocalLater) {
+    local_tile<T, ANY_LCE, MODE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
     return;
   }
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
-    local_tile<T, ANY_LCE>(a, ip, pass, xcd_remap(lb, nblk));
+    local_tile<T, ANY_LCE, MODE>(a, ip, pass, xcd_remap(lb, nblk));
     __syncthreads();  // LDS of this tile read before the next one writes it
   }
+}
+
+// Mixed conditions: per local workgroup, the sums of F_{i+1} - I -
+// Lambda_i/rho over its voxels (cells with free components of <F> only),
+// for k_fbar. A pass of its own, so that the local kernel carries none of it.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fsum(KernelArgs a) {
+  __shared__ double red[9 * (kThreads / 64)];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  if (!st->active || !st->free_mask) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3;
+  const int V = (int)D.V;
+  const int t = threadIdx.x;
+  const int row = t / n1, x1 = t - row * n1;
+  const int grow = b * R + row;
+  double h[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) h[c] = 0.0;
+  if (row < R && grow < nrows) {
+    const auto Eg = global_view(static_cast<const T *>(D.E));
+    const auto Lg = global_view(static_cast<const T *>(D.Lam));
+    const int idx = grow * n1 + x1;
+    const double irho = 1.0 / st->rho;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) h[c] = (double)Eg[c * V + idx] - (double)Lg[c * V + idx] * irho;
+  }
+  block_sum<9>(h, red);
+  if (t == 0)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a.fpart[(size_t)blk * 9 + c] = h[c];
 }
 
 // Mixed conditions (Sec. 2.3; the UNI/PE/EB protocols of Sec. 5): Step 2
@@ -805,7 +829,7 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
       E[c] = (double)Eg[c * V + idx];
       v[9 + c] += (double)Lg[c * V + idx];
     }
-    const int ph = D.phase[idx];
+    const int ph = global_view(D.phase)[idx];
     Point<double> s;
     bool ok = false;
     // with rho = 0 the gradient of the prox objective is the stress P
@@ -923,21 +947,28 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       const bool inexact = ip.local_ratio > 0.0 || ip.local_fraction > 0.0;
       const int passes = inexact ? ip.local_passes : 1;
       for (int pass = 0; pass < passes; ++pass) {
-        if (pass == 0) {
+        if (!inexact) {
           if (L.any_lce)
-            hipLaunchKernelGGL((k_local<T, true, false>), dim3(L.nblk_x), blk, 0, L.stream, a, ip,
-                               0, L.nblk_x);
+            hipLaunchKernelGGL((k_local<T, true, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream,
+                               a, ip, 0, L.nblk_x);
           else
-            hipLaunchKernelGGL((k_local<T, false, false>), dim3(L.nblk_x), blk, 0, L.stream, a,
-                               ip, 0, L.nblk_x);
+            hipLaunchKernelGGL((k_local<T, false, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream,
+                               a, ip, 0, L.nblk_x);
+        } else if (pass == 0) {
+          if (L.any_lce)
+            hipLaunchKernelGGL((k_local<T, true, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream,
+                               a, ip, 0, L.nblk_x);
+          else
+            hipLaunchKernelGGL((k_local<T, false, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream,
+                               a, ip, 0, L.nblk_x);
         } else {
           const int grid = std::min(L.nblk_x, kLocalPassGrid);
           if (L.any_lce)
-            hipLaunchKernelGGL((k_local<T, true, true>), dim3(grid), blk, 0, L.stream, a, ip, pass,
-                               L.nblk_x);
+            hipLaunchKernelGGL((k_local<T, true, kLocalLater>), dim3(grid), blk, 0, L.stream, a,
+                               ip, pass, L.nblk_x);
           else
-            hipLaunchKernelGGL((k_local<T, false, true>), dim3(grid), blk, 0, L.stream, a, ip,
-                               pass, L.nblk_x);
+            hipLaunchKernelGGL((k_local<T, false, kLocalLater>), dim3(grid), blk, 0, L.stream, a,
+                               ip, pass, L.nblk_x);
         }
         if (inexact)
           hipLaunchKernelGGL(k_local_check, dim3(a.n_rve), blk, 0, L.stream, a, ip, pass);
@@ -947,7 +978,10 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
     case Part::Project: {
       {
         Timed tm(L, K_DIV_FWDX);
-        if (L.any_free) hipLaunchKernelGGL(k_fbar, dim3(a.n_rve), blk, 0, L.stream, a);
+        if (L.any_free) {
+          hipLaunchKernelGGL((k_fsum<T>), dim3(L.nblk_x), blk, 0, L.stream, a);
+          hipLaunchKernelGGL(k_fbar, dim3(a.n_rve), blk, 0, L.stream, a);
+        }
         hipLaunchKernelGGL((k_div_fwdx<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
       }
       {
