@@ -25,7 +25,15 @@ NEOHOOKE, LCE = 0, 1
 class Material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("mu", ctypes.c_double),
                 ("lam", ctypes.c_double), ("a", ctypes.c_double),
-                ("kappa", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("frank", ctypes.c_double), ("nu_F", ctypes.c_double),
+                ("nu_n", ctypes.c_double)]
+
+
+class Site(ctypes.Structure):
+    """Per-voxel data of the full LCE model: cross-link director n0 and the
+    constant quadratic form Sc in the director (see admm_oracle.h)."""
+    _fields_ = [("n0", ctypes.c_double * 3), ("Sc", ctypes.c_double * 9)]
 
 
 class Newton(ctypes.Structure):
@@ -42,7 +50,8 @@ class Params(ctypes.Structure):
                 ("newton", Newton), ("local_ratio", ctypes.c_double),
                 ("local_chunk", ctypes.c_int), ("local_passes", ctypes.c_int),
                 ("local_start_iter", ctypes.c_int), ("local_rd_prev", ctypes.c_double),
-                ("local_fraction", ctypes.c_double), ("free_mask", ctypes.c_uint)]
+                ("local_fraction", ctypes.c_double), ("free_mask", ctypes.c_uint),
+                ("dt", ctypes.c_double)]
 
 
 _lib = None
@@ -64,19 +73,21 @@ def lib():
         L.or_dft3.argtypes = [i, i, i, dp, dp, dp, dp, i]
         L.or_gradient.argtypes = [i, i, i, dp, dp, dp]
         L.or_project.argtypes = [i, i, i, dp, dp, dp]
-        L.or_energy.argtypes = [mp, dp, dp]
+        sp = ctypes.POINTER(Site)
+        L.or_energy.argtypes = [mp, dp, dp, sp]
         L.or_energy.restype = ctypes.c_double
-        L.or_stress.argtypes = [mp, dp, dp, dp]
-        L.or_tangent.argtypes = [mp, dp, dp, dp]
+        L.or_stress.argtypes = [mp, dp, dp, sp, dp]
+        L.or_tangent.argtypes = [mp, dp, dp, sp, dp]
         L.or_director.argtypes = [dp, dp, dp]
-        L.or_relaxed.argtypes = [mp, dp, dp, dp, dp, dp]
-        L.or_prox.argtypes = [mp, ctypes.c_double, dp, ctypes.POINTER(Newton), dp, dp, ip]
+        L.or_relaxed.argtypes = [mp, dp, sp, dp, dp, dp, dp]
+        L.or_prox.argtypes = [mp, ctypes.c_double, dp, sp, ctypes.POINTER(Newton), dp, dp, ip]
         L.or_rho_update.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.POINTER(Params)]
         L.or_rho_update.restype = ctypes.c_double
         L.or_admm_run.argtypes = [i, i, i, bp, mp, i, dp, ctypes.POINTER(Params),
-                                  dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]
-        L.or_mean_stress.argtypes = [i, i, i, bp, mp, i, dp, dp, dp, dp, dp]
+                                  dp, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]
+        L.or_mean_stress.argtypes = [i, i, i, bp, mp, i, dp, dp, dp, dp, dp, dp]
+        L.or_orientation.argtypes = [i, i, i, bp, mp, i, dp, dp]
         L.or_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -94,10 +105,31 @@ def _vec(x, n):
     return a
 
 
-def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0):
+def site(nref=None, Sc=None):
+    """A Site from the cross-link director nref and the form Sc (3x3);
+    None for both gives no site (the ideal model)."""
+    if nref is None and Sc is None:
+        return None
+    s = Site()
+    nv = _vec(nref if nref is not None else (0.0, 0.0, 0.0), 3)
+    Sv = _vec(Sc if Sc is not None else np.zeros(9), 9)
+    for k in range(3):
+        s.n0[k] = nv[k]
+    for k in range(9):
+        s.Sc[k] = Sv[k]
+    return s
+
+
+def _sp(s):
+    return ctypes.byref(s) if s is not None else None
+
+
+def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0, alpha=0.0, frank=0.0,
+             nu_F=0.0, nu_n=0.0):
     m = Material()
     m.model = NEOHOOKE if model == "neohooke" else LCE
     m.mu, m.lam, m.a, m.kappa = float(mu), float(lam), float(a), float(kappa)
+    m.alpha, m.frank, m.nu_F, m.nu_n = float(alpha), float(frank), float(nu_F), float(nu_n)
     return m
 
 
@@ -110,14 +142,16 @@ def newton_opts(max_iter=100, gtol=1e-15, step_tol=1e-10):
 def params(rho_min=1.0, rho_max=50.0, kappa_rho=1.3, tau=10.0, adapt_rho=False,
            tol_p=1e-8, tol_d=1e-8, mu_ref=1.0, max_iter=200, fixed_iters=False,
            newton=None, local_ratio=0.0, local_chunk=1, local_passes=8, local_start_iter=0,
-           local_rd_prev=0.0, local_fraction=0.0, free=()):
+           local_rd_prev=0.0, local_fraction=0.0, free=(), dt=1.0):
     """free: indices k = 3i + j of the components of <F> left free (mixed
-    boundary conditions); the others are prescribed."""
+    boundary conditions); the others are prescribed. dt: time step of the
+    load step (dissipation)."""
     p = Params()
     p.local_ratio, p.local_chunk, p.local_passes = local_ratio, local_chunk, local_passes
     p.local_start_iter, p.local_rd_prev = local_start_iter, local_rd_prev
     p.local_fraction = local_fraction
     p.free_mask = sum(1 << int(k) for k in set(free))
+    p.dt = float(dt)
     p.rho_min, p.rho_max, p.kappa_rho, p.tau = rho_min, rho_max, kappa_rho, tau
     p.adapt_rho = int(bool(adapt_rho))
     p.tol_p, p.tol_d, p.mu_ref = tol_p, tol_d, mu_ref
@@ -169,21 +203,24 @@ def project(H, return_imag=False):
     return (u, mi.value) if return_imag else u
 
 
-def energy(m, F, n=(0.0, 0.0, 1.0)):
-    return lib().or_energy(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)))
+def energy(m, F, n=(0.0, 0.0, 1.0), nref=None, Sc=None):
+    return lib().or_energy(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)),
+                           _sp(site(nref, Sc)))
 
 
-def stress(m, F, n=(0.0, 0.0, 1.0)):
+def stress(m, F, n=(0.0, 0.0, 1.0), nref=None, Sc=None):
     P = np.empty(9)
-    rc = lib().or_stress(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)), _dp(P))
+    rc = lib().or_stress(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)),
+                         _sp(site(nref, Sc)), _dp(P))
     if rc != OK:
         raise FloatingPointError("det F <= 0")
     return P
 
 
-def tangent(m, F, n=(0.0, 0.0, 1.0)):
+def tangent(m, F, n=(0.0, 0.0, 1.0), nref=None, Sc=None):
     C = np.empty(81)
-    rc = lib().or_tangent(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)), _dp(C))
+    rc = lib().or_tangent(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n, 3)),
+                          _sp(site(nref, Sc)), _dp(C))
     if rc != OK:
         raise FloatingPointError("det F <= 0")
     return C.reshape(9, 9)
@@ -195,26 +232,27 @@ def director(F, n_prev):
     return n
 
 
-def relaxed(m, F, n_prev):
+def relaxed(m, F, n_prev, nref=None, Sc=None):
     """LCE energy with the director eliminated: returns (n, P, K) at F."""
     n = np.empty(3)
     P = np.empty(9)
     K = np.empty(81)
-    rc = lib().or_relaxed(ctypes.byref(m), _dp(_vec(F, 9)), _dp(_vec(n_prev, 3)), _dp(n),
-                          _dp(P), _dp(K))
+    rc = lib().or_relaxed(ctypes.byref(m), _dp(_vec(F, 9)), _sp(site(nref, Sc)),
+                          _dp(_vec(n_prev, 3)), _dp(n), _dp(P), _dp(K))
     if rc != OK:
         raise ValueError(f"or_relaxed failed: {rc}")
     return n, P, K.reshape(9, 9)
 
 
-def prox(m, rho, A, F0, n0=(0.0, 0.0, 1.0), opts=None):
-    """Local problem at one point. Returns (F, n, iters, rc)."""
+def prox(m, rho, A, F0, n0=(0.0, 0.0, 1.0), opts=None, nref=None, Sc=None):
+    """Local problem at one point from the warm start (F0, n0). Returns
+    (F, n, iters, rc)."""
     F = _vec(F0, 9).copy()
     n = _vec(n0, 3).copy()
     it = ctypes.c_int(0)
     o = opts if opts is not None else newton_opts()
-    rc = lib().or_prox(ctypes.byref(m), float(rho), _dp(_vec(A, 9)), ctypes.byref(o),
-                       _dp(F), _dp(n), ctypes.byref(it))
+    rc = lib().or_prox(ctypes.byref(m), float(rho), _dp(_vec(A, 9)), _sp(site(nref, Sc)),
+                       ctypes.byref(o), _dp(F), _dp(n), ctypes.byref(it))
     return F, n, it.value, rc
 
 
@@ -222,7 +260,7 @@ def rho_update(rho, r_p, r_d, p):
     return lib().or_rho_update(float(rho), float(r_p), float(r_d), ctypes.byref(p))
 
 
-def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None):
+def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None, director0=None):
     """Runs ADMM iterations in place on (u, F, Lam[, director_field]).
 
     Returns a dict with rc, iters, rho, the r_p / r_d / rho histories and
@@ -244,7 +282,7 @@ def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None):
     rc = lib().or_admm_run(n1, n2, n3,
                            phase.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
                            marr, len(mats), _dp(Fb), ctypes.byref(p),
-                           _dp(u), _dp(F), _dp(Lam), _dp(director_field),
+                           _dp(u), _dp(F), _dp(Lam), _dp(director_field), _dp(director0),
                            ctypes.byref(r), _dp(hp), _dp(hd), _dp(hr),
                            ctypes.byref(it), ctypes.byref(nf))
     k = it.value
@@ -253,7 +291,7 @@ def admm_run(phase, mats, Fbar, p, u, F, Lam, rho, director_field=None):
             "Fbar": Fb}
 
 
-def mean_stress(phase, mats, F, director_field=None, Lam=None):
+def mean_stress(phase, mats, F, director_field=None, Lam=None, director0=None):
     phase = np.ascontiguousarray(phase, dtype=np.uint8)
     n3, n2, n1 = phase.shape
     P = np.empty(9)
@@ -261,11 +299,22 @@ def mean_stress(phase, mats, F, director_field=None, Lam=None):
     marr = _mats(mats)
     rc = lib().or_mean_stress(n1, n2, n3,
                               phase.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
-                              marr, len(mats), _dp(F), _dp(director_field), _dp(Lam),
-                              _dp(P), _dp(L))
+                              marr, len(mats), _dp(F), _dp(director_field), _dp(director0),
+                              _dp(Lam), _dp(P), _dp(L))
     if rc != OK:
         raise FloatingPointError(f"or_mean_stress rc={rc}")
     return (P, L) if Lam is not None else P
+
+
+def orientation(phase, mats, director_field):
+    """S = 3/2 (<n (x) n> - I/3) over the LCE voxels (3x3)."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    n3, n2, n1 = phase.shape
+    S = np.empty(9)
+    rc = lib().or_orientation(n1, n2, n3, phase.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                              _mats(mats), len(mats), _dp(director_field), _dp(S))
+    assert rc == OK, rc
+    return S.reshape(3, 3)
 
 
 def initial_state(shape, director0=None):

@@ -93,7 +93,8 @@ static double ftn2(const double *F, const double *n, double *Ftn) {
   return s;
 }
 
-double or_energy(const or_material *m, const double F[9], const double n[3]) {
+double or_energy(const or_material *m, const double F[9], const double n[3],
+                 const or_site *site) {
   double J = det3(F);
   if (!(J > 0.0)) return INFINITY;
   double f2 = dot9(F, F);
@@ -102,14 +103,22 @@ double or_energy(const or_material *m, const double F[9], const double n[3]) {
     return 0.5 * m->mu * (f2 - 3.0) - m->mu * lj + 0.5 * m->lambda * lj * lj;
   }
   /* OR_LCE */
-  double a13 = cbrt(m->a);
-  double t = ftn2(F, n, NULL);
-  return 0.5 * m->mu * (a13 * (f2 + (1.0 / m->a - 1.0) * t) - 3.0) +
-         0.5 * m->kappa * (J - 1.0) * (J - 1.0);
+  double a13 = cbrt(m->a), Ftn[3];
+  double t = ftn2(F, n, Ftn);
+  double W = 0.5 * m->mu * (a13 * (f2 + (1.0 / m->a - 1.0) * t) - 3.0) +
+             0.5 * m->kappa * (J - 1.0) * (J - 1.0);
+  if (site) {
+    /* non-ideality mu alpha/2 (|F^T n|^2 - (n0 . F^T n)^2), then n . Sc n */
+    double q = site->n0[0] * Ftn[0] + site->n0[1] * Ftn[1] + site->n0[2] * Ftn[2];
+    W += 0.5 * m->mu * m->alpha * (t - q * q);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) W += n[i] * site->Sc[3 * i + j] * n[j];
+  }
+  return W;
 }
 
 int or_stress(const or_material *m, const double F[9], const double n[3],
-              double P[9]) {
+              const or_site *site, double P[9]) {
   double J = det3(F);
   if (!(J > 0.0)) return OR_EDOMAIN;
   double C[9], G[9];
@@ -129,11 +138,18 @@ int or_stress(const or_material *m, const double F[9], const double n[3],
     for (int L = 0; L < 3; ++L)
       P[3 * i + L] = m->mu * a13 * (F[3 * i + L] + (1.0 / m->a - 1.0) * n[i] * Ftn[L]) +
                      m->kappa * (J - 1.0) * J * G[3 * i + L];
+  if (site && m->alpha != 0.0) {
+    /* + mu alpha n (x) (F^T n - (n0 . F^T n) n0) */
+    double q = site->n0[0] * Ftn[0] + site->n0[1] * Ftn[1] + site->n0[2] * Ftn[2];
+    for (int i = 0; i < 3; ++i)
+      for (int L = 0; L < 3; ++L)
+        P[3 * i + L] += m->mu * m->alpha * n[i] * (Ftn[L] - q * site->n0[L]);
+  }
   return OR_OK;
 }
 
 int or_tangent(const or_material *m, const double F[9], const double n[3],
-               double Cm[81]) {
+               const or_site *site, double Cm[81]) {
   double J = det3(F);
   if (!(J > 0.0)) return OR_EDOMAIN;
   double C[9], Fi[9]; /* Fi[3*J+k] = (F^{-1})_Jk = C_kJ / det */
@@ -159,6 +175,9 @@ int or_tangent(const or_material *m, const double F[9], const double n[3],
             v = m->mu * a13 * (d_ik + (1.0 / m->a - 1.0) * n[i] * n[k]) * d_JL +
                 m->kappa * ((2.0 * J - 1.0) * J * Fi[3 * Jx + i] * Fi[3 * L + k] -
                             (J - 1.0) * J * Fi[3 * Jx + k] * Fi[3 * L + i]);
+            /* non-ideality: mu alpha n_i n_k (d_JL - n0_J n0_L) */
+            if (site && m->alpha != 0.0)
+              v += m->mu * m->alpha * n[i] * n[k] * (d_JL - site->n0[Jx] * site->n0[L]);
           }
           Cm[(3 * i + Jx) * 9 + (3 * k + L)] = v;
         }
@@ -206,14 +225,30 @@ static void jacobi3(double B[9], double Vv[9], double w[3]) {
   w[2] = B[8];
 }
 
-/* Eigen-decomposition of B = F F^T sorted by decreasing eigenvalue (w[0] >=
-   w[1] >= w[2], eigenvectors in the columns of V), and the minimising
-   director: the top eigenvector, its sign chosen so that n . n_prev >= 0.
-   When the top eigenvalue is degenerate (the leading ncl eigenvalues within
-   1e-12 relative) every unit vector of that eigenspace is a minimiser and the
-   previous director's projection onto it is kept. Returns ncl. */
-static int director_eig(const double F[9], const double n_prev[3], double n[3],
-                        double w[3], double V[9]) {
+/* Coefficient of the non-ideality relative to the director term of the
+   neo-classical energy, and of Sc: with c = mu a^(1/3) (1 - 1/a) / 2 the
+   director terms are n . M n, M = -c F F^T + (mu alpha/2) F P0 F^T + Sc,
+   P0 = I - n0 n0, and the minimising director maximises n . S n with
+   S = -M / c = F F^T - gamma F P0 F^T - Sc / c, gamma = alpha / (a^(1/3)(1 - 1/a)).
+   Returns 0 (S = F F^T) for the ideal model or without a site. */
+static int director_form(const or_material *m, const or_site *site, double *gamma,
+                         double *inv_c) {
+  if (!m || !site || m->model != OR_LCE || !(m->a > 1.0)) return 0;
+  double a13 = cbrt(m->a), c = 0.5 * m->mu * a13 * (1.0 - 1.0 / m->a);
+  *gamma = m->alpha / (a13 * (1.0 - 1.0 / m->a));
+  *inv_c = 1.0 / c;
+  return 1;
+}
+
+/* Eigen-decomposition of S (F F^T for the ideal model, see director_form)
+   sorted by decreasing eigenvalue (w[0] >= w[1] >= w[2], eigenvectors in the
+   columns of V), and the minimising director: the top eigenvector, its sign
+   chosen so that n . n_prev >= 0. When the top eigenvalue is degenerate (the
+   leading ncl eigenvalues within 1e-12 relative) every unit vector of that
+   eigenspace is a minimiser and the previous director's projection onto it
+   is kept. Returns ncl. */
+static int director_eig(const or_material *m, const or_site *site, const double F[9],
+                        const double n_prev[3], double n[3], double w[3], double V[9]) {
   double B[9], Vv[9], wu[3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -221,6 +256,16 @@ static int director_eig(const double F[9], const double n_prev[3], double n[3],
       for (int k = 0; k < 3; ++k) s += F[3 * i + k] * F[3 * j + k];
       B[3 * i + j] = s;
     }
+  double gamma = 0.0, inv_c = 0.0;
+  if (director_form(m, site, &gamma, &inv_c)) {
+    double Fn0[3];
+    for (int i = 0; i < 3; ++i)
+      Fn0[i] = F[3 * i] * site->n0[0] + F[3 * i + 1] * site->n0[1] + F[3 * i + 2] * site->n0[2];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        B[3 * i + j] = B[3 * i + j] - gamma * (B[3 * i + j] - Fn0[i] * Fn0[j]) -
+                       inv_c * site->Sc[3 * i + j];
+  }
   jacobi3(B, Vv, wu);
   int order[3] = {0, 1, 2};
   for (int a = 0; a < 3; ++a) /* sort eigenvalues descending */
@@ -234,7 +279,7 @@ static int director_eig(const double F[9], const double n_prev[3], double n[3],
     w[e] = wu[order[e]];
     for (int k = 0; k < 3; ++k) V[3 * k + e] = Vv[3 * k + order[e]];
   }
-  double tie = 1e-12 * fabs(w[0]);
+  double tie = 1e-12 * fmax(fabs(w[0]), fabs(w[2]));
   double out[3];
   int ncl = 1;
   while (ncl < 3 && w[0] - w[ncl] <= tie) ++ncl;
@@ -261,7 +306,7 @@ static int director_eig(const double F[9], const double n_prev[3], double n[3],
 
 int or_director(const double F[9], const double n_prev[3], double n[3]) {
   double w[3], V[9];
-  director_eig(F, n_prev, n, w, V);
+  director_eig(NULL, NULL, F, n_prev, n, w, V);
   return OR_OK;
 }
 
@@ -276,33 +321,61 @@ int or_director(const double F[9], const double n_prev[3], double n[3]) {
    The first part is already in the fixed-director tangent; the second, times
    mu a^(1/3)(1/a - 1)/2, is negative semidefinite. Eigenvectors in the top
    eigenspace of n (ties, see director_eig) contribute nothing. K += that
-   term. */
-static void lce_rotation_term(const or_material *m, const double F[9], const double n[3],
-                              const double w[3], const double V[9], int ncl, double *K) {
+   term. With the non-ideality, S = F F^T - gamma F P0 F^T (director_form;
+   Sc does not depend on F) and t_k . dS n = w_k : dF with
+       w_k = t_k (x) F^T n + n (x) F^T t_k - gamma (t_k (x) P0 F^T n + n (x) P0 F^T t_k). */
+static void lce_rotation_term(const or_material *m, const or_site *site, const double F[9],
+                              const double n[3], const double w[3], const double V[9], int ncl,
+                              double *K) {
   double c2 = m->mu * cbrt(m->a) * (1.0 / m->a - 1.0); /* 2 c */
-  double ftn[3];
+  double gamma = 0.0, inv_c = 0.0;
+  int ext = director_form(m, site, &gamma, &inv_c);
+  double ftn[3], pftn[3];
   for (int J = 0; J < 3; ++J) ftn[J] = F[J] * n[0] + F[3 + J] * n[1] + F[6 + J] * n[2];
+  if (ext) {
+    double q = site->n0[0] * ftn[0] + site->n0[1] * ftn[1] + site->n0[2] * ftn[2];
+    for (int J = 0; J < 3; ++J) pftn[J] = ftn[J] - q * site->n0[J];
+  }
   for (int e = ncl; e < 3; ++e) {
     double t[3] = {V[e], V[3 + e], V[6 + e]};
     double ftt[3], wk[9];
     for (int J = 0; J < 3; ++J) ftt[J] = F[J] * t[0] + F[3 + J] * t[1] + F[6 + J] * t[2];
     for (int i = 0; i < 3; ++i)
       for (int J = 0; J < 3; ++J) wk[3 * i + J] = t[i] * ftn[J] + n[i] * ftt[J];
+    if (ext) {
+      double q = site->n0[0] * ftt[0] + site->n0[1] * ftt[1] + site->n0[2] * ftt[2];
+      for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J)
+          wk[3 * i + J] -= gamma * (t[i] * pftn[J] + n[i] * (ftt[J] - q * site->n0[J]));
+    }
     double f = c2 / (w[0] - w[e]);
     for (int a = 0; a < 9; ++a)
       for (int b = 0; b < 9; ++b) K[9 * a + b] += f * wk[a] * wk[b];
   }
 }
 
-int or_relaxed(const or_material *m, const double F[9], const double n_prev[3],
-               double n[3], double P[9], double K[81]) {
-  if (!m || !F || !n_prev || !n || m->model != OR_LCE || !(m->a >= 1.0)) return OR_EINVAL;
+/* LCE options valid for the director elimination: a >= 1, and a > 1 where
+   the non-ideality or Sc is used (at a = 1 the neo-classical director term
+   vanishes and S above is not defined) */
+static int lce_site_ok(const or_material *m, const or_site *site) {
+  if (!(m->a >= 1.0) || !(m->alpha >= 0.0)) return 0;
+  if (site && !(m->a > 1.0)) {
+    if (m->alpha != 0.0) return 0;
+    for (int k = 0; k < 9; ++k)
+      if (site->Sc[k] != 0.0) return 0;
+  }
+  return 1;
+}
+
+int or_relaxed(const or_material *m, const double F[9], const or_site *site,
+               const double n_prev[3], double n[3], double P[9], double K[81]) {
+  if (!m || !F || !n_prev || !n || m->model != OR_LCE || !lce_site_ok(m, site)) return OR_EINVAL;
   double w[3], V[9];
-  int ncl = director_eig(F, n_prev, n, w, V);
-  if (P && or_stress(m, F, n, P) != OR_OK) return OR_EDOMAIN;
+  int ncl = director_eig(m, site, F, n_prev, n, w, V);
+  if (P && or_stress(m, F, n, site, P) != OR_OK) return OR_EDOMAIN;
   if (K) {
-    if (or_tangent(m, F, n, K) != OR_OK) return OR_EDOMAIN;
-    lce_rotation_term(m, F, n, w, V, ncl, K);
+    if (or_tangent(m, F, n, site, K) != OR_OK) return OR_EDOMAIN;
+    lce_rotation_term(m, site, F, n, w, V, ncl, K);
   }
   return OR_OK;
 }
@@ -344,8 +417,8 @@ static void chol9_solve(const double *L, const double *b, double *x) {
 }
 
 static double prox_objective(const or_material *m, double rho, const double *A,
-                             const double *F, const double *n) {
-  double W = or_energy(m, F, n);
+                             const double *F, const double *n, const or_site *site) {
+  double W = or_energy(m, F, n, site);
   double d2 = 0.0;
   for (int k = 0; k < 9; ++k) d2 += (F[k] - A[k]) * (F[k] - A[k]);
   return W + 0.5 * rho * d2;
@@ -358,11 +431,12 @@ static double moduli_sum(const or_material *m) {
 /* Newton's method with Armijo backtracking on phi(F) = W(F,n) + rho/2|F-A|^2
    at fixed n. Returns OR_OK, OR_NOT_CONVERGED or OR_EDOMAIN; *it = iterations. */
 static int newton_fixed_n(const or_material *m, double rho, const double *A,
-                          const or_newton *opt, double *F, const double *n, int *it) {
+                          const or_newton *opt, double *F, const double *n,
+                          const or_site *site, int *it) {
   double P[9], g[9], K[81], d[9], Ft[9];
   double scale_mod = moduli_sum(m) + rho;
   for (int iter = 0; iter < opt->max_iter; ++iter) {
-    if (or_stress(m, F, n, P) != OR_OK) {
+    if (or_stress(m, F, n, site, P) != OR_OK) {
       *it = iter;
       return OR_EDOMAIN;
     }
@@ -372,7 +446,7 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
       *it = iter;
       return OR_OK;
     }
-    or_tangent(m, F, n, K);
+    or_tangent(m, F, n, site, K);
     for (int k = 0; k < 9; ++k) K[10 * k] += rho;
     int pd = chol9(K);
     if (pd) {
@@ -383,7 +457,7 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
       for (int k = 0; k < 9; ++k) d[k] = -g[k];
     }
     double slope = dot9(g, d);
-    double phi0 = prox_objective(m, rho, A, F, n);
+    double phi0 = prox_objective(m, rho, A, F, n, site);
     /* Armijo backtracking on phi. Once the predicted decrease falls below the
        rounding floor of phi itself, the energy test is noise; the step is then
        accepted on a decrease of the gradient norm instead. */
@@ -397,14 +471,14 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
       for (int k = 0; k < 9; ++k) Ft[k] = F[k] + t * d[k];
       if (det3(Ft) > 0.0) {
         if (!small) {
-          double phit = prox_objective(m, rho, A, Ft, n);
+          double phit = prox_objective(m, rho, A, Ft, n, site);
           if (phit <= phi0 + 1e-4 * t * slope) {
             accepted = 1;
             break;
           }
         } else {
           double Pt[9], gt[9];
-          or_stress(m, Ft, n, Pt);
+          or_stress(m, Ft, n, site, Pt);
           for (int k = 0; k < 9; ++k) gt[k] = Pt[k] + rho * (Ft[k] - A[k]);
           if (norm9(gt) <= (1.0 - 1e-4 * t) * gn) {
             accepted = 1;
@@ -443,12 +517,13 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
    the director once, leaving the rest of the director relaxation to the
    following iterations. */
 static int newton_relaxed(const or_material *m, double rho, const double A[9],
-                          const or_newton *opt, double F[9], double n[3], int *it) {
+                          const or_newton *opt, double F[9], double n[3],
+                          const or_site *site, int *it) {
   double P[9], g[9], Kr[81], d[9], Ft[9], nt[3], w[3], V[9], ncur[3];
   double scale_mod = moduli_sum(m) + rho;
-  int ncl = director_eig(F, n, ncur, w, V);
+  int ncl = director_eig(m, site, F, n, ncur, w, V);
   for (int iter = 0; iter < opt->max_iter; ++iter) {
-    if (or_stress(m, F, ncur, P) != OR_OK) {
+    if (or_stress(m, F, ncur, site, P) != OR_OK) {
       *it = iter;
       memcpy(n, ncur, sizeof(ncur));
       return OR_EDOMAIN;
@@ -461,9 +536,9 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
       memcpy(n, ncur, sizeof(ncur));
       return OR_OK;
     }
-    or_tangent(m, F, ncur, Kr);
+    or_tangent(m, F, ncur, site, Kr);
     for (int k = 0; k < 9; ++k) Kr[10 * k] += rho;
-    lce_rotation_term(m, F, ncur, w, V, ncl, Kr);
+    lce_rotation_term(m, site, F, ncur, w, V, ncl, Kr);
     /* the relaxed step only where phi_r is convex with modulus rho/4: then
        the minimiser is locally unique and the step well conditioned */
     double Ks[81];
@@ -473,19 +548,19 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
       or_newton rest = *opt;
       int it2 = 0;
       rest.max_iter = opt->max_iter - iter;
-      int rc = newton_fixed_n(m, rho, A, &rest, F, ncur, &it2);
+      int rc = newton_fixed_n(m, rho, A, &rest, F, ncur, site, &it2);
       *it = iter + it2;
       if (rc == OR_EDOMAIN)
         memcpy(n, ncur, sizeof(ncur));
       else
-        director_eig(F, ncur, n, w, V);
+        director_eig(m, site, F, ncur, n, w, V);
       return rc;
     }
     double mg[9];
     for (int k = 0; k < 9; ++k) mg[k] = -g[k];
     chol9_solve(Kr, mg, d);
     double slope = dot9(g, d);
-    double phi0 = prox_objective(m, rho, A, F, ncur);
+    double phi0 = prox_objective(m, rho, A, F, ncur, site);
     double fn0 = norm9(F);
     double floor_phi = 1e-12 * scale_mod * (1.0 + fn0 * fn0);
     int small = -slope <= floor_phi;
@@ -495,15 +570,15 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
     for (int ls = 0; ls < 60; ++ls) {
       for (int k = 0; k < 9; ++k) Ft[k] = F[k] + t * d[k];
       if (det3(Ft) > 0.0) {
-        nclt = director_eig(Ft, ncur, nt, wt, Vt);
+        nclt = director_eig(m, site, Ft, ncur, nt, wt, Vt);
         if (!small) {
-          if (prox_objective(m, rho, A, Ft, nt) <= phi0 + 1e-4 * t * slope) {
+          if (prox_objective(m, rho, A, Ft, nt, site) <= phi0 + 1e-4 * t * slope) {
             accepted = 1;
             break;
           }
         } else {
           double Pt[9], gt[9];
-          or_stress(m, Ft, nt, Pt);
+          or_stress(m, Ft, nt, site, Pt);
           for (int k = 0; k < 9; ++k) gt[k] = Pt[k] + rho * (Ft[k] - A[k]);
           if (norm9(gt) <= (1.0 - 1e-4 * t) * gn) {
             accepted = 1;
@@ -535,15 +610,15 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
   return OR_NOT_CONVERGED;
 }
 
-int or_prox(const or_material *m, double rho, const double A[9],
+int or_prox(const or_material *m, double rho, const double A[9], const or_site *site,
             const or_newton *opt, double F[9], double n[3], int *iters) {
   if (!m || !A || !opt || !F || !(rho > 0.0)) return OR_EINVAL;
   int it = 0, rc;
   if (m->model == OR_NEOHOOKE) {
-    rc = newton_fixed_n(m, rho, A, opt, F, n, &it);
+    rc = newton_fixed_n(m, rho, A, opt, F, n, NULL, &it);
   } else {
-    if (!n || !(m->a >= 1.0)) return OR_EINVAL;
-    rc = newton_relaxed(m, rho, A, opt, F, n, &it);
+    if (!n || !lce_site_ok(m, site)) return OR_EINVAL;
+    rc = newton_relaxed(m, rho, A, opt, F, n, site, &it);
   }
   if (iters) *iters = it;
   return rc;
@@ -727,25 +802,110 @@ double or_rho_update(double rho, double r_p, double r_d, const or_params *p) {
   return out;
 }
 
+/* The data of Step 1 beyond A and rho for the full LCE model (Sec. 5.1). */
+typedef struct {
+  int n1, n2, n3;
+  size_t V;
+  const unsigned char *phase;
+  const or_material *mats;
+  const double *director0; /* cross-link directors (non-ideality) */
+  const double *lag;       /* directors at the start of the iteration (Frank) */
+  const double *dir_n;     /* directors at the start of the call (dissipation) */
+  const double *F_n;       /* F at the start of the call (dissipation) */
+  double dt;
+} step1_data;
+
+/* Local problem of voxel x. Returns its site (NULL for the ideal model) and,
+   where F is dissipative, turns (rho, A) into the equivalent
+   (rho + nu_F/dt, (rho A + nu_F/dt F^n) / (rho + nu_F/dt)). The site's Sc:
+   the Frank energy kappa_F/2 sum over bonds |Q(x+e) - Q(x)|^2, Q = n (x) n,
+   equals const - kappa_F sum over bonds (n(x) . n(y))^2 for unit directors,
+   so with the neighbours lagged (the second approach of Sec. 2.1 for
+   gradients of internal variables) voxel x sees -kappa_F sum_y n~(y) n~(y)^T
+   over its six neighbours of an LCE phase; the director's dissipation
+   nu_n/(2 dt)|n - n^n|^2 is taken in the sign-blind form
+   nu_n/(2 dt)(1 - (n . n^n)^2) (equal to first order), i.e.
+   -(nu_n/(2 dt)) n^n n^n^T. */
+static const or_site *step1_site(const step1_data *c, size_t x, double *rho, double A[9],
+                                 double Fn_buf[9], or_site *s) {
+  const or_material *m = &c->mats[c->phase[x]];
+  if (m->nu_F > 0.0) {
+    double nu = m->nu_F / c->dt, r2 = *rho + nu;
+    for (int k = 0; k < 9; ++k) {
+      Fn_buf[k] = c->F_n[k * c->V + x];
+      A[k] = (*rho * A[k] + nu * Fn_buf[k]) / r2;
+    }
+    *rho = r2;
+  }
+  if (m->model != OR_LCE || (m->alpha == 0.0 && m->frank == 0.0 && m->nu_n == 0.0)) return NULL;
+  for (int k = 0; k < 3; ++k) s->n0[k] = c->director0 ? c->director0[k * c->V + x] : 0.0;
+  for (int k = 0; k < 9; ++k) s->Sc[k] = 0.0;
+  if (m->frank > 0.0) {
+    int k1 = (int)(x % (size_t)c->n1), k2 = (int)((x / (size_t)c->n1) % (size_t)c->n2),
+        k3 = (int)(x / ((size_t)c->n1 * c->n2));
+    for (int d = 0; d < 6; ++d) {
+      int j1 = k1, j2 = k2, j3 = k3, sg = (d & 1) ? -1 : 1;
+      if (d < 2) j1 = (k1 + sg + c->n1) % c->n1;
+      else if (d < 4) j2 = (k2 + sg + c->n2) % c->n2;
+      else j3 = (k3 + sg + c->n3) % c->n3;
+      size_t y = ((size_t)j3 * c->n2 + j2) * c->n1 + j1;
+      if (c->mats[c->phase[y]].model != OR_LCE) continue;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          s->Sc[3 * i + j] -= m->frank * c->lag[i * c->V + y] * c->lag[j * c->V + y];
+    }
+  }
+  if (m->nu_n > 0.0) {
+    double w = 0.5 * m->nu_n / c->dt;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        s->Sc[3 * i + j] -= w * c->dir_n[i * c->V + x] * c->dir_n[j * c->V + x];
+  }
+  return s;
+}
+
 int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
                 const or_material *mats, int n_mat, double Fbar[9],
                 const or_params *p, double *u, double *F, double *Lambda,
-                double *director, double *rho, double *hist_rp, double *hist_rd,
-                double *hist_rho, int *iters, int *newton_fail) {
+                double *director, const double *director0, double *rho, double *hist_rp,
+                double *hist_rd, double *hist_rho, int *iters, int *newton_fail) {
   if (!valid_dims(n1, n2, n3) || !phase || !mats || n_mat < 1 || !Fbar || !p || !u ||
       !F || !Lambda || !rho || !(*rho > 0.0) || p->max_iter < 0)
     return OR_EINVAL;
   size_t V = (size_t)n1 * n2 * n3;
   for (size_t x = 0; x < V; ++x)
     if (phase[x] >= n_mat) return OR_EINVAL;
-  for (int q = 0; q < n_mat; ++q)
-    if (mats[q].model == OR_LCE && !director) return OR_EINVAL;
+  int need_lag = 0, need_dirn = 0, need_Fn = 0;
+  for (int q = 0; q < n_mat; ++q) {
+    const or_material *m = &mats[q];
+    if (!(m->nu_F >= 0.0) || (m->nu_F > 0.0 && !(p->dt > 0.0))) return OR_EINVAL;
+    need_Fn |= m->nu_F > 0.0;
+    if (m->model != OR_LCE) continue;
+    if (!director || !(m->alpha >= 0.0) || !(m->frank >= 0.0) || !(m->nu_n >= 0.0) ||
+        !(m->a >= 1.0))
+      return OR_EINVAL;
+    if ((m->alpha > 0.0 || m->frank > 0.0 || m->nu_n > 0.0) && !(m->a > 1.0)) return OR_EINVAL;
+    if (m->alpha > 0.0 && !director0) return OR_EINVAL;
+    if (m->nu_n > 0.0 && !(p->dt > 0.0)) return OR_EINVAL;
+    need_lag |= m->frank > 0.0;
+    need_dirn |= m->nu_n > 0.0;
+  }
+  double *lag = need_lag ? (double *)malloc(3 * V * sizeof(double)) : NULL;
+  double *dir_n = need_dirn ? (double *)malloc(3 * V * sizeof(double)) : NULL;
+  double *F_n = need_Fn ? (double *)malloc(9 * V * sizeof(double)) : NULL;
+  if ((need_lag && !lag) || (need_dirn && !dir_n) || (need_Fn && !F_n)) {
+    free(lag); free(dir_n); free(F_n);
+    return OR_EINVAL;
+  }
+  if (dir_n) memcpy(dir_n, director, 3 * V * sizeof(double));
+  if (F_n) memcpy(F_n, F, 9 * V * sizeof(double));
+  step1_data s1 = {n1, n2, n3, V, phase, mats, director0, lag, dir_n, F_n, p->dt};
 
   double *Gold = (double *)malloc(9 * V * sizeof(double));
   double *Gnew = (double *)malloc(9 * V * sizeof(double));
   double *H = (double *)malloc(9 * V * sizeof(double));
   if (!Gold || !Gnew || !H) {
-    free(Gold); free(Gnew); free(H);
+    free(Gold); free(Gnew); free(H); free(lag); free(dir_n); free(F_n);
     return OR_EINVAL;
   }
   or_gradient(n1, n2, n3, u, Fbar, Gold); /* grad u_0 = Fbar + D_h u_0 */
@@ -755,7 +915,7 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
   double rd_prev = p->local_rd_prev;
   double *g2 = (double *)malloc(V * sizeof(double));
   if (!g2) {
-    free(Gold); free(Gnew); free(H);
+    free(Gold); free(Gnew); free(H); free(lag); free(dir_n); free(F_n);
     return OR_EINVAL;
   }
   if (p->local_ratio < 0.0 || p->local_fraction < 0.0 || p->local_fraction > 1.0 ||
@@ -763,11 +923,12 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
       (p->local_ratio > 0.0 && p->local_fraction > 0.0) ||
       ((p->local_ratio > 0.0 || p->local_fraction > 0.0) &&
        (p->local_chunk < 1 || p->local_passes < 1))) {
-    free(Gold); free(Gnew); free(H); free(g2);
+    free(Gold); free(Gnew); free(H); free(g2); free(lag); free(dir_n); free(F_n);
     return OR_EINVAL;
   }
   for (int it = 0; it < p->max_iter; ++it) {
     double r = *rho;
+    if (lag) memcpy(lag, director, 3 * V * sizeof(double));
     double rl = 0.0; /* r_l after Step 1 (0 when solved exactly) */
     const int inexact = p->local_fraction > 0.0 ||
                         (p->local_ratio > 0.0 && p->local_start_iter + it > 0);
@@ -791,15 +952,18 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
             for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
           const or_material *m = &mats[phase[x]];
           int its = 0;
-          int pr = or_prox(m, r, A, &chunk, Fx, nx, &its);
+          double rx = r, Fn[9];
+          or_site sb;
+          const or_site *site = step1_site(&s1, x, &rx, A, Fn, &sb);
+          int pr = or_prox(m, rx, A, site, &chunk, Fx, nx, &its);
           if (pr == OR_OK) conv += 1;
-          if (pr == OR_EDOMAIN || or_stress(m, Fx, nx, P) != OR_OK) {
+          if (pr == OR_EDOMAIN || or_stress(m, Fx, nx, site, P) != OR_OK) {
             dom += 1;
             g2[x] = 0.0;
           } else {
             double s2 = 0.0;
             for (int c = 0; c < 9; ++c) {
-              double gc = P[c] + r * (Fx[c] - A[c]);
+              double gc = P[c] + rx * (Fx[c] - A[c]);
               s2 += gc * gc;
             }
             g2[x] = s2;
@@ -836,7 +1000,10 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
         if (director)
           for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
         int its = 0;
-        int pr = or_prox(&mats[phase[x]], r, A, &p->newton, Fx, nx, &its);
+        double rx = r, Fn[9];
+        or_site sb;
+        const or_site *site = step1_site(&s1, x, &rx, A, Fn, &sb);
+        int pr = or_prox(&mats[phase[x]], rx, A, site, &p->newton, Fx, nx, &its);
         if (pr == OR_NOT_CONVERGED) fails += 1;
         if (pr == OR_EDOMAIN) dom += 1;
         for (int c = 0; c < 9; ++c) F[c * V + x] = Fx[c];
@@ -899,13 +1066,16 @@ int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
   free(Gnew);
   free(H);
   free(g2);
+  free(lag);
+  free(dir_n);
+  free(F_n);
   return rc;
 }
 
 int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
                    const or_material *mats, int n_mat, const double *F,
-                   const double *director, const double *Lambda, double P_mean[9],
-                   double Lambda_mean[9]) {
+                   const double *director, const double *director0, const double *Lambda,
+                   double P_mean[9], double Lambda_mean[9]) {
   if (!valid_dims(n1, n2, n3) || !phase || !mats || !F) return OR_EINVAL;
   size_t V = (size_t)n1 * n2 * n3;
   double sP[9] = {0}, sL[9] = {0};
@@ -915,7 +1085,13 @@ int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
     for (int c = 0; c < 9; ++c) Fx[c] = F[c * V + x];
     if (director)
       for (int c = 0; c < 3; ++c) nx[c] = director[c * V + x];
-    if (or_stress(&mats[phase[x]], Fx, nx, P) != OR_OK) return OR_EDOMAIN;
+    or_site sb, *site = NULL;
+    if (director0 && mats[phase[x]].model == OR_LCE && mats[phase[x]].alpha != 0.0) {
+      for (int c = 0; c < 3; ++c) sb.n0[c] = director0[c * V + x];
+      for (int c = 0; c < 9; ++c) sb.Sc[c] = 0.0;
+      site = &sb;
+    }
+    if (or_stress(&mats[phase[x]], Fx, nx, site, P) != OR_OK) return OR_EDOMAIN;
     for (int c = 0; c < 9; ++c) sP[c] += P[c];
     if (Lambda)
       for (int c = 0; c < 9; ++c) sL[c] += Lambda[c * V + x];
@@ -924,5 +1100,24 @@ int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
     if (P_mean) P_mean[c] = sP[c] / (double)V;
     if (Lambda_mean) Lambda_mean[c] = sL[c] / (double)V;
   }
+  return OR_OK;
+}
+
+int or_orientation(int n1, int n2, int n3, const unsigned char *phase,
+                   const or_material *mats, int n_mat, const double *director,
+                   double S[9]) {
+  if (!valid_dims(n1, n2, n3) || !phase || !mats || !director || !S) return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3, cnt = 0;
+  double Q[9] = {0};
+  for (size_t x = 0; x < V; ++x) {
+    if (phase[x] >= n_mat) return OR_EINVAL;
+    if (mats[phase[x]].model != OR_LCE) continue;
+    double n[3] = {director[x], director[V + x], director[2 * V + x]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q[3 * i + j] += n[i] * n[j];
+    cnt += 1;
+  }
+  for (int k = 0; k < 9; ++k)
+    S[k] = cnt ? 1.5 * (Q[k] / (double)cnt - ((k % 4 == 0) ? 1.0 / 3.0 : 0.0)) : 0.0;
   return OR_OK;
 }

@@ -39,14 +39,32 @@ enum { OR_NEOHOOKE = 0, OR_LCE = 1 };
  *   OR_NEOHOOKE: W = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 (ln J)^2
  *   OR_LCE:      W = mu/2 [ a^(1/3) (|F|^2 + (1/a - 1) |F^T n|^2) - 3 ]
  *                    + kappa/2 (J - 1)^2
+ *                    + mu alpha/2 (|F^T n|^2 - (n0 . F^T n)^2)
  *                (neo-classical energy with step length tensor
- *                 L(n) = a^(-1/3) (I + (a-1) n n), plus a volumetric penalty;
- *                 a >= 1: the director elongates the material) */
+ *                 L(n) = a^(-1/3) (I + (a-1) n n), a volumetric penalty, and
+ *                 the non-ideality of Sec. 5.1 with the cross-link director
+ *                 n0 of the voxel; a >= 1: the director elongates the
+ *                 material). The Frank term and the dissipation of Sec. 5.1
+ *                 enter the local problem through or_site (below) and
+ *                 or_admm_run. */
 typedef struct {
   int model;
   double mu, lambda; /* neo-Hookean */
   double a, kappa;   /* LCE */
+  double alpha;      /* LCE non-ideality strength (0: ideal) */
+  double frank;      /* LCE Frank constant kappa_F, energy density x voxel^2 */
+  double nu_F, nu_n; /* LCE dissipation coefficients of F and of the director */
 } or_material;
+
+/* What the full LCE model adds at one voxel: the cross-link director n0 of
+ * the non-ideality, and a constant symmetric form Sc (row-major 3x3) with
+ * W += n . Sc n, which carries the Frank term with the neighbours' directors
+ * lagged and the director's dissipation (or_admm_run builds it). A NULL site
+ * means alpha = 0 and Sc = 0. */
+typedef struct {
+  double n0[3];
+  double Sc[9];
+} or_site;
 
 /* Options of the per-voxel Newton solve of the local problem. */
 typedef struct {
@@ -92,6 +110,11 @@ typedef struct {
    * over u, which sets <F>_ij = <F_{i+1} - Lambda_i / rho>_ij, and Step 3
    * then leaves <Lambda>_ij = 0, so <P>_ij = 0 at convergence. */
   unsigned free_mask;
+  /* Time step of the load step (Sec. 5.1's implicit discretisation), read
+   * where a material has nu_F or nu_n > 0: Step 1 then adds
+   * nu_F/(2 dt) |F - F^n|^2 and nu_n/(2 dt) (1 - (n . n^n)^2), with F^n, n^n
+   * the fields at the start of the call. */
+  double dt;
 } or_params;
 
 /* ---- small pieces, exposed so that tests can pin each one ---- */
@@ -112,24 +135,28 @@ int or_project(int n1, int n2, int n3, const double *H, double *u,
                double *max_imag);
 
 /* Energy, first Piola stress and tangent dP_iJ/dF_kL (81 doubles, row
- * (3i+J), column (3k+L)) of one material point; n is read by OR_LCE only. */
-double or_energy(const or_material *m, const double F[9], const double n[3]);
+ * (3i+J), column (3k+L)) of one material point; n and site (may be NULL) are
+ * read by OR_LCE only. */
+double or_energy(const or_material *m, const double F[9], const double n[3],
+                 const or_site *site);
 int or_stress(const or_material *m, const double F[9], const double n[3],
-              double P[9]);
+              const or_site *site, double P[9]);
 int or_tangent(const or_material *m, const double F[9], const double n[3],
-               double C[81]);
+               const or_site *site, double C[81]);
 
 /* Top eigenvector of F F^T with the sign / tie rules of the director update.
  * n_prev: previous director (unit). Writes unit n. */
 int or_director(const double F[9], const double n_prev[3], double n[3]);
 
 /* LCE with the director eliminated: W_r(F) = min over unit n of W(F, n).
- * Writes the minimising director n (top eigenvector of F F^T, rules of
- * or_director), the stress P = dW_r/dF (= P(F, n)) and the tangent
+ * The director terms form a quadratic n . M(F) n; the minimiser is the
+ * eigenvector of the smallest eigenvalue of M (for the ideal model the top
+ * eigenvector of F F^T), with the rules of or_director for signs and ties.
+ * Writes n, the stress P = dW_r/dF (= P(F, n)) and the tangent
  * K = d2W_r/dF2 (81 doubles, or NULL), which adds to the fixed-director
- * tangent the top eigenvector's sensitivity to F. */
-int or_relaxed(const or_material *m, const double F[9], const double n_prev[3],
-               double n[3], double P[9], double K[81]);
+ * tangent the eigenvector's sensitivity to F. */
+int or_relaxed(const or_material *m, const double F[9], const or_site *site,
+               const double n_prev[3], double n[3], double P[9], double K[81]);
 
 /* Step 1 (local problem) at one point: F = argmin W(F,n) + rho/2 |F - A|^2,
  * for the LCE jointly over F and the unit director n (Newton on the relaxed
@@ -137,7 +164,7 @@ int or_relaxed(const or_material *m, const double F[9], const double n_prev[3],
  * the minimiser on exit; n (LCE) holds the previous director on entry and the
  * minimising one on exit. iters (may be NULL) receives the Newton iteration
  * count. */
-int or_prox(const or_material *m, double rho, const double A[9],
+int or_prox(const or_material *m, double rho, const double A[9], const or_site *site,
             const or_newton *opt, double F[9], double n[3], int *iters);
 
 /* Adaptive penalty rule applied after the convergence test. */
@@ -149,22 +176,31 @@ double or_rho_update(double rho, double r_p, double r_d, const or_params *p);
  *   phase: V bytes indexing mats; Fbar: macroscopic gradient (row-major; its
  *   free components, see free_mask, are updated in place);
  *   u (3V), F (9V), Lambda (9V): state, updated in place; director (3V) or NULL;
+ *   director0 (3V): cross-link directors of the non-ideality, or NULL (then
+ *   no material may have alpha != 0);
  *   rho: in/out penalty; hist_* (max_iter doubles each, may be NULL) receive
  *   r_p, r_d and the rho used at each iteration; iters: iterations done.
  * Returns OR_OK (converged or fixed count done), OR_NOT_CONVERGED, or an error. */
 int or_admm_run(int n1, int n2, int n3, const unsigned char *phase,
                 const or_material *mats, int n_mat, double Fbar[9],
                 const or_params *p, double *u, double *F, double *Lambda,
-                double *director, double *rho, double *hist_rp,
+                double *director, const double *director0, double *rho, double *hist_rp,
                 double *hist_rd, double *hist_rho, int *iters,
                 int *newton_fail);
 
 /* Homogenised first Piola stress <P> = (1/V) sum_x P(F(x)) (plain summation in
- * voxel order), and the mean multiplier <Lambda>. Either output may be NULL. */
+ * voxel order), and the mean multiplier <Lambda>. Either output may be NULL.
+ * director0 as in or_admm_run. */
 int or_mean_stress(int n1, int n2, int n3, const unsigned char *phase,
                    const or_material *mats, int n_mat, const double *F,
-                   const double *director, const double *Lambda,
-                   double P_mean[9], double Lambda_mean[9]);
+                   const double *director, const double *director0,
+                   const double *Lambda, double P_mean[9], double Lambda_mean[9]);
+
+/* Orientation tensor of Sec. 5 (polydomain order parameter):
+ * S = 3/2 (<n (x) n> - I/3) over the voxels whose phase is an LCE. */
+int or_orientation(int n1, int n2, int n3, const unsigned char *phase,
+                   const or_material *mats, int n_mat, const double *director,
+                   double S[9]);
 
 /* Number of OpenMP threads the oracle uses (1 without OpenMP). */
 int or_num_threads(void);
