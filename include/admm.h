@@ -79,6 +79,20 @@ typedef struct {
   int32_t reserved;
   double mu, lambda; /* neo-Hookean moduli */
   double a, kappa;   /* LCE: step-length ratio (>= 1), volumetric penalty */
+  /* The rest of Sec. 5.1's LCE model (0 = off; each needs a > 1):
+   *   alpha: non-ideality mu alpha/2 tr((I - n0 n0) F^T (n n) F) with the
+   *          voxel's cross-link director n0 (admm_rve.director0);
+   *   frank: Frank constant kappa_F of kappa_F/2 |grad(n (x) n)|^2 with
+   *          forward differences between neighbouring LCE voxels (lengths
+   *          in voxels), the neighbours' directors taken from the previous
+   *          iteration;
+   *   nu_n:  director dissipation nu_n/(2 dt)(1 - (n . n^n)^2), n^n the
+   *          director at the start of the load step.
+   * nu_F (any model): dissipation nu_F/(2 dt)|F - F^n|^2, F^n the field at
+   * the start of the load step. The library keeps the start-of-step copies
+   * (and the previous iteration's directors for the Frank term) in device
+   * memory it allocates at admm_init. */
+  double alpha, frank, nu_F, nu_n;
 } admm_material;
 
 /* One periodic cell (representative volume element). Pointers: device. */
@@ -92,6 +106,9 @@ typedef struct {
   void *Lambda;          /* 9V: multiplier (in/out) */
   void *director;        /* 3V unit director (in/out; required when a phase
                             is ADMM_LCE, else may be NULL) */
+  const void *director0; /* 3V unit cross-link director n0 of the
+                            non-ideality (read only; required when a phase
+                            has alpha > 0, else may be NULL) */
   double Fbar[9];        /* macroscopic gradient <F>, row-major, det > 0 */
 } admm_rve;
 
@@ -138,6 +155,8 @@ typedef struct {
   double local_fraction; /* in (0, 1]: every iteration, stop once the local
                            Newton solves (their own stopping rule) have
                            converged at >= local_fraction of the voxels (0) */
+  double dt;            /* time step of a load step, for the dissipation
+                           terms (admm_material nu_F, nu_n) (1) */
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;
@@ -186,6 +205,11 @@ int admm_set_free(admm_ctx *ctx, int32_t rve, uint32_t free_mask);
 /* The current <F> of cell `rve` (row-major): the prescribed load and the free
  * components' iterate. Synchronises the stream. */
 int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]);
+
+/* Orientation tensor of the LCE voxels of cell `rve` (the order parameter of
+ * Sec. 5's polydomain studies): S = 3/2 (<n (x) n> - I/3), row-major.
+ * Synchronises the stream. Errors: EINVAL (no LCE voxel). */
+int admm_orientation(admm_ctx *ctx, int32_t rve, double S_out[9]);
 
 /* Sets the penalty of one cell (rve >= 0) or of all cells (rve < 0). */
 int admm_set_rho(admm_ctx *ctx, int32_t rve, double rho);

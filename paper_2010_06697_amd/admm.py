@@ -26,7 +26,7 @@ NEOHOOKE, LCE = 0, 1
 # entry points declared in include/admm.h, in order
 ENTRY_POINTS = (
     "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_free",
-    "admm_get_fbar", "admm_set_rho",
+    "admm_get_fbar", "admm_orientation", "admm_set_rho",
     "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
     "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
     "admm_profile_read", "admm_autotune", "admm_strerror", "admm_destroy",
@@ -46,7 +46,9 @@ class Tuning(ctypes.Structure):
 class Material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mu", ctypes.c_double), ("lam", ctypes.c_double),
-                ("a", ctypes.c_double), ("kappa", ctypes.c_double)]
+                ("a", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("frank", ctypes.c_double),
+                ("nu_F", ctypes.c_double), ("nu_n", ctypes.c_double)]
 
 
 class Rve(ctypes.Structure):
@@ -54,7 +56,7 @@ class Rve(ctypes.Structure):
                 ("phase", ctypes.c_void_p), ("u", ctypes.c_void_p),
                 ("u_prev", ctypes.c_void_p), ("F", ctypes.c_void_p),
                 ("Lambda", ctypes.c_void_p), ("director", ctypes.c_void_p),
-                ("Fbar", ctypes.c_double * 9)]
+                ("director0", ctypes.c_void_p), ("Fbar", ctypes.c_double * 9)]
 
 
 class Params(ctypes.Structure):
@@ -68,7 +70,7 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("local_ratio", ctypes.c_double), ("local_chunk", ctypes.c_int32),
                 ("local_passes", ctypes.c_int32), ("local_fraction", ctypes.c_double),
-]
+                ("dt", ctypes.c_double)]
 
 
 _lib = None
@@ -93,6 +95,7 @@ def lib():
         L.admm_set_load.argtypes = [vp, i32, dp]
         L.admm_set_free.argtypes = [vp, i32, ctypes.c_uint32]
         L.admm_get_fbar.argtypes = [vp, i32, dp]
+        L.admm_orientation.argtypes = [vp, i32, dp]
         L.admm_set_rho.argtypes = [vp, i32, ctypes.c_double]
         L.admm_step.argtypes = [vp, i32, dp, dp, dp]
         L.admm_solve.argtypes = [vp, ip, ip]
@@ -178,6 +181,13 @@ def admm_get_fbar(ctx, rve: int) -> np.ndarray:
     F = np.zeros(9)
     _check(lib().admm_get_fbar(ctx, rve, _dptr(F)), "admm_get_fbar")
     return F
+
+
+def admm_orientation(ctx, rve: int) -> np.ndarray:
+    """S = 3/2 (<n (x) n> - I/3) over the LCE voxels of a cell (3x3)."""
+    S = np.zeros(9)
+    _check(lib().admm_orientation(ctx, rve, _dptr(S)), "admm_orientation")
+    return S.reshape(3, 3)
 
 
 def admm_set_rho(ctx, rve: int, rho: float) -> int:
@@ -281,6 +291,7 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     p.adapt_rho, p.max_iter, p.check_every, p.newton_max = 0, 200, 10, 100
     p.use_graph = 1
     p.local_ratio, p.local_chunk, p.local_passes, p.local_fraction = 0.0, 1, 8, 0.0
+    p.dt = 1.0
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -288,10 +299,12 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     return p
 
 
-def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0) -> Material:
+def material(model="neohooke", mu=1.0, lam=0.0, a=1.0, kappa=0.0, alpha=0.0, frank=0.0,
+             nu_F=0.0, nu_n=0.0) -> Material:
     m = Material()
     m.model = NEOHOOKE if model == "neohooke" else LCE
     m.mu, m.lam, m.a, m.kappa = float(mu), float(lam), float(a), float(kappa)
+    m.alpha, m.frank, m.nu_F, m.nu_n = float(alpha), float(frank), float(nu_F), float(nu_n)
     return m
 
 
@@ -307,7 +320,7 @@ class Solver:
 
     def __init__(self, phases, materials, Fbars, params: Params | None = None,
                  precision: str = "fp64", device: str = "cuda:0", stream=None,
-                 directors=None):
+                 directors=None, directors0=None):
         import torch
 
         self.torch = torch
@@ -321,7 +334,9 @@ class Solver:
         any_lce = any(m.model == LCE for m in mats)
         if directors is None:
             directors = [None] * len(phases)
-        for ph, Fb, n0 in zip(phases, Fbars, directors):
+        if directors0 is None:
+            directors0 = [None] * len(phases)
+        for ph, Fb, n0, nref in zip(phases, Fbars, directors, directors0):
             ph = np.ascontiguousarray(ph, np.uint8)
             n3, n2, n1 = ph.shape
             if admm_check_grid(n1, n2, n3) != OK:
@@ -334,12 +349,16 @@ class Solver:
                 "F": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "Lambda": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "director": None,
+                "director0": None,
             }
             if any_lce:
                 if n0 is None:
                     raise AdmmError(EINVAL, "an LCE phase needs a director field per cell")
                 n0 = np.ascontiguousarray(n0, np.float64).reshape(3, n3, n2, n1)
                 cell["director"] = torch.from_numpy(n0).to(self.device, self.dtype)
+            if nref is not None:
+                nref = np.ascontiguousarray(nref, np.float64).reshape(3, n3, n2, n1)
+                cell["director0"] = torch.from_numpy(nref).to(self.device, self.dtype)
             self.cells.append(cell)
             r = Rve()
             r.n[0], r.n[1], r.n[2] = n1, n2, n3
@@ -349,6 +368,7 @@ class Solver:
             r.F = cell["F"].data_ptr()
             r.Lambda = cell["Lambda"].data_ptr()
             r.director = cell["director"].data_ptr() if cell["director"] is not None else None
+            r.director0 = cell["director0"].data_ptr() if cell["director0"] is not None else None
             for k, v in enumerate(np.asarray(Fb, np.float64).reshape(9)):
                 r.Fbar[k] = v
             rves.append(r)
@@ -372,6 +392,9 @@ class Solver:
 
     def fbar(self, rve=0):
         return admm_get_fbar(self.ctx, rve)
+
+    def orientation(self, rve=0):
+        return admm_orientation(self.ctx, rve)
 
     def set_rho(self, rho, rve=-1):
         admm_set_rho(self.ctx, rve, rho)

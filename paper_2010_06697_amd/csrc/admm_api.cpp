@@ -237,6 +237,8 @@ struct admm_ctx {
   double2 *lpart_d = nullptr;
   double *fpart_d = nullptr;
   int2 *newton_part_d = nullptr;
+  std::vector<void *> owned;  // start-of-step copies and lagged directors
+  bool any_nuF = false, any_nun = false, any_frank = false;
   void *workspace = nullptr;
   bool own_workspace = false;
   LaunchCfg L{};
@@ -261,6 +263,20 @@ namespace {
     hipError_t e_ = (expr);                   \
     if (e_ != hipSuccess) return ADMM_EHIP;   \
   } while (0)
+
+// the start of a load step for the dissipation terms: F^n and n^n
+int snapshot_step(admm_ctx *c) {
+  const size_t s = c->fp64 ? 8 : 4;
+  for (int r = 0; r < c->n_rve; ++r) {
+    const RveDesc &D = c->desc_h[r];
+    const size_t V = (size_t)D.V;
+    if (D.E_step)
+      HIP_TRY(hipMemcpyAsync(D.E_step, D.E, 9 * V * s, hipMemcpyDeviceToDevice, c->stream));
+    if (D.dir_step)
+      HIP_TRY(hipMemcpyAsync(D.dir_step, D.dir, 3 * V * s, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return ADMM_OK;
+}
 
 int upload_states(admm_ctx *c) {
   HIP_TRY(hipMemcpyAsync(c->state_d, c->state_h.data(), sizeof(RveState) * c->n_rve,
@@ -323,6 +339,7 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   ip.local_chunk = p.local_chunk;
   ip.local_passes = p.local_passes;
   ip.local_fraction = p.local_fraction;
+  ip.dt = p.dt;
   return ip;
 }
 
@@ -480,6 +497,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->newton_part_d);
   (void)hipFree(c->lpart_d);
   (void)hipFree(c->fpart_d);
+  for (void *q : c->owned) (void)hipFree(q);
   if (c->own_workspace) (void)hipFree(c->workspace);
   for (auto &g : c->graph)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -664,18 +682,30 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   *out = nullptr;
   if (!rves || n_rve <= 0 || !mats || n_mat <= 0 || n_mat > 256 || !params) return ADMM_EINVAL;
   if (precision != ADMM_FP64 && precision != ADMM_FP32_FP64RED) return ADMM_EINVAL;
-  bool any_lce = false;
+  bool any_lce = false, any_ext = false, any_alpha = false, any_frank = false, any_nun = false,
+       any_nuF = false;
   for (int q = 0; q < n_mat; ++q) {
-    if (mats[q].model == ADMM_LCE) {
-      if (!(mats[q].mu > 0.0) || !(mats[q].a >= 1.0) || !(mats[q].kappa >= 0.0)) return ADMM_EINVAL;
+    const admm_material &m = mats[q];
+    if (!(m.alpha >= 0.0) || !(m.frank >= 0.0) || !(m.nu_F >= 0.0) || !(m.nu_n >= 0.0))
+      return ADMM_EINVAL;
+    const bool lce_terms = m.alpha > 0.0 || m.frank > 0.0 || m.nu_n > 0.0;
+    if (m.model == ADMM_LCE) {
+      if (!(m.mu > 0.0) || !(m.a >= 1.0) || !(m.kappa >= 0.0)) return ADMM_EINVAL;
+      if (lce_terms && !(m.a > 1.0)) return ADMM_EINVAL;
       any_lce = true;
-    } else if (mats[q].model == ADMM_NEOHOOKE) {
-      if (!(mats[q].mu > 0.0) || !(mats[q].lambda >= 0.0)) return ADMM_EINVAL;
+    } else if (m.model == ADMM_NEOHOOKE) {
+      if (!(m.mu > 0.0) || !(m.lambda >= 0.0) || lce_terms) return ADMM_EINVAL;
     } else {
       return ADMM_EINVAL;
     }
+    any_ext = any_ext || lce_terms || m.nu_F > 0.0;
+    any_alpha = any_alpha || m.alpha > 0.0;
+    any_frank = any_frank || m.frank > 0.0;
+    any_nun = any_nun || m.nu_n > 0.0;
+    any_nuF = any_nuF || m.nu_F > 0.0;
   }
   const admm_params &p = *params;
+  if ((any_nun || any_nuF) && !(p.dt > 0.0)) return ADMM_EINVAL;
   if (!(p.rho0 > 0.0) || !(p.rho_min > 0.0) || !(p.rho_max >= p.rho_min) || !(p.kappa_rho > 1.0) ||
       !(p.tau > 0.0) || !(p.mu_ref > 0.0) || !(p.tol_p >= 0.0) || !(p.tol_d >= 0.0) ||
       p.max_iter < 1 || p.newton_max < 1 || !(p.newton_gtol >= 0.0) || !(p.newton_step_tol >= 0.0) ||
@@ -691,6 +721,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     if (g != ADMM_OK) return g;
     if (!R.phase || !R.u || !R.u_prev || !R.F || !R.Lambda || R.u == R.u_prev) return ADMM_EINVAL;
     if (any_lce && !R.director) return ADMM_EINVAL;
+    if (any_alpha && !R.director0) return ADMM_EINVAL;
     if (!valid_fbar(R.Fbar)) return ADMM_EINVAL;
   }
   const bool fp64 = precision == ADMM_FP64;
@@ -788,6 +819,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.E = R.F;
     D.Lam = R.Lambda;
     D.dir = R.director;
+    D.dir0 = R.director0;
+    D.dir_lag = D.dir_step = D.E_step = nullptr;
     D.spec = static_cast<char *>(c->workspace) + spec_off;
     spec_off += spec_bytes(D.n1, D.n2, D.n3, fp64);
     const int nrows = D.n2 * D.n3;
@@ -804,6 +837,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
   c->L.any_lce = any_lce;
+  c->L.lce_kind = any_ext ? 2 : (any_lce ? 1 : 0);
+  c->L.any_frank = any_frank;
   c->L.any_free = false;
   c->L.stream = c->stream;
   c->L.nblk_x = bx[n_rve];
@@ -817,6 +852,34 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   c->L.n3max = n3max;
   c->L.lds_x = (size_t)lds_x * csz;
 
+  // the full LCE model's copies: directors of the previous iteration (Frank
+  // term), directors and F at the start of the load step (dissipation)
+  c->any_frank = any_frank;
+  c->any_nun = any_nun;
+  c->any_nuF = any_nuF;
+  {
+    const size_t s = fp64 ? 8 : 4;
+    for (int r = 0; r < n_rve; ++r) {
+      RveDesc &D = c->desc_h[r];
+      const size_t V = (size_t)D.V;
+      void *q = nullptr;
+      if (any_frank) {
+        INIT_TRY(hipMalloc(&q, 3 * V * s));
+        c->owned.push_back(q);
+        D.dir_lag = q;
+      }
+      if (any_nun) {
+        INIT_TRY(hipMalloc(&q, 3 * V * s));
+        c->owned.push_back(q);
+        D.dir_step = q;
+      }
+      if (any_nuF) {
+        INIT_TRY(hipMalloc(&q, 9 * V * s));
+        c->owned.push_back(q);
+        D.E_step = q;
+      }
+    }
+  }
   INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
   INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
   INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 5 * (n_rve + 1)));
@@ -833,8 +896,10 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   for (int q = 0; q < n_mat; ++q) {
     const admm_material &m = mats[q];
     const bool lce = m.model == ADMM_LCE;
-    mh[q] = Material{m.model, 0, m.mu, m.lambda, m.a, m.kappa,
-                     lce ? m.mu * std::cbrt(m.a) : 0.0, lce ? 1.0 / m.a - 1.0 : 0.0};
+    const int ext = (m.alpha > 0.0 || m.frank > 0.0 || m.nu_n > 0.0 || m.nu_F > 0.0) ? 1 : 0;
+    mh[q] = Material{m.model, ext, m.mu, m.lambda, m.a, m.kappa,
+                     lce ? m.mu * std::cbrt(m.a) : 0.0, lce ? 1.0 / m.a - 1.0 : 0.0,
+                     m.mu * m.alpha, m.frank, m.nu_F, m.nu_n};
   }
   INIT_TRY(hipMalloc(&c->mats_d, sizeof(Material) * n_mat));
   INIT_TRY(hipMemcpy(c->mats_d, mh.data(), sizeof(Material) * n_mat, hipMemcpyHostToDevice));
@@ -882,6 +947,10 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.fpart = c->fpart_d;
   A.n_rve = n_rve;
   A.n_mat = n_mat;
+  if (snapshot_step(c) != ADMM_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_ctx(c);
+    return ADMM_EHIP;
+  }
 #undef INIT_TRY
   *out = c;
   return ADMM_OK;
@@ -910,6 +979,7 @@ int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
   s.newton_iters = 0;
   s.domain_err = 0;
   int rc = upload_states(ctx);
+  if (rc == ADMM_OK) rc = snapshot_step(ctx);  // a new time step starts here
   if (rc != ADMM_OK) return rc;
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return ADMM_OK;
@@ -938,6 +1008,19 @@ int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]) {
   if (rc != ADMM_OK) return rc;
   for (int k = 0; k < 9; ++k)
     Fbar_out[k] = ctx->state_h[rve].Ebar[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+  return ADMM_OK;
+}
+
+int admm_orientation(admm_ctx *ctx, int32_t rve, double S_out[9]) {
+  if (!ctx || !S_out || rve < 0 || rve >= ctx->n_rve || !ctx->L.any_lce) return ADMM_EINVAL;
+  HIP_TRY(launch_orientation(ctx->L, ctx->A, ctx->fp64));
+  double q[18];
+  HIP_TRY(hipMemcpyAsync(q, ctx->mean_d + 18 * (size_t)rve, sizeof(q), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const double cnt = q[9];
+  if (!(cnt > 0.0)) return ADMM_EINVAL;
+  for (int k = 0; k < 9; ++k) S_out[k] = 1.5 * (q[k] / cnt - ((k % 4 == 0) ? 1.0 / 3.0 : 0.0));
   return ADMM_OK;
 }
 

@@ -33,6 +33,10 @@ struct RveDesc {
   void *E;                  // F - I
   void *Lam;                // multiplier
   void *dir;                // director (LCE) or null
+  const void *dir0;         // cross-link director (non-ideality) or null
+  void *dir_lag;            // directors of the previous iteration (Frank) or null
+  void *dir_step;           // directors at the start of the load step (nu_n) or null
+  void *E_step;             // F - I at the start of the load step (nu_F) or null
   void *spec;               // 9 spectral components, layout [c][x3][x2][m1]
 };
 
@@ -62,10 +66,12 @@ constexpr int kLocalPassGrid = 2048;  // workgroups of the later inexact local p
 
 struct Material {
   int model;  // 0 neo-Hookean, 1 LCE
-  int pad;
+  int ext;    // 1: some term of the full LCE model (or nu_F) is on
   double mu, lam, a, kappa;
   double mua;   // mu a^(1/3)
   double beta;  // 1/a - 1
+  double mual;  // mu alpha (non-ideality)
+  double frank, nu_F, nu_n;
 };
 
 // scalar parameters of one launch sequence (passed by value: kernel arguments
@@ -85,6 +91,7 @@ struct IterParams {
   int local_chunk;
   int local_passes;
   double local_fraction;  // inexact local step, converged fraction (0: off)
+  double dt;              // time step (dissipation)
 };
 
 template <typename T> struct cplx;

@@ -112,12 +112,14 @@ __device__ __forceinline__ void block_sum(double *v, double *red /* LDS NV*nwave
 // iterations to its.
 template <typename T>
 __device__ int lce_local(T *E, const T *At, const Material &m, double rho, double *n,
-                         const IterParams &ip, int cap, int &its) {
+                         const IterParams &ip, int cap, int &its, const DirForm *form) {
   Lce<T> M;
   M.mua = (T)m.mua;
   M.beta = (T)m.beta;
   M.kappa = (T)m.kappa;
   M.mu = (T)m.mu;
+  M.mual = (T)m.mual;
+  M.form = form;
   const int rc = lce_newton<T>(E, At, M, m.mua * m.beta, (T)rho, n, cap, ip.gtol, ip.step_tol);
   its += rc >= 0 ? rc : cap;
   return rc;
@@ -140,7 +142,9 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // strategy configured), the first pass of an inexact step, a later pass
 enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2 };
 
-template <typename T, bool ANY_LCE, int MODE>
+// LK: 0 no LCE phase, 1 the ideal LCE, 2 some term of the full LCE model
+// (non-ideality, Frank, dissipation) or the dissipation of F
+template <typename T, int LK, int MODE>
 __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass, int blk) {
   const int r = find_rve(a.blk_x, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
@@ -158,8 +162,8 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
   int n_fail = 0, n_its = 0;
   double lsum[2] = {0.0, 0.0};  // |local residual|^2, converged
   if (row < R && grow < nrows) {
-    const double rho = st->rho;
-    const double irho = 1.0 / rho;
+    const double rho0 = st->rho;
+    const double irho = 1.0 / rho0;
     const int x2 = grow % n2, x3 = grow / n2;
     const int idx = grow * n1 + x1;
     const auto u = global_view(static_cast<const T *>(D.u[st->cur]));
@@ -174,19 +178,79 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
       E[c] = Eg[c * V + idx];
       At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
     }
-    const int ph = global_view(D.phase)[idx];
+    const auto phg = global_view(D.phase);
+    const int ph = phg[idx];
     if (ph < a.n_mat) {
       const Material m = a.mats[ph];
       const int cap = inexact ? ip.local_chunk : ip.newton_max;
       int rc;
-      if (ANY_LCE && m.model == 1) {
+      double rho = rho0;
+      if (LK == 2 && m.nu_F > 0.0) {
+        // dissipation of F: rho/2|F - A|^2 + nu/2|F - F^n|^2 is
+        // (rho + nu)/2 |F - (rho A + nu F^n)/(rho + nu)|^2 + const
+        const auto Es = global_view(static_cast<const T *>(D.E_step));
+        const double nu = m.nu_F / ip.dt, r2 = rho + nu;
+#pragma unroll
+        for (int c = 0; c < 9; ++c)
+          At[c] = (T)((rho * (double)At[c] + nu * (double)Es[c * V + idx]) / r2);
+        rho = r2;
+      }
+      if (LK >= 1 && m.model == 1) {
         const auto dg = global_view(static_cast<T *>(D.dir));
         double n[3] = {(double)dg[idx], (double)dg[V + idx], (double)dg[2 * V + idx]};
         const double nn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         n[0] *= nn;
         n[1] *= nn;
         n[2] *= nn;
-        rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its);
+        DirForm form;
+        const DirForm *fp = nullptr;
+        if (LK == 2 && (m.mual != 0.0 || m.frank != 0.0 || m.nu_n != 0.0)) {
+          // the full model's director terms at this voxel
+          form.gamma = m.mual / (-m.mua * m.beta);
+          form.inv_c = -2.0 / (m.mua * m.beta);
+          form.n0[0] = form.n0[1] = form.n0[2] = 0.0;
+          if (m.mual != 0.0) {
+            const auto d0 = global_view(static_cast<const T *>(D.dir0));
+            double q[3] = {(double)d0[idx], (double)d0[V + idx], (double)d0[2 * V + idx]};
+            const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) form.n0[k] = q[k] * qn;
+          }
+#pragma unroll
+          for (int k = 0; k < 6; ++k) form.sc[k] = 0.0;
+          if (m.frank != 0.0) {
+            // Frank term, neighbours of an LCE phase lagged by one iteration:
+            // Sc -= kappa_F sum_y n~(y) n~(y)^T
+            const auto lg = global_view(static_cast<const T *>(D.dir_lag));
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+              const int y = sn.o[q];
+              const int py = phg[y];
+              if (py >= a.n_mat || a.mats[py].model != 1) continue;
+              const double v0 = (double)lg[y], v1 = (double)lg[V + y], v2 = (double)lg[2 * V + y];
+              form.sc[0] -= m.frank * v0 * v0;
+              form.sc[1] -= m.frank * v0 * v1;
+              form.sc[2] -= m.frank * v0 * v2;
+              form.sc[3] -= m.frank * v1 * v1;
+              form.sc[4] -= m.frank * v1 * v2;
+              form.sc[5] -= m.frank * v2 * v2;
+            }
+          }
+          if (m.nu_n != 0.0) {
+            // director dissipation: Sc -= nu_n/(2 dt) n^n n^n^T
+            const auto ds = global_view(static_cast<const T *>(D.dir_step));
+            const double v0 = (double)ds[idx], v1 = (double)ds[V + idx], v2 = (double)ds[2 * V + idx];
+            const double w = 0.5 * m.nu_n / ip.dt;
+            form.sc[0] -= w * v0 * v0;
+            form.sc[1] -= w * v0 * v1;
+            form.sc[2] -= w * v0 * v2;
+            form.sc[3] -= w * v1 * v1;
+            form.sc[4] -= w * v1 * v2;
+            form.sc[5] -= w * v2 * v2;
+          }
+          fp = &form;
+        }
+        rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its, fp);
         dg[idx] = (T)n[0];
         dg[V + idx] = (T)n[1];
         dg[2 * V + idx] = (T)n[2];
@@ -196,6 +260,8 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
           M.beta = (T)m.beta;
           M.kappa = (T)m.kappa;
           M.mu = (T)m.mu;
+          M.mual = (T)m.mual;
+          M.form = fp;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             M.n[k] = (T)n[k];
@@ -266,16 +332,93 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
 // logical workgroups blockIdx.x, blockIdx.x + gridDim.x, ... (a multiple of
 // 8 workgroups, so each logical workgroup keeps its XCD). The exact mode
 // compiles without the inexact bookkeeping.
-template <typename T, bool ANY_LCE, int MODE>
+template <typename T, int LK, int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
 void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
   if (MODE != kLocalLater) {
-    local_tile<T, ANY_LCE, MODE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
+    local_tile<T, LK, MODE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
     return;
   }
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
-    local_tile<T, ANY_LCE, MODE>(a, ip, pass, xcd_remap(lb, nblk));
+    local_tile<T, LK, MODE>(a, ip, pass, xcd_remap(lb, nblk));
     __syncthreads();  // LDS of this tile read before the next one writes it
+  }
+}
+
+// Frank term: the directors of the previous iteration, copied before Step 1
+// so that every local problem sees its neighbours' lagged directors.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lag(KernelArgs a) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  if (!a.state[r].active || !D.dir_lag) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3, V = (int)D.V;
+  const int row = threadIdx.x / n1, x1 = threadIdx.x - row * n1;
+  const int grow = b * R + row;
+  if (row >= R || grow >= nrows) return;
+  const int idx = grow * n1 + x1;
+  const auto src = global_view(static_cast<const T *>(D.dir));
+  const auto dst = global_view(static_cast<T *>(D.dir_lag));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dst[k * V + idx] = src[k * V + idx];
+}
+
+// Orientation tensor: per local workgroup, the sums of n (x) n over its LCE
+// voxels (xx xy xz yy yz zz) and their count, then one workgroup per cell
+// writes <n (x) n> sums (9) and the count to mean_out.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_orient(KernelArgs a) {
+  __shared__ double red[7 * (kThreads / 64)];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3, V = (int)D.V;
+  const int row = threadIdx.x / n1, x1 = threadIdx.x - row * n1;
+  const int grow = b * R + row;
+  double v[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v[k] = 0.0;
+  if (row < R && grow < nrows && D.dir) {
+    const int idx = grow * n1 + x1;
+    const int ph = global_view(D.phase)[idx];
+    if (ph < a.n_mat && a.mats[ph].model == 1) {
+      const auto dg = global_view(static_cast<const T *>(D.dir));
+      const double n0 = dg[idx], n1v = dg[V + idx], n2v = dg[2 * V + idx];
+      v[0] = n0 * n0;
+      v[1] = n0 * n1v;
+      v[2] = n0 * n2v;
+      v[3] = n1v * n1v;
+      v[4] = n1v * n2v;
+      v[5] = n2v * n2v;
+      v[6] = 1.0;
+    }
+  }
+  block_sum<7>(v, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) a.fpart[(size_t)blk * 9 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_orient_final(KernelArgs a) {
+  __shared__ double red[7 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  const int x0 = a.blk_x[r], nx = a.blk_x[r + 1] - x0;
+  double v[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v[k] = 0.0;
+  for (int k = threadIdx.x; k < nx; k += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] += a.fpart[(size_t)(x0 + k) * 9 + c];
+  block_sum<7>(v, red);
+  if (threadIdx.x == 0) {
+    double *o = a.mean_out + 18 * (size_t)r;
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
+    o[3] = v[1]; o[4] = v[3]; o[5] = v[4];
+    o[6] = v[2]; o[7] = v[4]; o[8] = v[5];
+    o[9] = v[6];
   }
 }
 
@@ -847,6 +990,17 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
         M.n[0] = n0 * nn;
         M.n[1] = n1v * nn;
         M.n[2] = n2v * nn;
+        DirForm form;
+        if (m.mual != 0.0) {
+          // the non-ideality's stress needs the cross-link director
+          const T *d0 = static_cast<const T *>(D.dir0);
+          double q[3] = {(double)d0[idx], (double)d0[V + idx], (double)d0[2 * V + idx]};
+          const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) form.n0[k] = q[k] * qn;
+          M.mual = m.mual;
+          M.form = &form;
+        }
         ok = M.point(E, E, 0.0, s);
       } else {
         NeoHooke<double> M;
@@ -937,6 +1091,22 @@ static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
     hipLaunchKernelGGL((k_poisson_z<T, B>), grid, blk, lds, L.stream, a);
 }
 
+// one pass of Step 1 in the kernel variant of the context's materials
+template <typename T, int LK>
+static void launch_local(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, int pass,
+                         bool inexact) {
+  const dim3 blk(kThreads);
+  if (!inexact)
+    hipLaunchKernelGGL((k_local<T, LK, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, 0,
+                       L.nblk_x);
+  else if (pass == 0)
+    hipLaunchKernelGGL((k_local<T, LK, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, 0,
+                       L.nblk_x);
+  else
+    hipLaunchKernelGGL((k_local<T, LK, kLocalLater>), dim3(std::min(L.nblk_x, kLocalPassGrid)),
+                       blk, 0, L.stream, a, ip, pass, L.nblk_x);
+}
+
 template <typename T>
 static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
                                         const IterParams &ip, Part part) {
@@ -946,29 +1116,12 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       Timed tm(L, K_LOCAL);
       const bool inexact = ip.local_ratio > 0.0 || ip.local_fraction > 0.0;
       const int passes = inexact ? ip.local_passes : 1;
+      if (L.any_frank) hipLaunchKernelGGL((k_lag<T>), dim3(L.nblk_x), blk, 0, L.stream, a);
       for (int pass = 0; pass < passes; ++pass) {
-        if (!inexact) {
-          if (L.any_lce)
-            hipLaunchKernelGGL((k_local<T, true, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream,
-                               a, ip, 0, L.nblk_x);
-          else
-            hipLaunchKernelGGL((k_local<T, false, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream,
-                               a, ip, 0, L.nblk_x);
-        } else if (pass == 0) {
-          if (L.any_lce)
-            hipLaunchKernelGGL((k_local<T, true, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream,
-                               a, ip, 0, L.nblk_x);
-          else
-            hipLaunchKernelGGL((k_local<T, false, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream,
-                               a, ip, 0, L.nblk_x);
-        } else {
-          const int grid = std::min(L.nblk_x, kLocalPassGrid);
-          if (L.any_lce)
-            hipLaunchKernelGGL((k_local<T, true, kLocalLater>), dim3(grid), blk, 0, L.stream, a,
-                               ip, pass, L.nblk_x);
-          else
-            hipLaunchKernelGGL((k_local<T, false, kLocalLater>), dim3(grid), blk, 0, L.stream, a,
-                               ip, pass, L.nblk_x);
+        switch (L.lce_kind) {
+          case 0: launch_local<T, 0>(L, a, ip, pass, inexact); break;
+          case 1: launch_local<T, 1>(L, a, ip, pass, inexact); break;
+          default: launch_local<T, 2>(L, a, ip, pass, inexact); break;
         }
         if (inexact)
           hipLaunchKernelGGL(k_local_check, dim3(a.n_rve), blk, 0, L.stream, a, ip, pass);
@@ -1020,6 +1173,16 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       break;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_orientation(const LaunchCfg &L, const KernelArgs &a, bool fp64) {
+  const dim3 blk(kThreads);
+  if (fp64)
+    hipLaunchKernelGGL((k_orient<double>), dim3(L.nblk_x), blk, 0, L.stream, a);
+  else
+    hipLaunchKernelGGL((k_orient<float>), dim3(L.nblk_x), blk, 0, L.stream, a);
+  hipLaunchKernelGGL(k_orient_final, dim3(a.n_rve), blk, 0, L.stream, a);
   return hipGetLastError();
 }
 

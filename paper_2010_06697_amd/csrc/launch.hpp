@@ -54,10 +54,16 @@ struct LaunchCfg {
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
   bool any_lce;   // some phase uses the LCE energy
+  int lce_kind;   // 0 no LCE, 1 the ideal LCE, 2 some term of the full model or nu_F
+  bool any_frank; // the Frank term needs the previous iteration's directors
   bool any_free;  // some cell leaves components of <F> free
 };
 
 enum class Part { Local, Project, Update, MeanStress };
+
+// Orientation tensor sums of every cell into a.mean_out (<n (x) n> sums in
+// entries 0..8, the LCE voxel count in entry 9).
+hipError_t launch_orientation(const LaunchCfg &L, const KernelArgs &a, bool fp64);
 
 // Enqueues one part of the iteration on L.stream.
 hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, Part part,

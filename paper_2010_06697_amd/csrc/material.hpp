@@ -145,6 +145,24 @@ template <typename TG> struct NeoHooke {
   }
 };
 
+// What the full LCE model (Sec. 5.1) adds at one voxel. The director terms
+// of the energy are n . M n with M = -c F F^T + (mu alpha/2) F P0 F^T + Sc,
+// c = mu a^(1/3)(1 - 1/a)/2, P0 = I - n0 n0 (non-ideality, cross-link
+// director n0) and Sc constant (the Frank term with the neighbours'
+// directors lagged, the director's dissipation). The minimising director
+// is the top eigenvector of S = -M/c = F F^T - gamma (F F^T - (F n0)(F n0)^T)
+// - inv_c Sc, gamma = alpha / (a^(1/3)(1 - 1/a)), inv_c = 1/c.
+struct DirForm {
+  double n0[3];
+  double sc[6];  // Sc packed: xx, xy, xz, yy, yz, zz
+  double gamma, inv_c;
+};
+
+__device__ __forceinline__ double sc_at(const double *sc, int i, int j) {
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  return sc[lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)];
+}
+
 template <typename TG> struct Lce {
   TG mua;    // mu a^(1/3)
   TG beta;   // 1/a - 1
@@ -154,6 +172,8 @@ template <typename TG> struct Lce {
   double nd[3];  // the same director in double: the objective phi uses it,
                  // since a float-rounded director is not unit to 1e-8 and
                  // W depends on |n| at that level
+  TG mual = (TG)0;                 // mu alpha (non-ideality)
+  const DirForm *form = nullptr;   // null: the ideal model
 
   __device__ double smod() const { return (double)mua + (double)kappa; }
 
@@ -176,7 +196,12 @@ template <typename TG> struct Lce {
         const int a = 3 * i + j;
         const TG dia = (i == j) ? (TG)1 : (TG)0;
         const TG cof = cE[a] - E[3 * j + i] + dia * ((TG)1 + trt);  // J F^-T
-        const TG P = mua * (dia + E[a] + beta * n[i] * ftn[j]) + kv * cof;
+        TG P = mua * (dia + E[a] + beta * n[i] * ftn[j]) + kv * cof;
+        if (form) {
+          // non-ideality: mu alpha n (x) (F^T n - (n0 . F^T n) n0)
+          const TG q = (TG)form->n0[0] * ftn[0] + (TG)form->n0[1] * ftn[1] + (TG)form->n0[2] * ftn[2];
+          P += mual * n[i] * (ftn[j] - q * (TG)form->n0[j]);
+        }
         const TG g = P + rho * (E[a] - A[a]);
         s.G[a] = cof * iJ;
         s.g[a] = g;
@@ -202,8 +227,22 @@ template <typename TG> struct Lce {
       t2 += v * v;
     }
     const double f2 = 3.0 + 2.0 * tr + e2;
-    return 0.5 * (double)mua * (f2 + (double)beta * t2) - 1.5 * (double)mu +
-           0.5 * (double)kappa * s.jm1 * s.jm1 + 0.5 * rho * d2;
+    double W = 0.5 * (double)mua * (f2 + (double)beta * t2) - 1.5 * (double)mu +
+               0.5 * (double)kappa * s.jm1 * s.jm1 + 0.5 * rho * d2;
+    if (form) {
+      double ft[3], q = 0.0, sn = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        ft[l] = nd[l] + (double)E[l] * nd[0] + (double)E[3 + l] * nd[1] + (double)E[6 + l] * nd[2];
+        q += form->n0[l] * ft[l];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) sn += nd[i] * sc_at(form->sc, i, j) * nd[j];
+      W += 0.5 * (double)mual * (t2 - q * q) + sn;
+    }
+    return W;
   }
 
   template <typename TH>
@@ -217,7 +256,11 @@ template <typename TG> struct Lce {
   // mu a^(1/3) (1/a - 1) n_i n_k d_JL for the entry ((iJ), (kL))
   template <typename TH> __device__ __forceinline__ TH director_term(int a, int b) const {
     const int i = a / 3, J = a % 3, k = b / 3, L = b % 3;
-    return J == L ? (TH)(mua * beta * n[i] * n[k]) : (TH)0;
+    TH v = J == L ? (TH)(mua * beta * n[i] * n[k]) : (TH)0;
+    if (form)  // mu alpha n_i n_k (d_JL - n0_J n0_L)
+      v += (TH)(mual * n[i] * n[k]) *
+           ((TH)(J == L ? 1.0 : 0.0) - (TH)(form->n0[J] * form->n0[L]));
+    return v;
   }
 };
 
@@ -421,7 +464,7 @@ __device__ __forceinline__ void jacobi3(double *B, double *Vv) {
 // eigenvalue's cluster (1 when it is simple).
 template <typename TG>
 __device__ int director_eig(const TG *E, const double *np, double *n, double *w, double *V,
-                            const double *V0 = nullptr) {
+                            const double *V0 = nullptr, const DirForm *form = nullptr) {
   double F[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
@@ -431,6 +474,19 @@ __device__ int director_eig(const TG *E, const double *np, double *n, double *w,
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       B[3 * i + j] = F[3 * i] * F[3 * j] + F[3 * i + 1] * F[3 * j + 1] + F[3 * i + 2] * F[3 * j + 2];
+  if (form) {
+    // S = F F^T - gamma (F F^T - (F n0)(F n0)^T) - inv_c Sc
+    double fn0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      fn0[i] = F[3 * i] * form->n0[0] + F[3 * i + 1] * form->n0[1] + F[3 * i + 2] * form->n0[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        B[3 * i + j] = B[3 * i + j] - form->gamma * (B[3 * i + j] - fn0[i] * fn0[j]) -
+                       form->inv_c * sc_at(form->sc, i, j);
+  }
   if (V0) {
     // start from a nearby eigenbasis (the current iterate's): B <- V0^T B V0
     // is then almost diagonal and the sweeps converge at once
@@ -464,7 +520,7 @@ __device__ int director_eig(const TG *E, const double *np, double *n, double *w,
 #pragma unroll
     for (int k = 0; k < 3; ++k) V[3 * k + e] = Vv[3 * k + ord[e]];
   }
-  const double tie = 1e-12 * fabs(w[0]);
+  const double tie = 1e-12 * fmax(fabs(w[0]), fabs(w[2]));
   const int ncl = (w[0] - w[1] <= tie) ? ((w[0] - w[2] <= tie) ? 3 : 2) : 1;
   double out[3];
   if (ncl == 1) {
@@ -491,9 +547,10 @@ __device__ int director_eig(const TG *E, const double *np, double *n, double *w,
 }
 
 template <typename TG>
-__device__ void director_update(const TG *E, const double *np, double *n) {
+__device__ void director_update(const TG *E, const double *np, double *n,
+                                const DirForm *form = nullptr) {
   double w[3], V[9];
-  director_eig(E, np, n, w, V);
+  director_eig(E, np, n, w, V, nullptr, form);
 }
 
 // Cholesky factorisation of a packed lower triangle in place, with the
@@ -539,21 +596,39 @@ __device__ __forceinline__ void lce_relaxed_tangent(const T *E, const Lce<T> &M,
       if (a == b) v += dia;
       L[tri(a, b)] = v;
     }
-  // eigenvector sensitivity of the top eigenvalue
+  // eigenvector sensitivity of the top eigenvalue; with the non-ideality
+  // w_e also carries -gamma (t (x) P0 F^T n + n (x) P0 F^T t)
   double F[9], ftn[3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F[k] = (double)E[k] + ((k % 4 == 0) ? 1.0 : 0.0);
 #pragma unroll
   for (int J = 0; J < 3; ++J) ftn[J] = F[J] * nc[0] + F[3 + J] * nc[1] + F[6 + J] * nc[2];
+  const DirForm *fm = M.form;
+  double pftn[3] = {0.0, 0.0, 0.0};
+  if (fm) {
+    const double q = fm->n0[0] * ftn[0] + fm->n0[1] * ftn[1] + fm->n0[2] * ftn[2];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) pftn[J] = ftn[J] - q * fm->n0[J];
+  }
   for (int e = ncl; e < 3; ++e) {
     const double t0 = V[e], t1 = V[3 + e], t2 = V[6 + e];
-    double wk[9];
+    double wk[9], ftt[3];
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
-      const double ftt = F[J] * t0 + F[3 + J] * t1 + F[6 + J] * t2;
-      wk[J] = t0 * ftn[J] + nc[0] * ftt;
-      wk[3 + J] = t1 * ftn[J] + nc[1] * ftt;
-      wk[6 + J] = t2 * ftn[J] + nc[2] * ftt;
+      ftt[J] = F[J] * t0 + F[3 + J] * t1 + F[6 + J] * t2;
+      wk[J] = t0 * ftn[J] + nc[0] * ftt[J];
+      wk[3 + J] = t1 * ftn[J] + nc[1] * ftt[J];
+      wk[6 + J] = t2 * ftn[J] + nc[2] * ftt[J];
+    }
+    if (fm) {
+      const double q = fm->n0[0] * ftt[0] + fm->n0[1] * ftt[1] + fm->n0[2] * ftt[2];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) {
+        const double pftt = ftt[J] - q * fm->n0[J];
+        wk[J] -= fm->gamma * (t0 * pftn[J] + nc[0] * pftt);
+        wk[3 + J] -= fm->gamma * (t1 * pftn[J] + nc[1] * pftt);
+        wk[6 + J] -= fm->gamma * (t2 * pftn[J] + nc[2] * pftt);
+      }
     }
     const double f = c2 / (w[0] - w[e]);
 #pragma unroll
@@ -585,7 +660,7 @@ template <typename T>
 __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double *n, int maxit,
                           double gtol, double step_tol) {
   double w[3], V[9], nc[3];
-  int ncl = director_eig(E, n, nc, w, V);
+  int ncl = director_eig(E, n, nc, w, V, nullptr, M.form);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     M.n[k] = (T)nc[k];
@@ -625,7 +700,7 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
         ret = -2;
         break;
       }
-      director_update(E, nc, nc);
+      director_update(E, nc, nc, M.form);
       ret = r >= 0 ? it + r : -1;
       break;
     }
@@ -668,7 +743,7 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Et[k] = E[k] + (T)t * d[k];
-      nclt = director_eig(Et, nc, nt, wt, Vt, V);
+      nclt = director_eig(Et, nc, nt, wt, Vt, V, M.form);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         M.n[k] = (T)nt[k];

@@ -33,8 +33,15 @@ def neohooke(mu: float, lam: float) -> dict:
     return {"model": "neohooke", "mu": float(mu), "lam": float(lam), "a": 1.0, "kappa": 0.0}
 
 
-def lce(mu: float, a: float, kappa: float) -> dict:
-    return {"model": "lce", "mu": float(mu), "lam": 0.0, "a": float(a), "kappa": float(kappa)}
+def lce(mu: float, a: float, kappa: float, alpha: float = 0.0, frank: float = 0.0,
+        nu_F: float = 0.0, nu_n: float = 0.0) -> dict:
+    """LCE phase; alpha, frank, nu_F, nu_n: the non-ideality, Frank and
+    dissipation terms of the full model (0: off)."""
+    d = {"model": "lce", "mu": float(mu), "lam": 0.0, "a": float(a), "kappa": float(kappa)}
+    for k, v in (("alpha", alpha), ("frank", frank), ("nu_F", nu_F), ("nu_n", nu_n)):
+        if v:
+            d[k] = float(v)
+    return d
 
 
 # ----------------------------------------------------------------------------

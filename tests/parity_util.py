@@ -10,7 +10,8 @@ from paper_2010_06697_amd import admm
 
 
 def omats(mats):
-    return [O.material(m["model"], mu=m["mu"], lam=m["lam"], a=m["a"], kappa=m["kappa"])
+    return [O.material(m["model"], mu=m["mu"], lam=m["lam"], a=m["a"], kappa=m["kappa"],
+                       **{k: m[k] for k in ("alpha", "frank", "nu_F", "nu_n") if k in m})
             for m in mats]
 
 

@@ -32,9 +32,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(admm.Material) == 40
-    assert ctypes.sizeof(admm.Rve) == 16 + 6 * 8 + 72
-    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4 + 8 + 2 * 4 + 8
+    assert ctypes.sizeof(admm.Material) == 40 + 4 * 8
+    assert ctypes.sizeof(admm.Rve) == 16 + 7 * 8 + 72
+    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4 + 8 + 2 * 4 + 8 + 8
 
 
 @pytest.mark.parametrize("n,ok", [((16, 16, 16), True), ((256, 256, 256), True),
@@ -100,6 +100,18 @@ def test_init_rejects_invalid_arguments_before_touching_the_gpu():
     assert _init(good, [admm.material("lce", mu=1.0, a=2.0, kappa=1.0)], p) == admm.EINVAL
     assert _init(good, [admm.material("lce", mu=1.0, a=-2.0, kappa=1.0)], p) == admm.EINVAL
     assert _init(good, [admm.material("lce", mu=1.0, a=0.5, kappa=1.0)], p) == admm.EINVAL
+    # the full LCE model: non-negative terms, a > 1, LCE-only director terms,
+    # a positive time step for the dissipation, cross-link directors for alpha
+    lce_kw = dict(mu=1.0, a=2.0, kappa=1.0)
+    d = _rve((8, 8, 8))
+    d.director = d.u
+    for kw in (dict(alpha=-0.1), dict(frank=-1.0), dict(nu_F=-1.0), dict(nu_n=-1.0),
+               dict(alpha=0.1, a=1.0), dict(frank=0.1, a=1.0), dict(nu_n=0.1, a=1.0)):
+        assert _init([d], [admm.material("lce", **dict(lce_kw, **kw))], p) == admm.EINVAL, kw
+    assert _init(good, [admm.material(mu=1.0, lam=2.0, frank=0.1)], p) == admm.EINVAL
+    assert _init(good, [admm.material(mu=1.0, lam=2.0, nu_F=0.1)],
+                 admm.default_params(dt=0.0)) == admm.EINVAL
+    assert _init([d], [admm.material("lce", alpha=0.1, **lce_kw)], p) == admm.EINVAL
     assert _init([_rve((10, 8, 8))], m, p) == admm.EUNSUPPORTED
     assert _init(good, m, p, precision=7) == admm.EINVAL
     bad = _rve((8, 8, 8))
