@@ -88,6 +88,8 @@ def lib():
                                   dp, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]
         L.or_mean_stress.argtypes = [i, i, i, bp, mp, i, dp, dp, dp, dp, dp, dp]
         L.or_orientation.argtypes = [i, i, i, bp, mp, i, dp, dp]
+        L.or_bloch.argtypes = [i, i, i, bp, mp, i, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                               i, dp, dp, dp, dp, ip]
         L.or_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -315,6 +317,24 @@ def orientation(phase, mats, director_field):
                               _mats(mats), len(mats), _dp(director_field), _dp(S))
     assert rc == OK, rc
     return S.reshape(3, 3)
+
+
+def bloch(phase, mats, F, omega, rho, p0, tol=1e-12, max_iter=5000, director_field=None):
+    """Stability modulus over Bloch waves p exp(i omega.x) (omega in radians
+    per voxel) of the tangent field at F. p0: complex (3, n3, n2, n1) start.
+    Returns dict(rc, beta, sigma_rho, iters, p)."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    n3, n2, n1 = phase.shape
+    pr = np.ascontiguousarray(np.real(p0), dtype=np.float64).copy()
+    pi = np.ascontiguousarray(np.imag(p0), dtype=np.float64).copy()
+    b, sr = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    it = ctypes.c_int(0)
+    rc = lib().or_bloch(n1, n2, n3, phase.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                        _mats(mats), len(mats), _dp(np.ascontiguousarray(F, dtype=np.float64)),
+                        _dp(director_field), _dp(_vec(omega, 3)), float(rho), float(tol),
+                        int(max_iter), _dp(pr), _dp(pi), ctypes.byref(b), ctypes.byref(sr),
+                        ctypes.byref(it))
+    return {"rc": rc, "beta": b.value, "sigma_rho": sr.value, "iters": it.value, "p": pr + 1j * pi}
 
 
 def initial_state(shape, director0=None):

@@ -1121,3 +1121,234 @@ int or_orientation(int n1, int n2, int n3, const unsigned char *phase,
     S[k] = cnt ? 1.5 * (Q[k] / (double)cnt - ((k % 4 == 0) ? 1.0 / 3.0 : 0.0)) : 0.0;
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Bloch-wave stability modulus (Sec. 2.5)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* (D_w p)(x) for the complex field p (re, im: 3V each): 9 complex values */
+static void bloch_grad(int n1, int n2, int n3, const double *pr, const double *pi,
+                       const double w[3], size_t x, double gr[9], double gi[9]) {
+  size_t V = (size_t)n1 * n2 * n3;
+  int nn[3] = {n1, n2, n3};
+  int k[3] = {(int)(x % (size_t)n1), (int)((x / (size_t)n1) % (size_t)n2),
+              (int)(x / ((size_t)n1 * n2))};
+  for (int j = 0; j < 3; ++j) {
+    int kp[3] = {k[0], k[1], k[2]}, km[3] = {k[0], k[1], k[2]};
+    kp[j] = (k[j] + 1) % nn[j];
+    km[j] = (k[j] - 1 + nn[j]) % nn[j];
+    size_t xp = ((size_t)kp[2] * n2 + kp[1]) * n1 + kp[0];
+    size_t xm = ((size_t)km[2] * n2 + km[1]) * n1 + km[0];
+    double c = cos(w[j]), s = sin(w[j]);
+    for (int i = 0; i < 3; ++i) {
+      /* (p(x+e) e^{iw} - p(x-e) e^{-iw}) / 2 */
+      double ar = pr[i * V + xp], ai = pi[i * V + xp];
+      double br = pr[i * V + xm], bi = pi[i * V + xm];
+      gr[3 * i + j] = 0.5 * ((ar * c - ai * s) - (br * c + bi * s));
+      gi[3 * i + j] = 0.5 * ((ar * s + ai * c) - (bi * c - br * s));
+    }
+  }
+}
+
+/* tangent L + rho I at voxel x, Cholesky factorised; 0 when not positive definite */
+static int bloch_factor(const or_material *m, const double *F, const double *director, size_t V,
+                        size_t x, double rho, double K[81]) {
+  double Fx[9], n[3] = {0.0, 0.0, 1.0}, nn[3];
+  for (int c = 0; c < 9; ++c) Fx[c] = F[c * V + x];
+  if (director)
+    for (int c = 0; c < 3; ++c) n[c] = director[c * V + x];
+  if (m->model == OR_LCE) {
+    double P[9];
+    if (or_relaxed(m, Fx, NULL, n, nn, P, K) != OR_OK) return 0;
+  } else if (or_tangent(m, Fx, n, NULL, K) != OR_OK) {
+    return 0;
+  }
+  for (int k = 0; k < 9; ++k) K[10 * k] += rho;
+  return chol9(K);
+}
+
+int or_bloch(int n1, int n2, int n3, const unsigned char *phase, const or_material *mats,
+             int n_mat, const double *F, const double *director, const double omega[3],
+             double rho, double tol, int max_iter, double *p_re, double *p_im, double *beta,
+             double *sigma_rho, int *iters) {
+  if (!valid_dims(n1, n2, n3) || !phase || !mats || n_mat < 1 || !F || !omega || !(rho > 0.0) ||
+      !(tol >= 0.0) || max_iter < 1 || !p_re || !p_im || !beta)
+    return OR_EINVAL;
+  size_t V = (size_t)n1 * n2 * n3;
+  for (size_t x = 0; x < V; ++x)
+    if (phase[x] >= n_mat || (mats[phase[x]].model == OR_LCE && !director)) return OR_EINVAL;
+  double *Lf = (double *)malloc(81 * V * sizeof(double));      /* factors */
+  double *Gr = (double *)calloc(9 * V, sizeof(double)), *Gi = (double *)calloc(9 * V, sizeof(double));
+  double *gr = (double *)calloc(9 * V, sizeof(double)), *gi = (double *)calloc(9 * V, sizeof(double));
+  double *Hr = (double *)malloc(9 * V * sizeof(double)), *Hi = (double *)malloc(9 * V * sizeof(double));
+  double *br = (double *)malloc(3 * V * sizeof(double)), *bi = (double *)malloc(3 * V * sizeof(double));
+  double *sr = (double *)malloc(3 * V * sizeof(double)), *si = (double *)malloc(3 * V * sizeof(double));
+  double *K2 = (double *)malloc(V * sizeof(double)), *B2 = (double *)malloc(V * sizeof(double));
+  double *Dor = (double *)malloc(9 * V * sizeof(double)), *Doi = (double *)malloc(9 * V * sizeof(double));
+  int rc = OR_EINVAL;
+  if (!Lf || !Gr || !Gi || !gr || !gi || !Hr || !Hi || !br || !bi || !sr || !si || !K2 || !B2 ||
+      !Dor || !Doi)
+    goto done;
+  rc = OR_OK;
+  for (size_t x = 0; x < V && rc == OR_OK; ++x)
+    if (!bloch_factor(&mats[phase[x]], F, director, V, x, rho, Lf + 81 * x)) rc = OR_EDOMAIN;
+  if (rc != OR_OK) goto done;
+  {
+    /* start: p normalised, G = g = 0 */
+    double s2 = 0.0;
+    for (size_t k = 0; k < 3 * V; ++k) s2 += p_re[k] * p_re[k] + p_im[k] * p_im[k];
+    if (!(s2 > 0.0)) {
+      rc = OR_EINVAL;
+      goto done;
+    }
+    double sc = sqrt((double)V / s2);
+    for (size_t k = 0; k < 3 * V; ++k) {
+      p_re[k] *= sc;
+      p_im[k] *= sc;
+    }
+    /* |K(xi + w)|^2 with xi_j = 2 pi m_j / n_j */
+    int nn[3] = {n1, n2, n3};
+    double K2min = INFINITY;
+    for (size_t x = 0; x < V; ++x) {
+      int m[3] = {(int)(x % (size_t)n1), (int)((x / (size_t)n1) % (size_t)n2),
+                  (int)(x / ((size_t)n1 * n2))};
+      double k2 = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        double sj = sin(TWO_PI * m[j] / nn[j] + omega[j]);
+        k2 += sj * sj;
+      }
+      K2[x] = k2;
+      if (k2 < K2min) K2min = k2;
+    }
+    rc = OR_NOT_CONVERGED;
+    int done_it = 0;
+    double sig = 0.0;
+    for (int it = 0; it < max_iter; ++it) {
+      /* Step 1': G = (L + rho I)^{-1} (g + rho D_w p); keep D_w p for r_d */
+      for (size_t x = 0; x < V; ++x) {
+        double dr[9], di[9], rr[9], ri[9], xr[9], xi[9];
+        bloch_grad(n1, n2, n3, p_re, p_im, omega, x, dr, di);
+        for (int c = 0; c < 9; ++c) {
+          Dor[c * V + x] = dr[c];
+          Doi[c * V + x] = di[c];
+          rr[c] = gr[c * V + x] + rho * dr[c];
+          ri[c] = gi[c * V + x] + rho * di[c];
+        }
+        chol9_solve(Lf + 81 * x, rr, xr);
+        chol9_solve(Lf + 81 * x, ri, xi);
+        for (int c = 0; c < 9; ++c) {
+          Gr[c * V + x] = xr[c];
+          Gi[c * V + x] = xi[c];
+          Hr[c * V + x] = xr[c] - gr[c * V + x] / rho;
+          Hi[c * V + x] = xi[c] - gi[c * V + x] / rho;
+        }
+      }
+      /* Step 2': b = D_w^H H, (D_w^H H)_i(x) = sum_j (e^{-iw_j} H_ij(x-e_j) - e^{iw_j} H_ij(x+e_j))/2 */
+      for (size_t x = 0; x < V; ++x) {
+        int k[3] = {(int)(x % (size_t)n1), (int)((x / (size_t)n1) % (size_t)n2),
+                    (int)(x / ((size_t)n1 * n2))};
+        for (int i = 0; i < 3; ++i) {
+          double ar = 0.0, ai = 0.0;
+          for (int j = 0; j < 3; ++j) {
+            int kp[3] = {k[0], k[1], k[2]}, km[3] = {k[0], k[1], k[2]};
+            kp[j] = (k[j] + 1) % nn[j];
+            km[j] = (k[j] - 1 + nn[j]) % nn[j];
+            size_t xp = ((size_t)kp[2] * n2 + kp[1]) * n1 + kp[0];
+            size_t xm = ((size_t)km[2] * n2 + km[1]) * n1 + km[0];
+            double c = cos(omega[j]), s = sin(omega[j]);
+            double hmr = Hr[(3 * i + j) * V + xm], hmi = Hi[(3 * i + j) * V + xm];
+            double hpr = Hr[(3 * i + j) * V + xp], hpi = Hi[(3 * i + j) * V + xp];
+            /* e^{-iw} hm - e^{iw} hp */
+            ar += 0.5 * ((hmr * c + hmi * s) - (hpr * c - hpi * s));
+            ai += 0.5 * ((hmi * c - hmr * s) - (hpi * c + hpr * s));
+          }
+          br[i * V + x] = ar;
+          bi[i * V + x] = ai;
+        }
+      }
+      for (int i = 0; i < 3; ++i)
+        or_dft3(n1, n2, n3, br + i * V, bi + i * V, sr + i * V, si + i * V, 0);
+      double bb = 0.0;
+      for (size_t x = 0; x < V; ++x) {
+        double v = 0.0;
+        for (int i = 0; i < 3; ++i)
+          v += sr[i * V + x] * sr[i * V + x] + si[i * V + x] * si[i * V + x];
+        B2[x] = v;
+        bb += v;
+      }
+      if (!(bb > 0.0)) {
+        rc = OR_EINVAL;
+        break;
+      }
+      /* sum B2/(K2 - sigma)^2 = V^2 on (K2min - sqrt(bb)/V, K2min) by bisection */
+      double lo = K2min - sqrt(bb) / (double)V, hi = K2min;
+      for (int b = 0; b < 200; ++b) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double f = 0.0;
+        for (size_t x = 0; x < V; ++x) {
+          double d = K2[x] - mid;
+          f += B2[x] / (d * d);
+        }
+        if (f > (double)V * (double)V)
+          hi = mid;
+        else
+          lo = mid;
+      }
+      sig = lo;
+      for (size_t x = 0; x < V; ++x) {
+        double d = 1.0 / (K2[x] - sig);
+        for (int i = 0; i < 3; ++i) {
+          sr[i * V + x] *= d;
+          si[i * V + x] *= d;
+        }
+      }
+      for (int i = 0; i < 3; ++i)
+        or_dft3(n1, n2, n3, sr + i * V, si + i * V, p_re + i * V, p_im + i * V, 1);
+      /* Step 3' and 4' */
+      double sp = 0.0, sd = 0.0;
+      for (size_t x = 0; x < V; ++x) {
+        double dr[9], di[9];
+        bloch_grad(n1, n2, n3, p_re, p_im, omega, x, dr, di);
+        for (int c = 0; c < 9; ++c) {
+          double er = dr[c] - Gr[c * V + x], ei = di[c] - Gi[c * V + x];
+          gr[c * V + x] += rho * er;
+          gi[c * V + x] += rho * ei;
+          sp += er * er + ei * ei;
+          double fr = dr[c] - Dor[c * V + x], fi = di[c] - Doi[c * V + x];
+          sd += fr * fr + fi * fi;
+        }
+      }
+      double rp = sqrt(sp / (double)V), rd = rho * sqrt(sd / (double)V);
+      done_it = it + 1;
+      if (rp <= tol && rd <= tol) {
+        rc = OR_OK;
+        break;
+      }
+    }
+    /* Rayleigh quotient of the last p: <D_w p, L D_w p> with L = (L + rho I) - rho I */
+    double q = 0.0;
+    for (size_t x = 0; x < V; ++x) {
+      double dr[9], di[9];
+      bloch_grad(n1, n2, n3, p_re, p_im, omega, x, dr, di);
+      const double *L = Lf + 81 * x;
+      /* |L^T d|^2 - rho |d|^2 for real and imaginary parts */
+      for (int part = 0; part < 2; ++part) {
+        const double *d = part ? di : dr;
+        for (int j = 0; j < 9; ++j) {
+          double t = 0.0;
+          for (int i = j; i < 9; ++i) t += L[9 * i + j] * d[i];
+          q += t * t;
+        }
+        for (int j = 0; j < 9; ++j) q -= rho * d[j] * d[j];
+      }
+    }
+    *beta = q / (double)V;
+    if (sigma_rho) *sigma_rho = rho * sig;
+    if (iters) *iters = done_it;
+  }
+done:
+  free(Lf); free(Gr); free(Gi); free(gr); free(gi); free(Hr); free(Hi); free(br); free(bi);
+  free(sr); free(si); free(K2); free(B2); free(Dor); free(Doi);
+  return rc;
+}

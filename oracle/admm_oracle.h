@@ -202,6 +202,32 @@ int or_orientation(int n1, int n2, int n3, const unsigned char *phase,
                    const or_material *mats, int n_mat, const double *director,
                    double S[9]);
 
+/* Stability modulus of Sec. 2.5 (quadratic functionals and Bloch waves):
+ *   beta = min over unit Bloch waves v = p(x) exp(i omega . x), p periodic,
+ *          <p, p> = 1, of <grad v, L grad v>
+ * (averages over the unit-volume cell; L(x) = d2W/dF2 at the equilibrium
+ * state F, director; the LCE with its director eliminated). On the grid the
+ * gradient of v is exp(i omega . x) D_w p with the shifted central
+ * difference (D_w p)_ij(x) = (p_i(x+e_j) e^{i w_j} - p_i(x-e_j) e^{-i w_j})/2,
+ * omega in radians per voxel (2 pi/(k n_j) for a k-cell super-lattice along
+ * x_j). ADMM of Steps 1'-4' with penalty rho:
+ *   1' G = (L + rho I)^{-1} (g + rho D_w p)        (needs L + rho I > 0)
+ *   2' p = argmin over <p, p> = 1 of |D_w p - (G - g/rho)|^2: in Fourier
+ *      space p^ = b^ / (|K|^2 - sigma), b = D_w^H (G - g/rho),
+ *      |K|^2 = sum_j sin^2(xi_j + w_j), sigma < min |K|^2 the root of
+ *      sum |b^|^2/(|K|^2 - sigma)^2 = V^2 (bisection)
+ *   3' g += rho (D_w p - G)
+ *   4' r_p = |D_w p - G|, r_d = rho |D_w p - D_w p_prev| (RMS), both <= tol.
+ * p_re, p_im (3V each): start in (normalised first), mode out. beta: the
+ * Rayleigh quotient <D_w p, L D_w p> of the last p; sigma_rho (may be NULL):
+ * rho sigma of the last Step 2', which equals beta at the fixed point.
+ * Returns OR_OK, OR_NOT_CONVERGED, OR_EDOMAIN (L + rho I not positive
+ * definite) or OR_EINVAL. */
+int or_bloch(int n1, int n2, int n3, const unsigned char *phase, const or_material *mats,
+             int n_mat, const double *F, const double *director, const double omega[3],
+             double rho, double tol, int max_iter, double *p_re, double *p_im, double *beta,
+             double *sigma_rho, int *iters);
+
 /* Number of OpenMP threads the oracle uses (1 without OpenMP). */
 int or_num_threads(void);
 
