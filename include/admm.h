@@ -206,6 +206,31 @@ int admm_set_free(admm_ctx *ctx, int32_t rve, uint32_t free_mask);
  * components' iterate. Synchronises the stream. */
 int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]);
 
+/* Stability modulus over Bloch waves (Sec. 2.5, Steps 1'-4'): for cell
+ * `rve` of a double-precision context,
+ *   beta = min over periodic p with <p, p> = 1 of <D_w p, L D_w p>,
+ * L(x) = d2W/dF2 at the cell's current F (and director: the LCE with the
+ * director eliminated; the ideal LCE model only), D_w the central
+ * difference of the Bloch wave p exp(i omega . x), omega in radians per voxel
+ * (2 pi / (k n_j) for a k-cell super-lattice along x_j); beta < 0 means the
+ * periodic state is unstable against that wave. ADMM with penalty rho (L +
+ * rho I must be positive definite at every voxel); Step 2' minimises over
+ * the unit sphere exactly (Fourier space and a scalar secular equation), so
+ * the fixed point is the smallest eigenvalue's mode. Runs until the RMS
+ * residuals r_p, r_d <= tol or max_iter iterations.
+ *   p: device buffer of 3V complex doubles (interleaved re, im; [c][x3][x2][x1]):
+ *      start in, unit mode out.
+ *   beta_out: <D_w p, L D_w p> of the mode; sigma_rho_out (may be NULL):
+ *      rho sigma of the last Step 2' (equals beta at the fixed point);
+ *   iters_out, status_out (may be NULL): iterations, ADMM_OK or
+ *      ADMM_NOT_CONVERGED.
+ * Allocates its work buffers (about 1 KB per voxel) for the call.
+ * Errors: EINVAL, EUNSUPPORTED (float context, full LCE model terms),
+ * EDOMAIN (L + rho I not positive definite), ENOMEM, EHIP. */
+int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
+               int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
+               int32_t *iters_out, int32_t *status_out);
+
 /* Orientation tensor of the LCE voxels of cell `rve` (the order parameter of
  * Sec. 5's polydomain studies): S = 3/2 (<n (x) n> - I/3), row-major.
  * Synchronises the stream. Errors: EINVAL (no LCE voxel). */

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadmm.so")
-SOURCES = ["kernels.hip", "admm_api.cpp"]
+SOURCES = ["kernels.hip", "bloch.hip", "admm_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -1011,6 +1011,33 @@ int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]) {
   return ADMM_OK;
 }
 
+int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
+               int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
+               int32_t *iters_out, int32_t *status_out) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve || !omega || !p || !beta_out || !(rho > 0.0) ||
+      !(tol >= 0.0) || max_iter < 1)
+    return ADMM_EINVAL;
+  for (int j = 0; j < 3; ++j)
+    if (!std::isfinite(omega[j])) return ADMM_EINVAL;
+  if (!ctx->fp64 || ctx->L.lce_kind == 2) return ADMM_EUNSUPPORTED;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // the state the context iterates on: u is the current buffer after every
+  // call, and F, the director hold the last iterate
+  double beta = 0.0, sr = 0.0;
+  int it = 0, status = 1;
+  const int rc = bloch_solve(ctx->stream, ctx->desc_h[rve], ctx->mats_d, ctx->n_mat, ctx->tw_d,
+                             omega, rho, tol, max_iter, static_cast<double *>(p), &beta, &sr, &it,
+                             &status);
+  if (rc == -3) return ADMM_EDOMAIN;
+  if (rc == -2) return ADMM_EINVAL;
+  if (rc != 0) return ADMM_EHIP;
+  *beta_out = beta;
+  if (sigma_rho_out) *sigma_rho_out = sr;
+  if (iters_out) *iters_out = it;
+  if (status_out) *status_out = status == 0 ? ADMM_OK : ADMM_NOT_CONVERGED;
+  return ADMM_OK;
+}
+
 int admm_orientation(admm_ctx *ctx, int32_t rve, double S_out[9]) {
   if (!ctx || !S_out || rve < 0 || rve >= ctx->n_rve || !ctx->L.any_lce) return ADMM_EINVAL;
   HIP_TRY(launch_orientation(ctx->L, ctx->A, ctx->fp64));

@@ -61,6 +61,14 @@ struct LaunchCfg {
 
 enum class Part { Local, Project, Update, MeanStress };
 
+// Bloch-wave stability modulus of one cell (double precision; bloch.hip).
+// p: 3V complex (interleaved) start in, unit mode out. Returns 0, -1 (HIP
+// error), -2 (a zero start or right-hand side), -3 (L + rho I not positive
+// definite); status 0 converged, 1 iteration cap.
+int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_mat,
+                const void *tw, const double omega[3], double rho, double tol, int max_iter,
+                double *p, double *beta, double *sigma_rho, int *iters, int *status);
+
 // Orientation tensor sums of every cell into a.mean_out (<n (x) n> sums in
 // entries 0..8, the LCE voxel count in entry 9).
 hipError_t launch_orientation(const LaunchCfg &L, const KernelArgs &a, bool fp64);
