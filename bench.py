@@ -10,7 +10,8 @@ every field resident in HBM before it starts.
 
 Also reported on the same line: the all-double form at 256^3, the 128-cell
 batch (edges 32..96, one load step each to tol 1e-6) as cell solves/s, the
-256^3 LCE polydomain, the 64^3 wavy laminate's 30-step compression path in
+256^3 LCE polydomain (ideal, and with the full model's non-ideality,
+Frank and dissipation terms), the 64^3 wavy laminate's 30-step compression path in
 double and in float, the inexact local step against exact local solves (on
 the fibre cell and the LCE polydomain), the per-kernel times from hipEvents on the library's
 stream, the roofline of the dominant kernel, and the CPU oracle timed on the
@@ -186,10 +187,16 @@ def run_batch(count, steps_warm=2):
     return out
 
 
-def run_lce(steps, warmup):
+# the full LCE model's terms for the lce256_full line (Sec. 5.1; Frank
+# constant in units of mu x voxel^2)
+LCE_FULL = dict(alpha=0.1, frank=0.05, nu_F=0.1, nu_n=0.1)
+
+
+def run_lce(steps, warmup, full=False):
     """The LCE polydomain at 256^3 (1000 Voronoi grains, neo-classical a = 2,
     kappa = 100), float with double reductions, first load increment of the
-    uniaxial path, rho0 = 10 adaptive in [1, 50]."""
+    uniaxial path, rho0 = 10 adaptive in [1, 50]; full: with the
+    non-ideality, Frank and dissipation terms of LCE_FULL (dt = 1)."""
     import torch
     from paper_2010_06697_amd import admm, microstructure as M
 
@@ -198,8 +205,10 @@ def run_lce(steps, warmup):
     V = case["phase"].size
     p = admm.default_params("fp32", rho0=case["rho0"], rho_min=1.0, rho_max=50.0, adapt_rho=1,
                             mu_ref=case["mu_ref"])
-    s = admm.Solver([case["phase"]], case["materials"], [case["loads"][0]], p,
-                    precision="fp32", directors=[case["director0"]])
+    mats = [M.lce(1.0, 2.0, 100.0, **LCE_FULL)] if full else case["materials"]
+    s = admm.Solver([case["phase"]], mats, [case["loads"][0]], p,
+                    precision="fp32", directors=[case["director0"]],
+                    directors0=[case["director0"]] if full else None)
     s.step(warmup)
     s.autotune(reps=3)
     torch.cuda.synchronize()
@@ -215,7 +224,8 @@ def run_lce(steps, warmup):
     del s
     torch.cuda.empty_cache()
     out = {"workload": "lce256: 256^3 LCE polydomain, 1000 grains, a=2 mu=1 kappa=100, "
-                       "Fbar = diag(1.01, 1.01^-1/2, 1.01^-1/2), float with double reductions",
+                       "Fbar = diag(1.01, 1.01^-1/2, 1.01^-1/2), float with double reductions"
+                       + (f", full model {LCE_FULL}" if full else ""),
            "value": V * steps / dt, "unit": "voxel-iterations/s", "ms_per_step": 1e3 * dt / steps,
            "newton_iters_per_voxel_iteration": newton_its / float(V * (warmup + steps)),
            "newton_fail": int(nfail), "r_p": float(rp[0]), "r_d": float(rd[0]),
@@ -432,6 +442,7 @@ def main():
     f64 = None if args.no_fp64 else run_single(case, "fp64", args.steps, args.warmup)
     batch = None if args.no_batch else run_batch(128)
     lce = None if args.no_lce else run_lce(10, 3)
+    lce_full = None if args.no_lce else run_lce(10, 3, full=True)
     wavy = None if args.no_wavy else run_wavy()
     inexact = None if args.no_inexact else run_inexact(case)
 
@@ -499,6 +510,7 @@ def main():
         "autotune": f32["autotune"],
         "rve_batch": batch,
         "lce256": lce,
+        "lce256_full": lce_full,
         "inexact_local_step": inexact,
         "wavy64": wavy,
         "roofline": roof,
