@@ -430,3 +430,22 @@ def test_inexact_lce_reaches_the_exact_fixed_point():
     assert np.max(np.abs(np.einsum("i...,j...->ij...", out[1][1], out[1][1])
                          - np.einsum("i...,j...->ij...", out[0][1], out[0][1]))) <= 1e-7
     assert np.max(np.abs(out[1][2] - out[0][2])) <= 1e-8
+
+
+def test_composed_parity_case_is_far_from_ties():
+    """The inexact step's pass decisions in the composed GPU parity case
+    (LCE full model, uniaxial stress) do not move when the ratio moves by
+    1e-9 relative."""
+    from parity_util import NEWTON64, omats
+    from test_gpu_compose import CELLS, LOC, MATS
+    (phase, d0), Fb, free = CELLS[0]
+    out = []
+    for f in (1.0, 1 + 1e-9, 1 - 1e-9):
+        u, F, L = O.initial_state(phase.shape)
+        n = d0.copy()
+        op = O.params(max_iter=10, fixed_iters=True, mu_ref=1.0, dt=0.5, free=free,
+                      newton=O.newton_opts(**NEWTON64), **dict(LOC, local_ratio=LOC["local_ratio"] * f))
+        O.admm_run(phase, omats(MATS), Fb.ravel(), op, u, F, L, 10.0, director_field=n,
+                   director0=d0)
+        out.append(F)
+    assert np.array_equal(out[1], out[0]) and np.array_equal(out[2], out[0])
