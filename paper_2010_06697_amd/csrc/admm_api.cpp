@@ -58,6 +58,7 @@ Plan1D make_plan(int n) {
   }
   p.nst = (int)r.size();
   for (int k = 0; k < p.nst; ++k) p.rad[k] = r[k];
+  plan_divisors(p);
   return p;
 }
 
@@ -382,6 +383,7 @@ int set_plan(admm_ctx *c, const Plan1D &p) {
         const int tw = x->tw;
         *x = p;
         x->tw = tw;
+        plan_divisors(*x);
       }
   }
   HIP_TRY(hipMemcpyAsync(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * c->n_rve,
@@ -401,6 +403,7 @@ int set_xpoints(admm_ctx *c, int points) {
   for (int r = 0; r < n; ++r) {
     RveDesc &D = c->desc_h[r];
     D.rows_f = rows_per_fft_block(D.n1, points);
+    D.f_rows_f = make_fastdiv((unsigned)D.rows_f);
     bf[r + 1] = bf[r] + (D.n2 * D.n3 + D.rows_f - 1) / D.rows_f;
     lds = std::max(lds, 2 * ((3 * D.rows_f + 1) / 2) * D.n1);
   }
@@ -807,6 +810,10 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.S = (long long)D.n3 * D.n2 * D.m1;
     D.rows = rows_per_block(D.n1);
     D.rows_f = rows_per_fft_block(D.n1, default_fft_points(fp64));
+    D.f_n1 = make_fastdiv((unsigned)D.n1);
+    D.f_n2 = make_fastdiv((unsigned)D.n2);
+    D.f_m1 = make_fastdiv((unsigned)D.m1);
+    D.f_rows_f = make_fastdiv((unsigned)D.rows_f);
     D.p1 = make_plan(D.n1);
     D.p2 = make_plan(D.n2);
     D.p3 = make_plan(D.n3);

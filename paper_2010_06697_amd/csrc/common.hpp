@@ -11,14 +11,44 @@ constexpr int kThreads = 256;   // threads per workgroup of every kernel
 constexpr int kMaxStages = 8;   // radix stages of one 1D transform
 constexpr int kMaxN = 256;      // largest supported edge
 
+// n / d by one high multiply, for 0 <= n < 2^32 / d: m = ceil(2^32 / d), and
+// m = 0 for d = 1 (the quotient is n). The transforms' index arithmetic
+// divides by lengths known only at run time, where the general division
+// costs about twenty instructions per use.
+struct FastDiv {
+  unsigned d, m;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  FastDiv f;
+  f.d = d;
+  f.m = d <= 1 ? 0u : (unsigned)(((1ull << 32) + d - 1) / d);
+  return f;
+}
+__device__ __forceinline__ int fdiv(int n, FastDiv f) {
+  return f.m ? (int)__umulhi((unsigned)n, f.m) : n;
+}
+
 // radix plan of one 1D transform of length n; tw: offset of its twiddle table
-// exp(-2 pi i t / n), t = 0..n-1, in the twiddle pool
+// exp(-2 pi i t / n), t = 0..n-1, in the twiddle pool. nb[s], ns[s]: the
+// butterflies per line (n / rad[s]) and the span before stage s (the product
+// of the earlier radices), as divisors.
 struct Plan1D {
   int n;
   int nst;
   int rad[kMaxStages];
   int tw;
+  FastDiv nb[kMaxStages];
+  FastDiv ns[kMaxStages];
 };
+
+inline void plan_divisors(Plan1D &p) {
+  unsigned span = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    p.nb[s] = make_fastdiv((unsigned)(p.n / p.rad[s]));
+    p.ns[s] = make_fastdiv(span);
+    span *= (unsigned)p.rad[s];
+  }
+}
 
 // one periodic cell, as the kernels see it
 struct RveDesc {
@@ -27,6 +57,7 @@ struct RveDesc {
   long long S;              // complex entries of one spectral component
   int rows;                 // x1-lines per workgroup of the per-voxel kernels
   int rows_f;               // x1-lines per workgroup of the x1 transforms
+  FastDiv f_n1, f_n2, f_m1, f_rows_f;  // the same as divisors
   Plan1D p1, p2, p3;
   const uint8_t *phase;
   void *u[2];               // displacement fluctuation, ping-pong

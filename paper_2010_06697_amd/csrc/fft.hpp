@@ -92,8 +92,9 @@ template <int R, bool INV, typename C> __device__ __forceinline__ void dftR(C *v
 // [k][line] layouts) instead of consecutive butterflies of one line.
 template <int R, bool INV, typename C>
 __device__ __forceinline__ void fft_stage(const C *__restrict__ src, C *__restrict__ dst, int N,
-                                          int Ns, int nlines, int ls, int es, bool lfast,
-                                          const C *__restrict__ tw, int tid, int nthr) {
+                                          int Ns, FastDiv fnb, FastDiv fns, int nlines, int ls,
+                                          int es, bool lfast, const C *__restrict__ tw, int tid,
+                                          int nthr) {
   const int nb = N / R;
   const int total = nb * nlines;
   const int twstep = N / (Ns * R);
@@ -103,12 +104,15 @@ __device__ __forceinline__ void fft_stage(const C *__restrict__ src, C *__restri
       l = w % nlines;
       j = w / nlines;
     } else {
-      j = w % nb;
-      l = w / nb;
+      l = fdiv(w, fnb);
+      j = w - l * nb;
     }
     const C *s = src + l * ls;
     C *d = dst + l * ls;
-    const int jm = j % Ns;
+    // the multiply-high division pays in the x1 transforms (lines along the
+    // workgroup, issue bound); in the column layouts it costs registers and
+    // occupancy instead
+    const int jm = lfast ? j % Ns : j - fdiv(j, fns) * Ns;
     C v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = s[(j + r * nb) * es];
@@ -136,10 +140,18 @@ __device__ C *fft_lines(C *a, C *b, const Plan1D &p, const C *__restrict__ twpoo
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.rad[s];
     switch (R) {
-      case 2: fft_stage<2, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
-      case 3: fft_stage<3, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
-      case 4: fft_stage<4, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
-      default: fft_stage<8, INV>(a, b, p.n, Ns, nlines, ls, es, lfast, tw, tid, nthr); break;
+      case 2:
+        fft_stage<2, INV>(a, b, p.n, Ns, p.nb[s], p.ns[s], nlines, ls, es, lfast, tw, tid, nthr);
+        break;
+      case 3:
+        fft_stage<3, INV>(a, b, p.n, Ns, p.nb[s], p.ns[s], nlines, ls, es, lfast, tw, tid, nthr);
+        break;
+      case 4:
+        fft_stage<4, INV>(a, b, p.n, Ns, p.nb[s], p.ns[s], nlines, ls, es, lfast, tw, tid, nthr);
+        break;
+      default:
+        fft_stage<8, INV>(a, b, p.n, Ns, p.nb[s], p.ns[s], nlines, ls, es, lfast, tw, tid, nthr);
+        break;
     }
     __syncthreads();
     C *t = a;

@@ -528,16 +528,6 @@ __global__ __launch_bounds__(kThreads) void k_local_check(KernelArgs a, IterPara
 // b = D_h^T (F - Lambda/rho) and its forward FFT along x1
 // ----------------------------------------------------------------------------
 
-// Line rw of divergence workgroup b: its R lines are consecutive along x3
-// at one x2 (so the +-x3 neighbours of the divergence are mostly the
-// workgroup's own lines) when R divides n3, else consecutive rows.
-__device__ __forceinline__ int div_row(int b, int rw, int R, int n2, int n3) {
-  if (n3 % R == 0) {
-    const int zc = b / n2, x2 = b - zc * n2;
-    return (zc * R + rw) * n2 + x2;
-  }
-  return b * R + rw;
-}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
@@ -558,15 +548,21 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   C *za = reinterpret_cast<C *>(smem);
   C *zb = za + ncl * n1;
   const int t = threadIdx.x, nthr = blockDim.x;
+  // line rw of this workgroup: its R lines are consecutive along x3 at one x2
+  // (so the +-x3 neighbours of the divergence are mostly the workgroup's own
+  // lines) when R divides n3, else consecutive rows
+  const bool colmode = n3 % R == 0;
+  const int zc = b / n2, x2b = b - zc * n2;
+  auto row_of = [&](int rw) { return colmode ? (zc * R + rw) * n2 + x2b : b * R + rw; };
 
   for (int w = t; w < ncl * n1; w += nthr) za[w] = C{(T)0, (T)0};
   __syncthreads();
   const double irho = 1.0 / st->rho;
   for (int v = t; v < R * n1; v += nthr) {
-    const int row = v / n1, x1 = v - row * n1;
+    const int row = fdiv(v, D.f_n1), x1 = v - row * n1;
     if (row0 + row >= nrows) continue;
-    const int grow = div_row(b, row, R, n2, n3);
-    const int x2 = grow % n2, x3 = grow / n2;
+    const int grow = row_of(row);
+    const int x3 = fdiv(grow, D.f_n2), x2 = grow - x3 * n2;
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     const T *Eg = static_cast<const T *>(D.E);
     const T *Lg = static_cast<const T *>(D.Lam);
@@ -591,21 +587,19 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   C *res = fft_lines<false>(za, zb, D.p1, tw, ncl, n1, 1, false, t, nthr);
   C *spec = static_cast<C *>(D.spec);
   for (int w = t; w < ncl * m1; w += nthr) {
-    const int p = w / m1, m = w - p * m1;
+    const int p = fdiv(w, D.f_m1), m = w - p * m1;
     const C Zm = res[p * n1 + m];
     const C Zn = res[p * n1 + (m == 0 ? 0 : n1 - m)];
     const C Av = C{(T)0.5 * (Zm.x + Zn.x), (T)0.5 * (Zm.y - Zn.y)};
     const C Bv = C{(T)0.5 * (Zm.y + Zn.y), (T)(-0.5) * (Zm.x - Zn.x)};
     const int la = 2 * p, lb = 2 * p + 1;
     {
-      const int c = la / R, rw = la - c * R;
-      if (row0 + rw < nrows)
-        spec[c * S + (long long)div_row(b, rw, R, n2, n3) * m1 + m] = Av;
+      const int c = fdiv(la, D.f_rows_f), rw = la - c * R;
+      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1 + m] = Av;
     }
     if (lb < 3 * R) {
-      const int c = lb / R, rw = lb - c * R;
-      if (row0 + rw < nrows)
-        spec[c * S + (long long)div_row(b, rw, R, n2, n3) * m1 + m] = Bv;
+      const int c = fdiv(lb, D.f_rows_f), rw = lb - c * R;
+      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1 + m] = Bv;
     }
   }
 }
@@ -771,16 +765,16 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   // Z[k] = A[k] + i B[k] over the full length from the half spectra of the
   // two real lines (A, B Hermitian; DC and Nyquist taken as real)
   for (int w = t; w < ncl * n1; w += nthr) {
-    const int p = w / n1, k = w - p * n1;
+    const int p = fdiv(w, D.f_n1), k = w - p * n1;
     const int kk = k <= h ? k : n1 - k;
     C Av = C{(T)0, (T)0}, Bv = C{(T)0, (T)0};
     const int la = 2 * p, lb = 2 * p + 1;
     {
-      const int c = la / R, rw = la - c * R;
+      const int c = fdiv(la, D.f_rows_f), rw = la - c * R;
       if (row0 + rw < nrows) Av = spec[c * S + (long long)(row0 + rw) * m1 + kk];
     }
     if (lb < 3 * R) {
-      const int c = lb / R, rw = lb - c * R;
+      const int c = fdiv(lb, D.f_rows_f), rw = lb - c * R;
       if (row0 + rw < nrows) Bv = spec[c * S + (long long)(row0 + rw) * m1 + kk];
     }
     if (kk == 0 || kk == h) {
@@ -798,8 +792,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   C *res = fft_lines<true>(za, zb, D.p1, tw, ncl, n1, 1, false, t, nthr);
   T *un = static_cast<T *>(D.u[1 - st->cur]);
   for (int w = t; w < 3 * R * n1; w += nthr) {
-    const int ell = w / n1, x1 = w - ell * n1;
-    const int c = ell / R, rw = ell - c * R;
+    const int ell = fdiv(w, D.f_n1), x1 = w - ell * n1;
+    const int c = fdiv(ell, D.f_rows_f), rw = ell - c * R;
     const int grow = row0 + rw;
     if (grow < nrows) {
       const C v = res[(ell >> 1) * n1 + x1];
