@@ -274,7 +274,8 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         NeoHooke<T> M;
         M.mu = (T)m.mu;
         M.lam = (T)m.lam;
-        rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol, &lsum[0]);
+        rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol,
+                           MODE == kLocalExact ? nullptr : &lsum[0]);
         n_its = rc >= 0 ? rc : cap;
       }
       lsum[1] = rc >= 0 ? 1.0 : 0.0;

@@ -277,9 +277,16 @@ __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 
 constexpr __host__ __device__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// det(I + E) > 0, decided exactly as the point evaluations decide it
+template <typename TG> __device__ __forceinline__ bool admissible(const TG *E) {
+  TG cE[9];
+  double jm1, tr, q;
+  return kinematics(E, cE, jm1, tr, q);
+}
+
 // The iterations of newton() from the point s at E; on exit s is the point
-// of the returned iterate.
-template <typename TG, typename TH, typename M>
+// of the returned iterate when KEEP is set (otherwise it may be stale).
+template <typename TG, typename TH, bool KEEP, typename M>
 __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
                            double step_tol, Point<TG> &s) {
   const double smod = m.smod() + (double)rho;
@@ -358,6 +365,19 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
     // taken as it is; the float gradient is at its rounding floor there and
     // no longer decides a line search
     const bool tiny = sizeof(TG) == 4 && pd && nd2 <= tol_step2 * fmax(1.0, nF2);
+    if (!KEEP && tiny) {
+      // the full step ends the solve when det F > 0 there and it is also
+      // below the tolerance at the new iterate: the point evaluation at
+      // E + d (stress and gradient) has no use then
+      TG En[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) En[k] = E[k] + d[k];
+      if (admissible(En) && nd2 <= tol_step2 * fmax(1.0, (double)norm2_ipx(En))) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) E[k] = En[k];
+        return it + 1;
+      }
+    }
     const double phi0 = small ? 0.0 : m.phi(E, A, rho, s);
     double t = 1.0;
     bool acc = false;
@@ -408,8 +428,9 @@ __device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double 
                       double step_tol, double *g2 = nullptr) {
   Point<TG> s;
   if (!m.point(E, A, rho, s)) return -2;
-  int ret = newton_loop<TG, TH>(E, A, m, rho, maxit, gtol, step_tol, s);
-  if (g2) *g2 = (double)s.gn2;
+  if (!g2) return newton_loop<TG, TH, false>(E, A, m, rho, maxit, gtol, step_tol, s);
+  int ret = newton_loop<TG, TH, true>(E, A, m, rho, maxit, gtol, step_tol, s);
+  *g2 = (double)s.gn2;
   return ret;
 }
 
