@@ -92,8 +92,12 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // three half-spectrum components (the divergence of F - Lambda/rho, then the
 // displacement fluctuation) per cell
+// row stride of the half spectra: m1 = n1/2 + 1 entries rounded up to 32
+// bytes (the columns past m1 are zero)
+int spec_stride(int n1, bool fp64) { return (int)align_up((size_t)(n1 / 2 + 1), fp64 ? 2 : 4); }
+
 size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
-  const size_t S = (size_t)n3 * n2 * (n1 / 2 + 1);
+  const size_t S = (size_t)n3 * n2 * spec_stride(n1, fp64);
   return align_up(3 * S * (fp64 ? 16 : 8), 256);
 }
 
@@ -361,7 +365,7 @@ int set_tiles(admm_ctx *c, int ty, int tz) {
   for (int r = 0; r < n; ++r) {
     const RveDesc &D = c->desc_h[r];
     by[r + 1] = by[r] + D.n3 * ((D.m1 + ty - 1) / ty);
-    bz[r + 1] = bz[r] + (D.n2 * D.m1 + tz - 1) / tz;
+    bz[r + 1] = bz[r] + (D.n2 * D.m1s + tz - 1) / tz;
   }
   c->L.tile_y = ty;
   c->L.tile_z = tz;
@@ -806,8 +810,9 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.n2 = R.n[1];
     D.n3 = R.n[2];
     D.m1 = D.n1 / 2 + 1;
+    D.m1s = spec_stride(D.n1, fp64);
     D.V = (long long)D.n1 * D.n2 * D.n3;
-    D.S = (long long)D.n3 * D.n2 * D.m1;
+    D.S = (long long)D.n3 * D.n2 * D.m1s;
     D.rows = rows_per_block(D.n1);
     D.rows_f = rows_per_fft_block(D.n1, default_fft_points(fp64));
     D.f_n1 = make_fastdiv((unsigned)D.n1);
@@ -834,13 +839,16 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     bf[r + 1] = bf[r] + (nrows + D.rows_f - 1) / D.rows_f;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
-    bz[r + 1] = bz[r] + (D.n2 * D.m1 + B - 1) / B;
+    bz[r + 1] = bz[r] + (D.n2 * D.m1s + B - 1) / B;
     bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) *
                             ((D.n3 + kVoxelsPerThread - 1) / kVoxelsPerThread);
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
     lds_x = std::max(lds_x, 2 * ((3 * D.rows_f + 1) / 2) * D.n1);
   }
+  // the spectra's padding columns stay zero: no kernel writes them but the
+  // x3 pass, which maps zero to zero there
+  INIT_TRY(hipMemset(c->workspace, 0, spec_off));
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
   c->L.any_lce = any_lce;

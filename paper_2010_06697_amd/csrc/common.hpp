@@ -57,6 +57,8 @@ struct RveDesc {
   long long S;              // complex entries of one spectral component
   int rows;                 // x1-lines per workgroup of the per-voxel kernels
   int rows_f;               // x1-lines per workgroup of the x1 transforms
+  int m1s;                  // row stride of the half spectra (m1 rounded up to 32
+                            // bytes, so that every column tile starts on a sector)
   FastDiv f_n1, f_n2, f_m1, f_rows_f;  // the same as divisors
   Plan1D p1, p2, p3;
   const uint8_t *phase;

@@ -540,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   const RveState *st = a.state + r;
   if (!st->active) return;
   const int b = blk - a.blk_f[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f, m1 = D.m1;
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f, m1 = D.m1, m1s = D.m1s;
   const int nrows = n2 * n3;
   const int row0 = b * R;
   const int ncl = (3 * R + 1) / 2;
@@ -596,11 +596,11 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
     const int la = 2 * p, lb = 2 * p + 1;
     {
       const int c = fdiv(la, D.f_rows_f), rw = la - c * R;
-      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1 + m] = Av;
+      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1s + m] = Av;
     }
     if (lb < 3 * R) {
       const int c = fdiv(lb, D.f_rows_f), rw = lb - c * R;
-      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1 + m] = Bv;
+      if (row0 + rw < nrows) spec[c * S + (long long)row_of(rw) * m1s + m] = Bv;
     }
   }
 }
@@ -619,10 +619,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
   const RveDesc &D = a.desc[r];
   if (!a.state[r].active) return;
   const int b = blk - a.blk_y[r];
-  const int n2 = D.n2, m1 = D.m1;
+  const int n2 = D.n2, m1 = D.m1, m1s = D.m1s;
   const int nty = (m1 + B - 1) / B;
   const int x3 = b / nty, m0 = (b - x3 * nty) * B;
-  C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + (long long)x3 * n2 * m1;
+  C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + (long long)x3 * n2 * m1s;
   C *za = reinterpret_cast<C *>(smem);
   C *zb = za + n2 * B;
   const int t = threadIdx.x, nthr = blockDim.x;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
   for (int k = 0; k < PMAX; ++k) {
     const int w = t + k * nthr;
     const int x2 = w / B, bb = w - x2 * B;
-    v[k] = (w < npts && m0 + bb < m1) ? base[x2 * m1 + m0 + bb] : C{(T)0, (T)0};
+    v[k] = (w < npts && m0 + bb < m1) ? base[x2 * m1s + m0 + bb] : C{(T)0, (T)0};
   }
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) {
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(KernelArgs a) {
   for (int k = 0; k < PMAX; ++k) {
     const int w = t + k * nthr;
     const int x2 = w / B, bb = w - x2 * B;
-    if (w < npts && m0 + bb < m1) base[x2 * m1 + m0 + bb] = v[k];
+    if (w < npts && m0 + bb < m1) base[x2 * m1s + m0 + bb] = v[k];
   }
 }
 
@@ -671,8 +671,8 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
   const RveDesc &D = a.desc[r];
   if (!a.state[r].active) return;
   const int b = blk - a.blk_z[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, m1 = D.m1;
-  const int plane = n2 * m1;  // stride between x3 planes
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, m1 = D.m1, m1s = D.m1s;
+  const int plane = n2 * m1s;  // stride between x3 planes (padding columns included)
   const int q0 = b * B;
   const int npts = n3 * B;
   C *base = static_cast<C *>(D.spec) + blockIdx.y * D.S + q0;
@@ -703,12 +703,13 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
       const int m3 = w / B, bb = w - m3 * B;
       int q = q0 + bb;
       if (q >= plane) q = 0;
-      const int m2 = q / m1, mm1 = q - m2 * m1;
-      const double K1 = (double)tw[D.p1.tw + mm1].y;
+      const int m2 = q / m1s, mm1 = q - m2 * m1s;
+      const bool pad = mm1 >= m1;  // padding column: stays zero
+      const double K1 = (double)tw[D.p1.tw + (pad ? 0 : mm1)].y;
       const double K2 = (double)tw[D.p2.tw + m2].y;
       const double K3 = (double)tw[D.p3.tw + m3].y;
-      const bool null = (mm1 == 0 || 2 * mm1 == n1) && (m2 == 0 || 2 * m2 == n2) &&
-                        (m3 == 0 || 2 * m3 == n3);
+      const bool null = pad || ((mm1 == 0 || 2 * mm1 == n1) && (m2 == 0 || 2 * m2 == n2) &&
+                                (m3 == 0 || 2 * m3 == n3));
       const T s = null ? (T)0 : (T)(iV / (K1 * K1 + K2 * K2 + K3 * K3));
       const C h = res[w];
       v[k] = C{h.x * s, h.y * s};
@@ -751,7 +752,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   const RveState *st = a.state + r;
   if (!st->active) return;
   const int b = blk - a.blk_f[r];
-  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f, m1 = D.m1;
+  const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows_f;
   const int nrows = n2 * n3;
   const int row0 = b * R;
   const int ncl = (3 * R + 1) / 2;
@@ -772,11 +773,11 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
     const int la = 2 * p, lb = 2 * p + 1;
     {
       const int c = fdiv(la, D.f_rows_f), rw = la - c * R;
-      if (row0 + rw < nrows) Av = spec[c * S + (long long)(row0 + rw) * m1 + kk];
+      if (row0 + rw < nrows) Av = spec[c * S + (long long)(row0 + rw) * D.m1s + kk];
     }
     if (lb < 3 * R) {
       const int c = fdiv(lb, D.f_rows_f), rw = lb - c * R;
-      if (row0 + rw < nrows) Bv = spec[c * S + (long long)(row0 + rw) * m1 + kk];
+      if (row0 + rw < nrows) Bv = spec[c * S + (long long)(row0 + rw) * D.m1s + kk];
     }
     if (kk == 0 || kk == h) {
       Av.y = (T)0;
