@@ -420,8 +420,8 @@ def main():
                          "(reference kernel for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}): this build runs the "
-              "single-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs "
+              "each cell on a single GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch
