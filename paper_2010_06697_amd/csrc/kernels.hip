@@ -880,7 +880,23 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
   if (!st->active) return;
   const int p0 = a.blk_u[r], nb = a.blk_u[r + 1] - p0;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+  // eight loads in flight per thread, added in the order of k as one at a
+  // time would (the sums keep their bits)
+  const int step = blockDim.x;
+  int k = threadIdx.x;
+  for (; k + 7 * step < nb; k += 8 * step) {
+    double4 q[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = a.partials[p0 + k + j * step];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      v[0] += q[j].x;
+      v[1] += q[j].y;
+      v[2] += q[j].z;
+      v[3] += q[j].w;
+    }
+  }
+  for (; k < nb; k += step) {
     const double4 q = a.partials[p0 + k];
     v[0] += q.x;
     v[1] += q.y;
