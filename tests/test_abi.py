@@ -72,6 +72,18 @@ def test_workspace_bytes():
     assert admm.admm_workspace_bytes([_rve((10, 8, 8))], admm.FP64) == 0
 
 
+@pytest.mark.parametrize("n", [(16, 12, 8), (6, 8, 12), (256, 4, 4), (18, 6, 4)])
+def test_workspace_holds_padded_half_spectra(n):
+    # three half-spectrum components whose rows of n1/2 + 1 entries are
+    # padded to 32 bytes (2 complex128 or 4 complex64), 256-byte aligned
+    n1, n2, n3 = n
+    m1 = n1 // 2 + 1
+    for prec, csz, q in ((admm.FP64, 16, 2), (admm.FP32_FP64RED, 8, 4)):
+        m1s = -(-m1 // q) * q
+        want = -(-(3 * n3 * n2 * m1s * csz) // 256) * 256
+        assert admm.admm_workspace_bytes([_rve(n)], prec) == want
+
+
 def _init(rves, mats, params, precision=admm.FP64):
     ctx = ctypes.c_void_p()
     ra = (admm.Rve * len(rves))(*rves)
