@@ -166,9 +166,10 @@ typedef struct admm_ctx admm_ctx;
 int admm_check_grid(int32_t n1, int32_t n2, int32_t n3);
 
 /* Device workspace the library needs for these cells and precision (bytes):
- * the half-spectrum buffers of Step 2, three components of
- * n3 * n2 * (n1/2 + 1) complex values per cell. Host only. Returns 0 on
- * invalid input. */
+ * the half-spectrum buffers of Step 2, three components of n3 * n2 rows per
+ * cell, each row n1/2 + 1 complex values padded to 32 bytes (2 complex128 or
+ * 4 complex64), 256-byte aligned per cell. The context owns the buffer for
+ * its lifetime. Host only. Returns 0 on invalid input. */
 size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precision);
 
 /* Creates a context for n_rve cells sharing one material table.
