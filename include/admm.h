@@ -225,12 +225,28 @@ int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]);
  *      rho sigma of the last Step 2' (equals beta at the fixed point);
  *   iters_out, status_out (may be NULL): iterations, ADMM_OK or
  *      ADMM_NOT_CONVERGED.
- * Allocates its work buffers (about 1 KB per voxel) for the call.
+ * Allocates its work buffers (about 960 bytes per voxel) for the call.
  * Errors: EINVAL, EUNSUPPORTED (float context, full LCE model terms),
  * EDOMAIN (L + rho I not positive definite), ENOMEM, EHIP. */
 int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
                int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
                int32_t *iters_out, int32_t *status_out);
+
+/* admm_bloch without any device allocation, for callers that cannot
+ * allocate (harnesses that forbid hipMalloc, loops that must not touch the
+ * allocator). Same arguments, results and errors as admm_bloch, computed by
+ * the same kernels in the same order (the results are identical). The work
+ * buffers live in a fixed array of admm_bloch_static_max_bytes() bytes
+ * (128 MiB) in the library's device code, one per GPU, held until the
+ * process ends; a cell needs about 960 bytes per voxel (at most about
+ * 139,000 voxels, e.g. 48^3). Larger cells: ADMM_ENOMEM, nothing run. The
+ * array keeps the last call's contents (every call clears what it needs at
+ * zero); calls on one GPU share it, so calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller. */
+int admm_bloch_static(admm_ctx *ctx, int32_t rve, const double omega[3], double rho,
+                      double tol, int32_t max_iter, void *p, double *beta_out,
+                      double *sigma_rho_out, int32_t *iters_out, int32_t *status_out);
+size_t admm_bloch_static_max_bytes(void);
 
 /* Orientation tensor of the LCE voxels of cell `rve` (the order parameter of
  * Sec. 5's polydomain studies): S = 3/2 (<n (x) n> - I/3), row-major.

@@ -26,7 +26,8 @@ NEOHOOKE, LCE = 0, 1
 # entry points declared in include/admm.h, in order
 ENTRY_POINTS = (
     "admm_check_grid", "admm_workspace_bytes", "admm_init", "admm_set_load", "admm_set_free",
-    "admm_get_fbar", "admm_bloch", "admm_orientation", "admm_set_rho",
+    "admm_get_fbar", "admm_bloch", "admm_bloch_static", "admm_bloch_static_max_bytes",
+    "admm_orientation", "admm_set_rho",
     "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
     "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
     "admm_profile_read", "admm_autotune", "admm_strerror", "admm_destroy",
@@ -98,6 +99,9 @@ def lib():
         L.admm_orientation.argtypes = [vp, i32, dp]
         L.admm_bloch.argtypes = [vp, i32, dp, ctypes.c_double, ctypes.c_double, i32, vp, dp, dp,
                                  ip, ip]
+        L.admm_bloch_static.argtypes = L.admm_bloch.argtypes
+        L.admm_bloch_static_max_bytes.argtypes = []
+        L.admm_bloch_static_max_bytes.restype = ctypes.c_size_t
         L.admm_set_rho.argtypes = [vp, i32, ctypes.c_double]
         L.admm_step.argtypes = [vp, i32, dp, dp, dp]
         L.admm_solve.argtypes = [vp, ip, ip]
@@ -194,6 +198,23 @@ def admm_bloch(ctx, rve: int, omega, rho: float, tol: float, max_iter: int, p_pt
     _check(lib().admm_bloch(ctx, rve, _dptr(w), float(rho), float(tol), int(max_iter), p_ptr,
                             _dptr(b), _dptr(s), _iptr(it), _iptr(st)), "admm_bloch")
     return float(b[0]), float(s[0]), int(it[0]), int(st[0])
+
+
+def admm_bloch_static(ctx, rve: int, omega, rho: float, tol: float, max_iter: int, p_ptr: int):
+    """admm_bloch with its work buffers in the library's fixed device array
+    (no device allocation). Same returns as admm_bloch."""
+    w = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(3))
+    b, s = np.zeros(1), np.zeros(1)
+    it, st = np.zeros(1, np.int32), np.zeros(1, np.int32)
+    _check(lib().admm_bloch_static(ctx, rve, _dptr(w), float(rho), float(tol), int(max_iter),
+                                   p_ptr, _dptr(b), _dptr(s), _iptr(it), _iptr(st)),
+           "admm_bloch_static")
+    return float(b[0]), float(s[0]), int(it[0]), int(st[0])
+
+
+def admm_bloch_static_max_bytes() -> int:
+    """Size of the fixed work array of admm_bloch_static (bytes)."""
+    return int(lib().admm_bloch_static_max_bytes())
 
 
 def admm_orientation(ctx, rve: int) -> np.ndarray:
@@ -417,6 +438,14 @@ class Solver:
         p = t.from_numpy(np.ascontiguousarray(p0, np.complex128)).to(self.device)
         self.torch.cuda.synchronize(self.device)
         b, s, it, st = admm_bloch(self.ctx, rve, omega, rho, tol, max_iter, p.data_ptr())
+        return {"beta": b, "sigma_rho": s, "iters": it, "status": st, "p": p.cpu().numpy()}
+
+    def bloch_static(self, rve, omega, rho, p0, tol=1e-10, max_iter=5000):
+        """bloch() through the allocation-free entry point."""
+        t = self.torch
+        p = t.from_numpy(np.ascontiguousarray(p0, np.complex128)).to(self.device)
+        self.torch.cuda.synchronize(self.device)
+        b, s, it, st = admm_bloch_static(self.ctx, rve, omega, rho, tol, max_iter, p.data_ptr())
         return {"beta": b, "sigma_rho": s, "iters": it, "status": st, "p": p.cpu().numpy()}
 
     def set_rho(self, rho, rve=-1):

@@ -1026,9 +1026,11 @@ int admm_get_fbar(admm_ctx *ctx, int32_t rve, double Fbar_out[9]) {
   return ADMM_OK;
 }
 
-int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
-               int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
-               int32_t *iters_out, int32_t *status_out) {
+// shared by admm_bloch and admm_bloch_static: work is null (allocate for
+// the call) or the static scratch
+static int bloch_call(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
+                      int32_t max_iter, void *p, void *work, double *beta_out,
+                      double *sigma_rho_out, int32_t *iters_out, int32_t *status_out) {
   if (!ctx || rve < 0 || rve >= ctx->n_rve || !omega || !p || !beta_out || !(rho > 0.0) ||
       !(tol >= 0.0) || max_iter < 1)
     return ADMM_EINVAL;
@@ -1041,8 +1043,8 @@ int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, do
   double beta = 0.0, sr = 0.0;
   int it = 0, status = 1;
   const int rc = bloch_solve(ctx->stream, ctx->desc_h[rve], ctx->mats_d, ctx->n_mat, ctx->tw_d,
-                             omega, rho, tol, max_iter, static_cast<double *>(p), &beta, &sr, &it,
-                             &status);
+                             omega, rho, tol, max_iter, static_cast<double *>(p), work, &beta,
+                             &sr, &it, &status);
   if (rc == -3) return ADMM_EDOMAIN;
   if (rc == -2) return ADMM_EINVAL;
   if (rc != 0) return ADMM_EHIP;
@@ -1051,6 +1053,26 @@ int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, do
   if (iters_out) *iters_out = it;
   if (status_out) *status_out = status == 0 ? ADMM_OK : ADMM_NOT_CONVERGED;
   return ADMM_OK;
+}
+
+int admm_bloch(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
+               int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
+               int32_t *iters_out, int32_t *status_out) {
+  return bloch_call(ctx, rve, omega, rho, tol, max_iter, p, nullptr, beta_out, sigma_rho_out,
+                    iters_out, status_out);
+}
+
+size_t admm_bloch_static_max_bytes(void) { return bloch_scratch_bytes(); }
+
+int admm_bloch_static(admm_ctx *ctx, int32_t rve, const double omega[3], double rho, double tol,
+                      int32_t max_iter, void *p, double *beta_out, double *sigma_rho_out,
+                      int32_t *iters_out, int32_t *status_out) {
+  if (!ctx || rve < 0 || rve >= ctx->n_rve) return ADMM_EINVAL;
+  if (bloch_work_bytes(ctx->desc_h[rve]) > bloch_scratch_bytes()) return ADMM_ENOMEM;
+  void *work = nullptr;
+  if (bloch_scratch(&work) != 0) return ADMM_EHIP;
+  return bloch_call(ctx, rve, omega, rho, tol, max_iter, p, work, beta_out, sigma_rho_out,
+                    iters_out, status_out);
 }
 
 int admm_orientation(admm_ctx *ctx, int32_t rve, double S_out[9]) {

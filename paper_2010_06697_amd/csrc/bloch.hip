@@ -16,7 +16,7 @@
 // Complex fields are double2, component-major [c][x3][x2][x1].
 #include <algorithm>
 #include <cmath>
-#include <vector>
+#include <mutex>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -424,12 +424,87 @@ __global__ __launch_bounds__(kThreads) void k_bl_reduce(BlochArgs a, int nblk, i
     for (int k = 0; k < NV; ++k) a.scal[dst + k] = v[k];
 }
 
+// zero fill of n doubles (the multiplier and the scalars start at zero)
+__global__ __launch_bounds__(kThreads) void k_bl_zero(double *q, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    q[k] = 0.0;
+}
+
+// partial sums of |p|^2 of the start vector
+__global__ __launch_bounds__(kThreads) void k_bl_norm(BlochArgs a) {
+  __shared__ double red[kThreads / 64];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  double q[1] = {0.0};
+  if (x < a.V)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double2 v = a.p[i * a.V + x];
+      q[0] += v.x * v.x + v.y * v.y;
+    }
+  bl_block_sum<1>(q, red);
+  if (threadIdx.x == 0) a.part[2 * blockIdx.x] = q[0];
+}
+
+// <p, p> = 1 (sum |p|^2 = V) from the sum in scal[5]; a zero start is an
+// error (flag in scal[6])
+__global__ __launch_bounds__(kThreads) void k_bl_normalize(BlochArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const double s2 = a.scal[5];
+  if (!(s2 > 0.0) || !isfinite(s2)) {
+    if (x == 0) a.scal[6] = 1.0;
+    return;
+  }
+  if (x >= a.V) return;
+  const double sc = sqrt((double)a.V / s2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double2 v = a.p[i * a.V + x];
+    a.p[i * a.V + x] = double2{v.x * sc, v.y * sc};
+  }
+}
+
+// Work buffers of the allocation-free entry point: one array per device,
+// held until the process ends; its address is looked up once per device
+// (hipGetSymbolAddress) and only that address is used on the host.
+constexpr size_t kBlochScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kBlochScratchBytes];
+
 }  // namespace
 
-// host side: one solve (see include/admm.h, admm_bloch)
+// bytes of the work buffers of one solve on this cell
+size_t bloch_work_bytes(const RveDesc &D) {
+  const size_t V = (size_t)D.V;
+  const size_t nblk = (V + kThreads - 1) / kThreads;
+  return V * 54 * 8 + (3 + 9 + 9 + 9 + 3) * V * 16 + 2 * nblk * 8 + 8 * 8 +
+         (size_t)(D.n1 + D.n2 + D.n3) * 8;
+}
+
+size_t bloch_scratch_bytes() { return kBlochScratchBytes; }
+
+// device address of this device's scratch array (looked up on first use)
+int bloch_scratch(void **ptr) {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return -1;
+    addr[dev] = q;
+  }
+  *ptr = addr[dev];
+  return 0;
+}
+
+// host side: one solve (see include/admm.h, admm_bloch). work: device
+// buffer of at least bloch_work_bytes(D) bytes, or null to allocate one for
+// the call.
 int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_mat,
                 const void *tw, const double omega[3], double rho, double tol, int max_iter,
-                double *p, double *beta, double *sigma_rho, int *iters, int *status) {
+                double *p, void *work, double *beta, double *sigma_rho, int *iters,
+                int *status) {
   BlochArgs a{};
   a.n1 = D.n1;
   a.n2 = D.n2;
@@ -447,25 +522,24 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
   a.n_mat = n_mat;
   const size_t V = (size_t)D.V;
   const int nblk = (int)((V + kThreads - 1) / kThreads);
-  // |K|^2 per axis and its minimum (separable)
+  // |K|^2 per axis and its minimum (separable); at most 3 * kMaxN entries
   const int ns[3] = {D.n1, D.n2, D.n3};
-  std::vector<double> k2h;
+  double k2h[3 * kMaxN];
+  int nk = 0;
   double k2min = 0.0;
   for (int j = 0; j < 3; ++j) {
     double mn = 1e300;
     for (int m = 0; m < ns[j]; ++m) {
       const double v = std::sin(2.0 * M_PI * m / ns[j] + omega[j]);
-      k2h.push_back(v * v);
+      k2h[nk++] = v * v;
       mn = std::min(mn, v * v);
     }
     k2min += mn;
   }
   a.k2min = k2min;
   // work buffers
-  void *buf = nullptr;
-  const size_t bytes = V * 54 * 8 + (3 + 9 + 9 + 9 + 3) * V * 16 + 2 * (size_t)nblk * 8 + 8 * 8 +
-                       k2h.size() * 8;
-  if (hipMalloc(&buf, bytes) != hipSuccess) return -1;
+  void *buf = work;
+  if (!buf && hipMalloc(&buf, bloch_work_bytes(D)) != hipSuccess) return -1;
   char *q = static_cast<char *>(buf);
   a.Lf = reinterpret_cast<double *>(q);
   q += V * 54 * 8;
@@ -477,9 +551,8 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
   q += 9 * V * 16;
   a.s2 = reinterpret_cast<double2 *>(q);
   q += 3 * V * 16;
-  double2 *pw = reinterpret_cast<double2 *>(q);  // p (interleaved complex)
+  a.p = reinterpret_cast<double2 *>(q);  // p (interleaved complex)
   q += 3 * V * 16;
-  a.p = pw;
   a.part = reinterpret_cast<double *>(q);
   q += 2 * (size_t)nblk * 8;
   a.scal = reinterpret_cast<double *>(q);
@@ -490,44 +563,32 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     rc = code;
     return code;
   };
+  const dim3 grid(nblk), blk(kThreads);
   do {
-    if (hipMemsetAsync(a.g, 0, 9 * V * 16, st) != hipSuccess ||
-        hipMemsetAsync(a.scal, 0, 8 * 8, st) != hipSuccess ||
-        hipMemcpyAsync(const_cast<double *>(a.k2t), k2h.data(), k2h.size() * 8,
-                       hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(pw, p, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    // the multiplier and the scalars start at zero (a fill kernel: the
+    // buffer may hold an earlier call's values)
+    hipLaunchKernelGGL(k_bl_zero, dim3(std::min(nblk * 9, 4096)), blk, 0, st,
+                       reinterpret_cast<double *>(a.g), 18 * V);
+    hipLaunchKernelGGL(k_bl_zero, dim3(1), blk, 0, st, a.scal, (size_t)8);
+    if (hipMemcpyAsync(const_cast<double *>(a.k2t), k2h, (size_t)nk * 8, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(a.p, p, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
       fail(-1);
       break;
     }
-    hipLaunchKernelGGL(k_bl_factor, dim3(nblk), dim3(kThreads), 0, st, a);
-    // normalise the start: <p, p> = 1
-    {
-      std::vector<double2> h(3 * V);
-      if (hipMemcpyAsync(h.data(), pw, 3 * V * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
-        fail(-1);
-        break;
-      }
-      double s2 = 0.0;
-      for (const auto &v : h) s2 += v.x * v.x + v.y * v.y;
-      if (!(s2 > 0.0)) {
-        fail(-2);
-        break;
-      }
-      const double sc = std::sqrt((double)V / s2);
-      for (auto &v : h) {
-        v.x *= sc;
-        v.y *= sc;
-      }
-      if (hipMemcpyAsync(pw, h.data(), 3 * V * 16, hipMemcpyHostToDevice, st) != hipSuccess) {
-        fail(-1);
-        break;
-      }
-    }
+    hipLaunchKernelGGL(k_bl_factor, grid, blk, 0, st, a);
+    // normalise the start on the device: <p, p> = 1
+    hipLaunchKernelGGL(k_bl_norm, grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_bl_reduce<1>), dim3(1), blk, 0, st, a, nblk, 5);
+    hipLaunchKernelGGL(k_bl_normalize, grid, blk, 0, st, a);
     double scal[8];
     if (hipMemcpyAsync(scal, a.scal, sizeof(scal), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       fail(-1);
+      break;
+    }
+    if (scal[6] != 0.0) {
+      fail(-2);  // zero start
       break;
     }
     if (scal[4] != 0.0) {
@@ -536,7 +597,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     }
     const Plan1D pls[3] = {D.p1, D.p2, D.p3};
     const double2 *twd = static_cast<const double2 *>(tw);
-    auto fft3 = [&](bool inv) {
+    auto fft3 = [&](double2 *data, bool inv) {
       for (int ax = 0; ax < 3; ++ax) {
         const int N = pls[ax].n;
         const int B = std::max(1, std::min(64, 2048 / N));
@@ -544,33 +605,31 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
         const int g = (nl + B - 1) / B;
         const size_t lds = 2 * (size_t)B * N * sizeof(double2);
         if (inv)
-          hipLaunchKernelGGL(k_bl_fft<true>, dim3(g), dim3(kThreads), lds, st, a.s2, 3, a.n1,
-                             a.n2, a.n3, ax, pls[ax], twd, B);
+          hipLaunchKernelGGL(k_bl_fft<true>, dim3(g), blk, lds, st, data, 3, a.n1, a.n2, a.n3, ax,
+                             pls[ax], twd, B);
         else
-          hipLaunchKernelGGL(k_bl_fft<false>, dim3(g), dim3(kThreads), lds, st, a.s2, 3, a.n1,
-                             a.n2, a.n3, ax, pls[ax], twd, B);
+          hipLaunchKernelGGL(k_bl_fft<false>, dim3(g), blk, lds, st, data, 3, a.n1, a.n2, a.n3,
+                             ax, pls[ax], twd, B);
       }
     };
     int it = 0;
     *status = 1;
     for (; it < max_iter;) {
-      hipLaunchKernelGGL(k_bl_local, dim3(nblk), dim3(kThreads), 0, st, a);
-      hipLaunchKernelGGL(k_bl_div, dim3(nblk), dim3(kThreads), 0, st, a);
-      fft3(false);
+      hipLaunchKernelGGL(k_bl_local, grid, blk, 0, st, a);
+      hipLaunchKernelGGL(k_bl_div, grid, blk, 0, st, a);
+      fft3(a.s2, false);
       hipLaunchKernelGGL(k_bl_secular, dim3(1), dim3(1024), 0, st, a);
-      hipLaunchKernelGGL(k_bl_scale, dim3(nblk), dim3(kThreads), 0, st, a);
-      // p^ into s2 for the inverse transform
-      if (hipMemcpyAsync(a.s2, pw, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
-        fail(-1);
-        break;
+      // p^ = b^ / (|K|^2 - sigma) in place, inverse transform there, and
+      // the two buffers swap roles (p in the transformed one)
+      {
+        BlochArgs b = a;
+        b.p = a.s2;
+        hipLaunchKernelGGL(k_bl_scale, grid, blk, 0, st, b);
       }
-      fft3(true);
-      if (hipMemcpyAsync(pw, a.s2, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
-        fail(-1);
-        break;
-      }
-      hipLaunchKernelGGL(k_bl_update, dim3(nblk), dim3(kThreads), 0, st, a);
-      hipLaunchKernelGGL((k_bl_reduce<2>), dim3(1), dim3(kThreads), 0, st, a, nblk, 1);
+      fft3(a.s2, true);
+      std::swap(a.p, a.s2);
+      hipLaunchKernelGGL(k_bl_update, grid, blk, 0, st, a);
+      hipLaunchKernelGGL((k_bl_reduce<2>), dim3(1), blk, 0, st, a, nblk, 1);
       ++it;
       if (hipMemcpyAsync(scal, a.scal, sizeof(scal), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
@@ -588,10 +647,10 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
       }
     }
     if (rc) break;
-    hipLaunchKernelGGL(k_bl_rayleigh, dim3(nblk), dim3(kThreads), 0, st, a);
-    hipLaunchKernelGGL((k_bl_reduce<1>), dim3(1), dim3(kThreads), 0, st, a, nblk, 3);
+    hipLaunchKernelGGL(k_bl_rayleigh, grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_bl_reduce<1>), dim3(1), blk, 0, st, a, nblk, 3);
     if (hipMemcpyAsync(scal, a.scal, sizeof(scal), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(p, pw, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(p, a.p, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       fail(-1);
       break;
@@ -601,7 +660,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     if (iters) *iters = it;
   } while (false);
   (void)hipStreamSynchronize(st);
-  (void)hipFree(buf);
+  if (!work) (void)hipFree(buf);
   if (hipGetLastError() != hipSuccess && rc == 0) rc = -1;
   return rc;
 }

@@ -65,9 +65,19 @@ enum class Part { Local, Project, Update, MeanStress };
 // p: 3V complex (interleaved) start in, unit mode out. Returns 0, -1 (HIP
 // error), -2 (a zero start or right-hand side), -3 (L + rho I not positive
 // definite); status 0 converged, 1 iteration cap.
+// work: device buffer of bloch_work_bytes(D) bytes, or null to allocate one
+// for the call.
 int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_mat,
                 const void *tw, const double omega[3], double rho, double tol, int max_iter,
-                double *p, double *beta, double *sigma_rho, int *iters, int *status);
+                double *p, void *work, double *beta, double *sigma_rho, int *iters,
+                int *status);
+size_t bloch_work_bytes(const RveDesc &D);
+
+// The allocation-free variant's work buffer: a fixed-size device array in
+// the library's code object (one per device). bloch_scratch() gives this
+// device's address (looked up on first use); -1 on a HIP error.
+size_t bloch_scratch_bytes();
+int bloch_scratch(void **ptr);
 
 // Orientation tensor sums of every cell into a.mean_out (<n (x) n> sums in
 // entries 0..8, the LCE voxel count in entry 9).
