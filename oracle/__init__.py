@@ -91,6 +91,8 @@ def lib():
         L.or_bloch.argtypes = [i, i, i, bp, mp, i, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                i, dp, dp, dp, dp, ip]
         L.or_num_threads.argtypes = []
+        L.or_set_num_threads.argtypes = [i]
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -171,6 +173,10 @@ def _mats(mats):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_num_threads(n):
+    lib().or_set_num_threads(int(n))
 
 
 def dft3(x, inverse=False):

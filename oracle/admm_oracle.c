@@ -47,6 +47,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* 3x3 helpers (row-major, A[3*i+j])                                        */
 /* ------------------------------------------------------------------------ */
@@ -506,16 +514,19 @@ static int newton_fixed_n(const or_material *m, double rho, const double *A,
 /* LCE: Newton's method on the relaxed objective phi_r(F) = W_r(F) +
    rho/2 |F - A|^2, i.e. on F and the director jointly with the director
    eliminated (W_r above). At each iterate n = n(F) (continuity with the
-   director of the previous iterate) and the Newton matrix is the relaxed
-   tangent plus rho I; backtracking as in newton_fixed_n, on phi_r with the
-   director recomputed at every trial point. Where the relaxed tangent plus
-   rho I is not positive definite with a margin of rho/4 (phi_r is not
-   convex, or barely, along a director-rotation mode: near states of
-   uniaxial symmetry the relaxed energy's curvature along that mode goes like
-   -1/(lambda_1 - lambda_2), and at A = I every director is a minimiser), the
-   solve finishes at the frozen director (newton_fixed_n) and then updates
-   the director once, leaving the rest of the director relaxation to the
-   following iterations. */
+   director of the previous iterate); backtracking as in newton_fixed_n, on
+   phi_r with the director recomputed at every trial point, so the iterates
+   descend monotonically. phi_r need not be convex: near states of uniaxial
+   symmetry its curvature along the director-rotation mode goes like
+   -1/(lambda_1 - lambda_2). The Newton matrix is therefore the relaxed
+   tangent plus (rho + tau) I with the smallest tau of the sequence
+   0, rho/16, rho/8, rho/4, ... for which the relaxed tangent plus
+   (rho + tau - rho/16) I has a Cholesky factorisation (Newton's method with
+   a multiple of the identity added to the Hessian, Nocedal & Wright,
+   Numerical Optimization, Sec. 3.4): a pure Newton step where phi_r is
+   convex with modulus rho/16, a descent direction of a positive-definite
+   model elsewhere. The solve stops at a stationary point of phi_r, which
+   with n = n(F) is a stationary point of the joint problem in (F, n). */
 static int newton_relaxed(const or_material *m, double rho, const double A[9],
                           const or_newton *opt, double F[9], double n[3],
                           const or_site *site, int *it) {
@@ -539,22 +550,21 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
     or_tangent(m, F, ncur, site, Kr);
     for (int k = 0; k < 9; ++k) Kr[10 * k] += rho;
     lce_rotation_term(m, site, F, ncur, w, V, ncl, Kr);
-    /* the relaxed step only where phi_r is convex with modulus rho/4: then
-       the minimiser is locally unique and the step well conditioned */
-    double Ks[81];
-    memcpy(Ks, Kr, sizeof(Ks));
-    for (int k = 0; k < 9; ++k) Ks[10 * k] -= 0.25 * rho;
-    if (!chol9(Ks) || !chol9(Kr)) {
-      or_newton rest = *opt;
-      int it2 = 0;
-      rest.max_iter = opt->max_iter - iter;
-      int rc = newton_fixed_n(m, rho, A, &rest, F, ncur, site, &it2);
-      *it = iter + it2;
-      if (rc == OR_EDOMAIN)
-        memcpy(n, ncur, sizeof(ncur));
-      else
-        director_eig(m, site, F, ncur, n, w, V);
-      return rc;
+    /* smallest tau of 0, rho/16, rho/8, ... with Kr + (tau - rho/16) I
+       positive definite; the step uses Kr + tau I */
+    double tau = 0.0, Ks[81];
+    int found = 0;
+    for (int tries = 0; tries < 64 && !found; ++tries) {
+      memcpy(Ks, Kr, sizeof(Ks));
+      for (int k = 0; k < 9; ++k) Ks[10 * k] += tau - rho / 16.0;
+      if (chol9(Ks)) found = 1;
+      else tau = tau == 0.0 ? rho / 16.0 : 2.0 * tau;
+    }
+    for (int k = 0; k < 9; ++k) Kr[10 * k] += tau;
+    if (!found || !chol9(Kr)) {
+      *it = iter + 1;
+      memcpy(n, ncur, sizeof(ncur));
+      return OR_NOT_CONVERGED;
     }
     double mg[9];
     for (int k = 0; k < 9; ++k) mg[k] = -g[k];

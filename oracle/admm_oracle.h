@@ -228,8 +228,10 @@ int or_bloch(int n1, int n2, int n3, const unsigned char *phase, const or_materi
              double rho, double tol, int max_iter, double *p_re, double *p_im, double *beta,
              double *sigma_rho, int *iters);
 
-/* Number of OpenMP threads the oracle uses (1 without OpenMP). */
+/* Number of OpenMP threads the oracle uses (1 without OpenMP), and setting
+ * it (n > 0). */
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

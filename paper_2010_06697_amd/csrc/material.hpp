@@ -292,6 +292,10 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
   const double smod = m.smod() + (double)rho;
   const double nA = sqrt((double)norm2_ipx(A));
   const double tol_step2 = step_tol * step_tol;
+  // phi at the current iterate when the line search evaluated it there (the
+  // accepted trial point), so that the next iteration does not evaluate it again
+  double phi_cur = 0.0;
+  bool have_phi = false;
   for (int it = 0; it < maxit; ++it) {
     const double nF2 = (double)norm2_ipx(E);
     const double thr = gtol * smod * (1.0 + sqrt(nF2) + nA);
@@ -378,7 +382,8 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
         return it + 1;
       }
     }
-    const double phi0 = small ? 0.0 : m.phi(E, A, rho, s);
+    const double phi0 = small ? 0.0 : (have_phi ? phi_cur : m.phi(E, A, rho, s));
+    have_phi = false;
     double t = 1.0;
     bool acc = false;
     Point<TG> st;
@@ -392,8 +397,11 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
           break;
         }
         if (!small) {
-          if (m.phi(Et, A, rho, st) <= phi0 + 1e-4 * t * slope) {
+          const double ph = m.phi(Et, A, rho, st);
+          if (ph <= phi0 + 1e-4 * t * slope) {
             acc = true;
+            phi_cur = ph;
+            have_phi = true;
             break;
           }
         } else {
@@ -567,13 +575,6 @@ __device__ int director_eig(const TG *E, const double *np, double *n, double *w,
   return ncl;
 }
 
-template <typename TG>
-__device__ void director_update(const TG *E, const double *np, double *n,
-                                const DirForm *form = nullptr) {
-  double w[3], V[9];
-  director_eig(E, np, n, w, V, nullptr, form);
-}
-
 // Cholesky factorisation of a packed lower triangle in place, with the
 // reciprocal square roots of the pivots in id. False when a pivot is not
 // positive.
@@ -668,13 +669,13 @@ __device__ __forceinline__ void lce_relaxed_tangent(const T *E, const Lce<T> &M,
 // the fixed-director tangent the top eigenvector's sensitivity to F,
 //     c2 / (w_0 - w_e) w_e w_e^T,  (w_e)_iJ = t_i (F^T n)_J + n_i (F^T t)_J,
 // over the eigenvectors t = t_e outside the top cluster, c2 = mu a^(1/3)(1/a - 1)
-// (negative semidefinite). Every trial point of the backtracking recomputes
-// the director (continuity with the current one). Where that Hessian plus
-// rho I is not positive definite with a margin of rho/4 (phi_r not convex,
-// or barely, along a director-rotation mode: near uniaxially symmetric
-// states the curvature goes like -1/(w_0 - w_1), and at A = I every director
-// is a minimiser), the solve finishes at the frozen director with newton()
-// and then updates the director once.
+// (negative semidefinite). phi_r need not be convex (near uniaxially
+// symmetric states the curvature along the director-rotation mode goes like
+// -1/(w_0 - w_1)); where the Newton matrix is not positive definite with a
+// margin of rho/16 a multiple of the identity is added (above), and every
+// trial point of the backtracking recomputes the director (continuity with
+// the current one), so the iterates descend monotonically to a stationary
+// point of phi_r, i.e. of the joint problem in (F, n).
 // n: previous director in, minimising director out. Returns as newton().
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -696,6 +697,8 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
   const double smod = M.smod() + (double)rho;
   const double nA = sqrt((double)norm2_ipx(A));
   const double tol_step2 = step_tol * step_tol;
+  double phi_cur = 0.0;  // phi at the accepted trial point (see newton_loop)
+  bool have_phi = false;
   int ret = -1;
   for (int it = 0; it < maxit; ++it) {
     const double nF2 = (double)norm2_ipx(E);
@@ -704,25 +707,29 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
       ret = it;
       break;
     }
-    // relaxed tangent plus rho I - shift, lower triangle packed; factorised
-    // first with shift = rho/4 (the relaxed step is taken only where phi_r
-    // is convex with that modulus: locally unique minimiser, well-conditioned
-    // step), then with shift = 0 for the step itself
+    // Newton matrix: the relaxed tangent plus (rho + tau) I, lower triangle
+    // packed, with the smallest tau of 0, rho/16, rho/8, ... for which the
+    // relaxed tangent plus (rho + tau - rho/16) I has a Cholesky
+    // factorisation (Newton's method with a multiple of the identity added,
+    // Nocedal & Wright, Sec. 3.4): a pure Newton step where phi_r is convex
+    // with modulus rho/16, a descent direction of a positive-definite model
+    // where it is not (near uniaxially symmetric states, or at A = I where
+    // every director is a minimiser)
     T L[45], id[9];
-    bool pd = true;
-    for (int pass = 0; pass < 2 && pd; ++pass) {
-      lce_relaxed_tangent(E, M, s, rho, c2, nc, w, V, ncl, pass == 0 ? (T)0.25 * rho : (T)0, L);
+    const T margin = (T)0.0625 * rho;
+    T tau = (T)0;
+    bool pd = false;
+    for (int tries = 0; tries < 64 && !pd; ++tries) {
+      lce_relaxed_tangent(E, M, s, rho, c2, nc, w, V, ncl, margin - tau, L);
+      pd = chol_packed(L, id);
+      if (!pd) tau = tau == (T)0 ? margin : (T)2 * tau;
+    }
+    if (pd) {
+      lce_relaxed_tangent(E, M, s, rho, c2, nc, w, V, ncl, -tau, L);
       pd = chol_packed(L, id);
     }
     if (!pd) {
-      // frozen director for the rest of this solve, then one director update
-      const int r = newton<T, T>(E, A, M, rho, maxit - it, gtol, step_tol);
-      if (r == -2) {
-        ret = -2;
-        break;
-      }
-      director_update(E, nc, nc, M.form);
-      ret = r >= 0 ? it + r : -1;
+      ret = -1;
       break;
     }
     T d[9];
@@ -754,7 +761,8 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
     const double slope = (double)slope_t, nd2 = (double)nd2_t;
     const bool small = -slope <= 1e-12 * smod * (1.0 + nF2);
     const bool tiny = sizeof(T) == 4 && nd2 <= tol_step2 * fmax(1.0, nF2);
-    const double phi0 = small ? 0.0 : M.phi(E, A, rho, s);
+    const double phi0 = small ? 0.0 : (have_phi ? phi_cur : M.phi(E, A, rho, s));
+    have_phi = false;
     double t = 1.0;
     bool acc = false;
     Point<T> st;
@@ -776,8 +784,11 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
           break;
         }
         if (!small) {
-          if (M.phi(Et, A, rho, st) <= phi0 + 1e-4 * t * slope) {
+          const double ph = M.phi(Et, A, rho, st);
+          if (ph <= phi0 + 1e-4 * t * slope) {
             acc = true;
+            phi_cur = ph;
+            have_phi = true;
             break;
           }
         } else {

@@ -45,7 +45,8 @@ def test_lce_local_step_matches_oracle(precision, stretched):
     """Per-voxel joint (F, director) local solves from random states: with a
     clear stretch (top eigenvalue of F F^T well separated, the relaxed
     problem convex) and with a random small distortion (near-degenerate
-    eigenvalues, where the solve may finish at a frozen director)."""
+    eigenvalues, where the relaxed problem is not convex at the start and
+    the Newton matrix gets a multiple of the identity added)."""
     shape = (6, 8, 12)
     say("lce local", precision, "stretched" if stretched else "random")
     phase = np.zeros(shape, np.uint8)
@@ -83,14 +84,17 @@ def test_lce_local_step_matches_oracle(precision, stretched):
     if precision == "fp64":
         assert errF <= 1e-10 and errn <= 1e-9
     else:
-        assert errF <= 5e-5 and errn <= (2e-3 if stretched else 5e-2)
+        # float rounding, amplified where the top two eigenvalues of F F^T
+        # are close (the director's sensitivity goes like 1/(w_0 - w_1))
+        assert errF <= (1e-6 if stretched else 1e-5) and errn <= (1e-6 if stretched else 2e-4)
 
 
 def iteration_case(name):
     """16^3 polydomain of 6 grains: relaxation of the grains' directors at
     zero macroscopic strain ('relax'); a small uniaxial stretch 1.02 where
-    the aligned state is a saddle of the relaxed local problems and the
-    solves finish at a frozen director ('small'); and a stretch 1.2 of the
+    the aligned state is a saddle of the relaxed local problems and many
+    solves start where the relaxed problem is not convex ('small'); and a
+    stretch 1.2 of the
     polydomain with a stiff neo-Hookean spherical inclusion (radius 4), where
     the LCE local problems are convex and the field is not homogeneous
     ('composite')."""
@@ -124,11 +128,13 @@ def run_both(name, precision, n_iter, rho=10.0):
     return rc, st, P, dict(u=u, F=F, Lambda=L, director=n), Po
 
 
-@pytest.mark.parametrize("name", ["relax", "small", "composite"])
+@pytest.mark.parametrize("name", ["relax", "composite"])
 def test_lce_iterations_match_oracle_fp64(name):
-    """Whole iterations (Steps 1-4) on the cases of iteration_case. Near
-    saddles of the local problems differences of rounding grow by a bounded
-    factor per iteration, so the comparison runs 4 iterations."""
+    """Whole iterations (Steps 1-4) on the cases of iteration_case whose
+    local minimisers are unique (the 'small' case's are not: see
+    test_lce_small_stretch_ends_at_local_minimisers). Near saddles of the
+    local problems differences of rounding grow by a bounded factor per
+    iteration, so the comparison runs 4 iterations."""
     say("lce iterations", name)
     rc, st, P, o, Po = run_both(name, "fp64", 4)
     errs = {k: rel(st[k], o[k]) for k in ("u", "F", "Lambda", "director")}
@@ -139,16 +145,73 @@ def test_lce_iterations_match_oracle_fp64(name):
     assert rel(P, Po) <= 1e-10
 
 
-@pytest.mark.parametrize("name,tol", [("composite", 1e-5), ("small", 1e-4)])
-def test_lce_fp32_homogenized_stress(name, tol):
-    """Float form against the double oracle after 6 iterations. 1e-5 where
-    the LCE local problems are convex; near the saddles of the small-stretch
-    case the director's sensitivity to F goes like 1/(w_0 - w_1) (about 1/0.06
-    here), which multiplies the float rounding, and the stated bound is
-    1e-4."""
+@pytest.mark.parametrize("name", ["composite", "relax"])
+def test_lce_fp32_homogenized_stress(name):
+    """Float form against the double oracle after 6 iterations, where the
+    local minimisers are unique: <P> to 1e-5."""
     rc, st, P, o, Po = run_both(name, "fp32", 6)
     say("lce fp32", name, "rel P", rel(P, Po))
-    assert rel(P, Po) <= tol
+    assert rel(P, Po) <= 1e-5
+
+
+def phi_relaxed(m, F, A, rho):
+    """W(F, n(F)) + rho/2 |F - A|^2 with n(F) the top eigenvector of F F^T
+    from numpy (not the library's or the oracle's eigen solver)."""
+    w, V = np.linalg.eigh(F.reshape(3, 3) @ F.reshape(3, 3).T)
+    return O.energy(m, F, V[:, -1]) + 0.5 * rho * np.sum((F - A) ** 2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lce_small_stretch_ends_at_local_minimisers(precision):
+    """Under the small stretch 1.02 the data A of the local problems are
+    nearly axisymmetric about the stretch, the aligned state is a saddle and
+    the local minimisers come in (near) circles of rotations about the
+    stretch axis: which one a solve ends at depends on its path, rounding
+    included, so the GPU is not compared with the oracle there. Instead every
+    GPU local solve (after 3 iterations of the polydomain) must end where the
+    joint problem is stationary (stress of the GPU's director against numpy's
+    top eigenvector of F F^T), below its warm start in the relaxed objective,
+    and, at sampled voxels, with no negative curvature of the relaxed
+    objective (central differences of the numpy-built objective)."""
+    say("lce small stretch, local minimisers", precision)
+    phase, n0, Fbar, mats = iteration_case("small")
+    rho = 10.0
+    p = admm.default_params(precision, rho0=rho, mu_ref=1.0)
+    s = admm.Solver([phase], mats, [Fbar], p, precision=precision, directors=[n0])
+    s.step(3)
+    st0 = s.state(0)
+    s.local_step()
+    st1 = s.state(0)
+    s.close()
+    m = omats(mats)[0]
+    A = O.gradient(st0["u"], Fbar.ravel()) + st0["Lambda"] / rho
+    gmax, rise, sample = 0.0, 0.0, []
+    rng = np.random.default_rng(0)
+    for k, x in enumerate(np.ndindex(phase.shape)):
+        sl = (slice(None),) + x
+        F, n, Ax = st1["F"][sl], st1["director"][sl], A[sl]
+        w, V = np.linalg.eigh(F.reshape(3, 3) @ F.reshape(3, 3).T)
+        assert abs(abs(V[:, -1] @ n) - 1.0) <= (1e-10 if precision == "fp64" else 1e-4)
+        g = O.stress(m, F, n) + rho * (F - Ax)
+        gmax = max(gmax, np.linalg.norm(g))
+        rise = max(rise, phi_relaxed(m, F, Ax, rho) - phi_relaxed(m, st0["F"][sl], Ax, rho))
+        if rng.random() < 24 / phase.size:
+            sample.append((F, Ax))
+    say("  max |grad|", gmax, "max rise", rise, "sampled", len(sample))
+    assert gmax <= (1e-9 if precision == "fp64" else 2e-4)
+    assert rise <= (1e-12 if precision == "fp64" else 1e-6)
+    h = 1e-4
+    for F, Ax in sample:
+        H = np.empty((9, 9))
+        E = np.eye(9)
+        for a in range(9):
+            for b in range(a, 9):
+                v = (phi_relaxed(m, F + h * (E[a] + E[b]), Ax, rho)
+                     - phi_relaxed(m, F + h * (E[a] - E[b]), Ax, rho)
+                     - phi_relaxed(m, F - h * (E[a] - E[b]), Ax, rho)
+                     + phi_relaxed(m, F - h * (E[a] + E[b]), Ax, rho))
+                H[a, b] = H[b, a] = v / (4 * h * h)
+        assert np.linalg.eigvalsh(H)[0] >= -1e-3 * rho
 
 
 def test_lce_load_path_matches_oracle_fp64():
@@ -172,6 +235,11 @@ def test_lce_load_path_matches_oracle_fp64():
     st = s.state(0)
     s.close()
     errs = {k: rel(st[k], o) for k, o in (("u", u), ("F", F), ("Lambda", L), ("director", n))}
-    say("  rel", errs)
-    assert errs["u"] <= 1e-10 and errs["F"] <= 1e-10 and errs["Lambda"] <= 1e-10
+    du = np.abs(st["u"] - u).max()
+    say("  rel", errs, "max|u|", np.abs(u).max(), "max|du|", du)
+    # the directors reorient and the polydomain deforms homogeneously here
+    # (u of order 1e-14): u is compared absolutely, against
+    # 1e-12 N |Fbar - I| (a relative error of a zero field means nothing)
+    assert du <= 1e-12 * 16 * np.linalg.norm(loads[-1] - np.eye(3)) or errs["u"] <= 1e-10
+    assert errs["F"] <= 1e-10 and errs["Lambda"] <= 1e-10
     assert errs["director"] <= 1e-9
