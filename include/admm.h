@@ -14,21 +14,24 @@
  * Every step runs in the library's HIP kernels; the host only launches them.
  *
  * Conventions
- *   - Grid n1 x n2 x n3 (each even, 4..256, of the form 2^a 3^b), spacing 1.
+ *   - Grid n1 x n2 x n3 (each even, 4..256, of the form 2^a 3^b; n3 = 1 is
+ *     also allowed: plane strain, every field independent of x3), spacing 1.
  *     Voxel (k1,k2,k3) has linear index (k3*n2 + k2)*n1 + k1 (x1 fastest);
  *     V = n1*n2*n3.
  *   - Fields are structure-of-arrays, component-major: a 3-vector field is
  *     3*V scalars, component i at [i*V + idx]; a 3x3 tensor field is 9*V
  *     scalars, component (i,J) at [(3*i+J)*V + idx] (row-major F_iJ).
- *   - Scalar type: double in ADMM_FP64, float in ADMM_FP32_FP64RED.
+ *   - Scalar type: double in ADMM_FP64, float in ADMM_FP32_FP64RED, except
+ *     the displacement fluctuation u (and u_prev), which is double in both.
  *   - u is the periodic displacement fluctuation (grad u = Fbar + D_h u).
  *   - The deformation-gradient field stores E = F - I (both precisions).
  *   - All field pointers are DEVICE pointers owned by the caller; the library
  *     never frees them. The context owns only its own metadata and the small
  *     device tables it allocates in admm_init.
  *   - Functions never throw; they return an admm_status code. On an error
- *     return (< 0) the state is left as it was, except ADMM_EDOMAIN, which
- *     leaves the last iterate and marks the offending cell.
+ *     return (< 0) the state is left as it was, except ADMM_EDOMAIN and
+ *     ADMM_EDIVERGED, which leave the last iterate and mark the offending
+ *     cell.
  *   - A context is bound to one HIP stream and is not thread safe. Work is
  *     enqueued on that stream; calls returning host scalars synchronise it.
  */
@@ -50,13 +53,20 @@ typedef enum {
   ADMM_EHIP = -3,         /* HIP runtime error */
   ADMM_ENOMEM = -4,       /* workspace too small / allocation failed */
   ADMM_EDOMAIN = -5,      /* det F <= 0 or NaN met in a cell */
+  ADMM_EDIVERGED = -6,    /* residuals grew or stagnated (admm_solve's
+                             divergence watch); the last iterate is kept */
   ADMM_ENOGPU = -7        /* no HIP device */
 } admm_status;
 
 typedef enum {
   ADMM_FP64 = 0,         /* everything in double precision */
-  ADMM_FP32_FP64RED = 1  /* float fields, FFT and Newton; double det F / ln J,
-                            residual norms, averages and convergence test */
+  ADMM_FP32_FP64RED = 1  /* float F, Lambda, FFT and Newton; double u, det F /
+                            ln J, residual norms, averages and convergence
+                            test. Step 2 solves for the correction
+                            u_{i+1} - u_i (its right-hand side, the defect
+                            D_h^T(F - Lambda/rho - D_h u_i), formed in double)
+                            so that the float transforms' rounding scales
+                            with the correction and not with u */
 } admm_precision;
 
 typedef enum {
@@ -69,8 +79,9 @@ typedef enum {
                         F and the unit director jointly: the director is
                         eliminated (top eigenvector of F F^T, double precision,
                         unit length) and Newton's method runs on the relaxed
-                        energy; where that is not convex the solve finishes at
-                        the frozen director and updates it once. */
+                        energy, with a multiple of the identity added to its
+                        Hessian where that is not positive definite, down to
+                        a stationary point of the joint problem. */
 } admm_model;
 
 /* One phase of the material table. */
@@ -100,8 +111,8 @@ typedef struct {
   int32_t n[3];          /* n1, n2, n3 */
   int32_t reserved;
   const uint8_t *phase;  /* V bytes, index into the material table */
-  void *u;               /* 3V: displacement fluctuation (in/out) */
-  void *u_prev;          /* 3V: second buffer the library iterates into */
+  void *u;               /* 3V doubles: displacement fluctuation (in/out) */
+  void *u_prev;          /* 3V doubles: second buffer the library iterates into */
   void *F;               /* 9V: F - I (in/out) */
   void *Lambda;          /* 9V: multiplier (in/out) */
   void *director;        /* 3V unit director (in/out; required when a phase
@@ -157,19 +168,32 @@ typedef struct {
                            converged at >= local_fraction of the voxels (0) */
   double dt;            /* time step of a load step, for the dissipation
                            terms (admm_material nu_F, nu_n) (1) */
+  /* Divergence watch of admm_solve (Sec. 4 reports that too small a penalty
+   * diverges; the method itself has no test for it). After each iteration's
+   * convergence test, with merit = max(r_p / tol_p, r_d / tol_d), a cell
+   * stops with ADMM_EDIVERGED when the merit exceeds div_growth times the
+   * smallest merit of its load step, or when the merit has not halved for
+   * stall_iters iterations. 0 switches either rule off. admm_step (a fixed
+   * count) does not watch. */
+  double div_growth;    /* (1e3) */
+  int32_t stall_iters;  /* (500) */
+  int32_t reserved2;
 } admm_params;
 
 typedef struct admm_ctx admm_ctx;
 
 /* Validates one grid (host only, no GPU needed): ADMM_OK, ADMM_EINVAL
- * (non-positive) or ADMM_EUNSUPPORTED (odd, outside 4..256, not 2^a 3^b). */
+ * (non-positive) or ADMM_EUNSUPPORTED (odd, outside 4..256, not 2^a 3^b;
+ * n3 = 1, plane strain, is supported, n1 = 1 or n2 = 1 is not). */
 int admm_check_grid(int32_t n1, int32_t n2, int32_t n3);
 
 /* Device workspace the library needs for these cells and precision (bytes):
  * the half-spectrum buffers of Step 2, three components of n3 * n2 rows per
  * cell, each row n1/2 + 1 complex values padded to 32 bytes (2 complex128 or
- * 4 complex64), 256-byte aligned per cell. The context owns the buffer for
- * its lifetime. Host only. Returns 0 on invalid input. */
+ * 4 complex64), 256-byte aligned per cell; in ADMM_FP32_FP64RED also the
+ * correction of Step 2 (3V floats, 256-byte aligned) after each cell's
+ * spectra. The context owns the buffer for its lifetime. Host only. Returns
+ * 0 on invalid input. */
 size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precision);
 
 /* Creates a context for n_rve cells sharing one material table.
@@ -352,6 +376,51 @@ typedef struct {
  * current configuration. The choice stays with the context; captured graphs
  * are rebuilt. Not thread-safe with other calls on the same context. */
 int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out);
+
+/* Persisted tuning: when the environment variable ADMM_AUTOTUNE_CACHE names
+ * a file, admm_autotune (reps > 0) first looks there for the configuration
+ * of this precision and these grids and applies it without timing; after
+ * tuning it appends its result. (The file is plain text, one line per
+ * configuration.) */
+
+/* Applies a Step 2 launch configuration (a tuning admm_autotune reported,
+ * or any other): tile widths of the x2 / x3 passes (compiled widths, LDS
+ * <= 64 KiB), points per workgroup of the x1 transforms (256, 512, 1024)
+ * and, for each of the n_len lengths listed, its radix sequence (2, 3, 4,
+ * 8, product equal to the length; lengths the context does not have are
+ * refused). ms_default / ms_tuned are ignored. ADMM_EINVAL, with nothing
+ * changed, on an invalid configuration. Results change only by rounding.
+ * Captured graphs are rebuilt. */
+int admm_set_tuning(admm_ctx *ctx, const admm_tuning *t);
+
+/* Replays admm_solve's divergence watch (admm_params div_growth,
+ * stall_iters, tol_p, tol_d) on a recorded residual history of one load
+ * step (host arrays of n entries): *at receives the index of the iteration
+ * at which the watch stops the cell, or -1 if it never does (a converged
+ * iteration ends the replay with -1). Host only, no GPU needed. */
+int admm_divergence_check(const admm_params *params, const double *r_p, const double *r_d,
+                          int32_t n, int32_t *at);
+
+/* Checkpoint and resume (Algorithm 1 carries u, F, Lambda, the director and
+ * the penalty from one iteration and one load step to the next). The state
+ * is everything the iteration reads: per cell u, F - I, Lambda, the
+ * director, the library's start-of-step copies and lagged directors of the
+ * full LCE model, the penalty, <F> and its prescribed load, the iteration
+ * count, status and residual history of the current load step, the Newton
+ * counters; and the Step 2 launch configuration (tiles, x1 points, radix
+ * plans), on which the rounding of the transforms depends. A context
+ * created with the same cells (grid sizes, phase maps), materials and
+ * parameters, given this state with admm_set_state, continues bit for bit
+ * as the original would have.
+ *   admm_get_state: blob == NULL (or *bytes too small: ADMM_ENOMEM) only
+ *     sets *bytes to the size needed; else writes the state to the host
+ *     buffer blob and sets *bytes. Synchronises the stream.
+ *   admm_set_state: reads a blob written by admm_get_state; ADMM_EINVAL
+ *     (nothing changed) when it does not match this context (format, cell
+ *     count, grid sizes, precision, which optional fields exist) or bytes
+ *     is not its size. Synchronises the stream. */
+int admm_get_state(admm_ctx *ctx, void *blob, size_t *bytes);
+int admm_set_state(admm_ctx *ctx, const void *blob, size_t bytes);
 
 /* Static description of an error code. */
 const char *admm_strerror(int code);

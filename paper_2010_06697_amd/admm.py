@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadmm.so")
 
 OK, NOT_CONVERGED = 0, 1
-EINVAL, EUNSUPPORTED, EHIP, ENOMEM, EDOMAIN, ENOGPU = -1, -2, -3, -4, -5, -7
+EINVAL, EUNSUPPORTED, EHIP, ENOMEM, EDOMAIN, EDIVERGED, ENOGPU = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_FP64RED = 0, 1
 NEOHOOKE, LCE = 0, 1
 
@@ -30,7 +30,9 @@ ENTRY_POINTS = (
     "admm_orientation", "admm_set_rho",
     "admm_step", "admm_solve", "admm_local_step", "admm_project_step", "admm_update_step",
     "admm_homogenized_stress", "admm_history", "admm_cell_info", "admm_profile_enable",
-    "admm_profile_read", "admm_autotune", "admm_strerror", "admm_destroy",
+    "admm_profile_read", "admm_autotune", "admm_set_tuning", "admm_divergence_check",
+    "admm_get_state",
+    "admm_set_state", "admm_strerror", "admm_destroy",
 )
 
 KERNELS = ("local", "div_fwdx", "fft_y_fwd", "poisson_z", "fft_y_inv", "inv_x", "update",
@@ -71,7 +73,8 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("local_ratio", ctypes.c_double), ("local_chunk", ctypes.c_int32),
                 ("local_passes", ctypes.c_int32), ("local_fraction", ctypes.c_double),
-                ("dt", ctypes.c_double)]
+                ("dt", ctypes.c_double), ("div_growth", ctypes.c_double),
+                ("stall_iters", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 _lib = None
@@ -114,6 +117,10 @@ def lib():
         L.admm_profile_enable.argtypes = [vp, i32]
         L.admm_profile_read.argtypes = [vp, i32, dp, ip]
         L.admm_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+        L.admm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.admm_divergence_check.argtypes = [ctypes.POINTER(Params), dp, dp, i32, ip]
+        L.admm_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.admm_set_state.argtypes = [vp, vp, ctypes.c_size_t]
         L.admm_strerror.argtypes = [ctypes.c_int]
         L.admm_strerror.restype = ctypes.c_char_p
         L.admm_destroy.argtypes = [vp]
@@ -239,7 +246,7 @@ def admm_solve(ctx, n_rve: int):
     it = np.zeros(n_rve, np.int32)
     st = np.zeros(n_rve, np.int32)
     rc = lib().admm_solve(ctx, _iptr(it), _iptr(st))
-    _check(rc, "admm_solve", allow=(OK, NOT_CONVERGED, EDOMAIN))
+    _check(rc, "admm_solve", allow=(OK, NOT_CONVERGED, EDOMAIN, EDIVERGED))
     return rc, it, st
 
 
@@ -308,6 +315,43 @@ def admm_autotune(ctx, reps):
             "ms_default": t.ms_default, "ms_tuned": t.ms_tuned}
 
 
+def admm_set_tuning(ctx, tile_y: int, tile_z: int, x_points: int, plans=None) -> int:
+    """Applies a Step 2 launch configuration; plans: {length: [radices]}."""
+    t = Tuning()
+    t.tile_y, t.tile_z, t.x_points = int(tile_y), int(tile_z), int(x_points)
+    plans = plans or {}
+    t.n_len = len(plans)
+    for k, (n, rad) in enumerate(sorted(plans.items())):
+        t.len[k] = int(n)
+        for j, r in enumerate(rad):
+            t.radix[k][j] = int(r)
+    return _check(lib().admm_set_tuning(ctx, ctypes.byref(t)), "admm_set_tuning")
+
+
+def admm_divergence_check(params: Params, r_p, r_d) -> int:
+    """Index of the iteration at which admm_solve's divergence watch stops a
+    cell with this residual history, or -1 (host only)."""
+    rp = np.ascontiguousarray(np.asarray(r_p, np.float64))
+    rd = np.ascontiguousarray(np.asarray(r_d, np.float64))
+    at = np.zeros(1, np.int32)
+    _check(lib().admm_divergence_check(ctypes.byref(params), _dptr(rp), _dptr(rd), len(rp),
+                                       _iptr(at)), "admm_divergence_check")
+    return int(at[0])
+
+
+def admm_get_state(ctx) -> bytes:
+    """The context's whole iteration state as a host byte string."""
+    n = ctypes.c_size_t(0)
+    _check(lib().admm_get_state(ctx, None, ctypes.byref(n)), "admm_get_state")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().admm_get_state(ctx, buf, ctypes.byref(n)), "admm_get_state")
+    return buf.raw
+
+
+def admm_set_state(ctx, blob: bytes) -> int:
+    return _check(lib().admm_set_state(ctx, blob, len(blob)), "admm_set_state")
+
+
 def admm_destroy(ctx) -> None:
     lib().admm_destroy(ctx)
 
@@ -326,6 +370,7 @@ def default_params(precision: str = "fp64", **kw) -> Params:
     p.use_graph = 1
     p.local_ratio, p.local_chunk, p.local_passes, p.local_fraction = 0.0, 1, 8, 0.0
     p.dt = 1.0
+    p.div_growth, p.stall_iters = 1e3, 500
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -347,7 +392,7 @@ class Solver:
     and macroscopic gradient, sharing one material table and parameters.
 
     Buffers are torch tensors on ``device``: per cell ``u``/``u_prev``
-    (3, n3, n2, n1), ``F`` (9, n3, n2, n1) holding F - I, ``Lambda`` (9, ...),
+    (3, n3, n2, n1, double in both precisions), ``F`` (9, n3, n2, n1) holding F - I, ``Lambda`` (9, ...),
     ``phase`` (n3, n2, n1) uint8. They start from the zero state (u = 0,
     F = I, Lambda = 0) unless overwritten with ``set_state``.
     """
@@ -378,8 +423,9 @@ class Solver:
             cell = {
                 "shape": (n3, n2, n1),
                 "phase": torch.from_numpy(ph).to(self.device),
-                "u": torch.zeros((3, n3, n2, n1), dtype=self.dtype, device=self.device),
-                "u_prev": torch.zeros((3, n3, n2, n1), dtype=self.dtype, device=self.device),
+                # the displacement fluctuation is double in both precisions
+                "u": torch.zeros((3, n3, n2, n1), dtype=torch.float64, device=self.device),
+                "u_prev": torch.zeros((3, n3, n2, n1), dtype=torch.float64, device=self.device),
                 "F": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "Lambda": torch.zeros((9, n3, n2, n1), dtype=self.dtype, device=self.device),
                 "director": None,
@@ -481,6 +527,17 @@ class Solver:
     def profile_read(self):
         return admm_profile_read(self.ctx)
 
+    def set_tuning(self, tile_y, tile_z, x_points, plans=None):
+        admm_set_tuning(self.ctx, tile_y, tile_z, x_points, plans)
+
+    def checkpoint(self) -> bytes:
+        """admm_get_state: everything needed to resume bit for bit."""
+        return admm_get_state(self.ctx)
+
+    def restore(self, blob: bytes):
+        """admm_set_state on a context built like the one checkpointed."""
+        admm_set_state(self.ctx, blob)
+
     def autotune(self, reps=5):
         return admm_autotune(self.ctx, reps)
 
@@ -503,7 +560,7 @@ class Solver:
         c = self.cells[rve]
         t = self.torch
         if u is not None:
-            c["u"].copy_(t.from_numpy(np.ascontiguousarray(u, np.float64)).to(self.device, self.dtype))
+            c["u"].copy_(t.from_numpy(np.ascontiguousarray(u, np.float64)).to(self.device))
         if F is not None:
             E = np.array(F, np.float64, copy=True)
             E[0] -= 1.0

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -20,7 +22,7 @@ using namespace admm;
 
 namespace {
 
-enum { ST_RUNNING = 0, ST_CAP = 1, ST_CONVERGED = 2, ST_DOMAIN = -5 };
+enum { ST_RUNNING = 0, ST_CAP = 1, ST_CONVERGED = 2, ST_DOMAIN = -5, ST_DIVERGED = -6 };
 
 bool is_2a3b(int n) {
   while (n % 2 == 0) n /= 2;
@@ -99,6 +101,11 @@ int spec_stride(int n1, bool fp64) { return (int)align_up((size_t)(n1 / 2 + 1), 
 size_t spec_bytes(int n1, int n2, int n3, bool fp64) {
   const size_t S = (size_t)n3 * n2 * spec_stride(n1, fp64);
   return align_up(3 * S * (fp64 ? 16 : 8), 256);
+}
+
+// float form: the correction u_{i+1} - u_i of Step 2 (3V float) after the spectra
+size_t du_bytes(int n1, int n2, int n3, bool fp64) {
+  return fp64 ? 0 : align_up(3 * (size_t)n1 * n2 * n3 * sizeof(float), 256);
 }
 
 int rows_per_block(int n1) { return std::max(1, kThreads / n1); }
@@ -242,6 +249,8 @@ struct admm_ctx {
   double2 *lpart_d = nullptr;
   double *fpart_d = nullptr;
   int2 *newton_part_d = nullptr;
+  double *nullpart_d = nullptr;
+  double *nullc_d = nullptr;
   std::vector<void *> owned;  // start-of-step copies and lagged directors
   bool any_nuF = false, any_nun = false, any_frank = false;
   void *workspace = nullptr;
@@ -303,11 +312,10 @@ int settle(admm_ctx *c) {
   int rc = download_states(c);
   if (rc != ADMM_OK) return rc;
   bool moved = false;
-  const size_t s = c->fp64 ? 8 : 4;
   for (int r = 0; r < c->n_rve; ++r) {
+    const RveDesc &D = c->desc_h[r];
     if (c->state_h[r].cur == 1) {
-      const RveDesc &D = c->desc_h[r];
-      HIP_TRY(hipMemcpyAsync(D.u[0], D.u[1], 3 * (size_t)D.V * s, hipMemcpyDeviceToDevice,
+      HIP_TRY(hipMemcpyAsync(D.u[0], D.u[1], 3 * (size_t)D.V * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
       c->state_h[r].cur = 0;
       moved = true;
@@ -345,6 +353,8 @@ IterParams iter_params(const admm_ctx *c, int test_conv) {
   ip.local_passes = p.local_passes;
   ip.local_fraction = p.local_fraction;
   ip.dt = p.dt;
+  ip.div_growth = p.div_growth;
+  ip.stall_iters = p.stall_iters;
   return ip;
 }
 
@@ -502,6 +512,8 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->mean_d);
   (void)hipFree(c->hist_d);
   (void)hipFree(c->newton_part_d);
+  (void)hipFree(c->nullpart_d);
+  (void)hipFree(c->nullc_d);
   (void)hipFree(c->lpart_d);
   (void)hipFree(c->fpart_d);
   for (void *q : c->owned) (void)hipFree(q);
@@ -645,6 +657,64 @@ int tune(admm_ctx *c, int reps, admm_tuning *out) {
   return rc;
 }
 
+// Persisted autotuner results (environment variable ADMM_AUTOTUNE_CACHE: a
+// text file, one line per key). The key names the precision and every
+// cell's grid; a line holds the tile widths, x1 points and the radix plan
+// of each length, then the two timings.
+std::string tuning_key(const admm_ctx *c) {
+  std::string k = c->fp64 ? "fp64" : "fp32";
+  for (const auto &D : c->desc_h)
+    k += "|" + std::to_string(D.n1) + "x" + std::to_string(D.n2) + "x" + std::to_string(D.n3);
+  return k;
+}
+
+bool read_tuning(const char *path, const std::string &key, admm_tuning *t) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (!found && std::fgets(line, sizeof(line), f)) {
+    char kbuf[2048];
+    int off = 0;
+    if (std::sscanf(line, "%2047s %d %d %d %d%n", kbuf, &t->tile_y, &t->tile_z, &t->x_points,
+                    &t->n_len, &off) != 5 || key != kbuf || t->n_len < 0 || t->n_len > 24)
+      continue;
+    const char *p = line + off;
+    bool ok = true;
+    for (int k = 0; k < t->n_len && ok; ++k) {
+      int n = 0, used = 0;
+      ok = std::sscanf(p, " %d:%n", &n, &used) == 1;
+      p += used;
+      t->len[k] = n;
+      for (int st = 0; st < 8; ++st) t->radix[k][st] = 0;
+      for (int st = 0; ok && st < 8; ++st) {
+        int r = 0;
+        if (std::sscanf(p, "%d%n", &r, &used) != 1) break;
+        p += used;
+        t->radix[k][st] = r;
+        if (*p != '.') break;
+        ++p;
+      }
+    }
+    found = ok && std::sscanf(p, " %lf %lf", &t->ms_default, &t->ms_tuned) == 2;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void write_tuning(const char *path, const std::string &key, const admm_tuning &t) {
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d", key.c_str(), t.tile_y, t.tile_z, t.x_points, t.n_len);
+  for (int k = 0; k < t.n_len; ++k) {
+    std::fprintf(f, " %d:", t.len[k]);
+    for (int st = 0; st < 8 && t.radix[k][st]; ++st)
+      std::fprintf(f, st ? ".%d" : "%d", t.radix[k][st]);
+  }
+  std::fprintf(f, " %.6f %.6f\n", t.ms_default, t.ms_tuned);
+  std::fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -653,6 +723,7 @@ int admm_check_grid(int32_t n1, int32_t n2, int32_t n3) {
   const int n[3] = {n1, n2, n3};
   for (int k = 0; k < 3; ++k) {
     if (n[k] <= 0) return ADMM_EINVAL;
+    if (k == 2 && n[k] == 1) continue;  // plane strain
     if (n[k] % 2 != 0 || n[k] < 4 || n[k] > kMaxN || !is_2a3b(n[k])) return ADMM_EUNSUPPORTED;
   }
   return ADMM_OK;
@@ -663,7 +734,8 @@ size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precisi
   size_t total = 0;
   for (int r = 0; r < n_rve; ++r) {
     if (admm_check_grid(rves[r].n[0], rves[r].n[1], rves[r].n[2]) != ADMM_OK) return 0;
-    total += spec_bytes(rves[r].n[0], rves[r].n[1], rves[r].n[2], precision == ADMM_FP64);
+    total += spec_bytes(rves[r].n[0], rves[r].n[1], rves[r].n[2], precision == ADMM_FP64) +
+             du_bytes(rves[r].n[0], rves[r].n[1], rves[r].n[2], precision == ADMM_FP64);
   }
   return total;
 }
@@ -677,6 +749,7 @@ const char *admm_strerror(int code) {
     case ADMM_EHIP: return "HIP runtime error";
     case ADMM_ENOMEM: return "workspace too small or allocation failed";
     case ADMM_EDOMAIN: return "det F <= 0 or NaN met";
+    case ADMM_EDIVERGED: return "residuals diverged or stagnated";
     case ADMM_ENOGPU: return "no HIP device";
     default: return "unknown status";
   }
@@ -720,7 +793,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
       !(p.local_fraction >= 0.0 && p.local_fraction <= 1.0) ||
       (p.local_ratio > 0.0 && p.local_fraction > 0.0) ||
       ((p.local_ratio > 0.0 || p.local_fraction > 0.0) &&
-       (p.local_chunk < 1 || p.local_passes < 1)))
+       (p.local_chunk < 1 || p.local_passes < 1)) ||
+      !(p.div_growth >= 0.0) || p.stall_iters < 0)
     return ADMM_EINVAL;
   for (int r = 0; r < n_rve; ++r) {
     const admm_rve &R = rves[r];
@@ -835,6 +909,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     D.dir_lag = D.dir_step = D.E_step = nullptr;
     D.spec = static_cast<char *>(c->workspace) + spec_off;
     spec_off += spec_bytes(D.n1, D.n2, D.n3, fp64);
+    D.du = fp64 ? nullptr : static_cast<char *>(c->workspace) + spec_off;
+    spec_off += du_bytes(D.n1, D.n2, D.n3, fp64);
     const int nrows = D.n2 * D.n3;
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     bf[r + 1] = bf[r] + (nrows + D.rows_f - 1) / D.rows_f;
@@ -919,14 +995,18 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->mats_d, sizeof(Material) * n_mat));
   INIT_TRY(hipMemcpy(c->mats_d, mh.data(), sizeof(Material) * n_mat, hipMemcpyHostToDevice));
 
-  INIT_TRY(hipMalloc(&c->partials_d, sizeof(double4) * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMalloc(&c->partials_d, sizeof(double4) * (size_t)c->L.nblk_x));
   INIT_TRY(hipMalloc(&c->partials18_d, sizeof(double) * 18 * (size_t)c->L.nblk_u));
   INIT_TRY(hipMalloc(&c->mean_d, sizeof(double) * 18 * n_rve));
   INIT_TRY(hipMalloc(&c->hist_d, sizeof(double) * 3 * (size_t)c->hist_cap * n_rve));
   INIT_TRY(hipMalloc(&c->lpart_d, sizeof(double2) * (size_t)c->L.nblk_x));
   INIT_TRY(hipMalloc(&c->fpart_d, sizeof(double) * 9 * (size_t)c->L.nblk_x));
-  INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_u));
-  INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_u));
+  INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_x));
+  if (!fp64) {
+    INIT_TRY(hipMalloc(&c->nullpart_d, sizeof(double) * 24 * (size_t)c->L.nblk_u));
+    INIT_TRY(hipMalloc(&c->nullc_d, sizeof(double) * 24 * (size_t)n_rve));
+  }
 
   c->state_h.assign(n_rve, RveState{});
   for (int r = 0; r < n_rve; ++r) {
@@ -935,6 +1015,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     s.rho_used = p.rho0;
     s.active = 1;
     s.status = ST_RUNNING;
+    s.best_merit = s.ref_merit = HUGE_VAL;
+    s.ref_iter = 0;
     for (int k = 0; k < 9; ++k) {
       s.Ebar[k] = rves[r].Fbar[k] - ((k % 4 == 0) ? 1.0 : 0.0);
       s.Ebar_prev[k] = s.Ebar[k];
@@ -958,6 +1040,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.mean_out = c->mean_d;
   A.hist = c->hist_d;
   A.newton_part = c->newton_part_d;
+  A.nullpart = c->nullpart_d;
+  A.nullc = c->nullc_d;
   A.lpart = c->lpart_d;
   A.fpart = c->fpart_d;
   A.n_rve = n_rve;
@@ -990,6 +1074,8 @@ int admm_set_load(admm_ctx *ctx, int32_t rve, const double Fbar[9]) {
   s.iter = 0;
   s.active = 1;
   s.status = ST_RUNNING;
+  s.best_merit = s.ref_merit = HUGE_VAL;
+  s.ref_iter = 0;
   s.newton_fail = 0;
   s.newton_iters = 0;
   s.domain_err = 0;
@@ -1119,7 +1205,8 @@ int admm_step(admm_ctx *ctx, int32_t n_iter, double *r_p, double *r_d, double *r
   int rc = activate_all(ctx);
   if (rc != ADMM_OK) return rc;
   const IterParams ip = iter_params(ctx, 0);
-  rc = run_iterations(ctx, ip, n_iter);
+  if (n_iter > 0) rc = launch(ctx, Part::StripNull, ip);
+  if (rc == ADMM_OK) rc = run_iterations(ctx, ip, n_iter);
   if (rc != ADMM_OK) return rc;
   rc = settle(ctx);
   if (rc != ADMM_OK) return rc;
@@ -1138,6 +1225,8 @@ int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out) {
   if (rc != ADMM_OK) return rc;
   const IterParams ip = iter_params(ctx, 1);
   const int every = ctx->params.check_every;
+  rc = launch(ctx, Part::StripNull, ip);
+  if (rc != ADMM_OK) return rc;
   for (;;) {
     bool any = false;
     for (const auto &s : ctx->state_h) any = any || s.active;
@@ -1152,12 +1241,14 @@ int admm_solve(admm_ctx *ctx, int32_t *iters_out, int32_t *status_out) {
   int all = ADMM_OK;
   for (int r = 0; r < ctx->n_rve; ++r) {
     const RveState &s = ctx->state_h[r];
-    int st = s.status == ST_CONVERGED ? ADMM_OK
-             : s.status == ST_DOMAIN  ? ADMM_EDOMAIN
-                                      : ADMM_NOT_CONVERGED;
+    int st = s.status == ST_CONVERGED  ? ADMM_OK
+             : s.status == ST_DOMAIN   ? ADMM_EDOMAIN
+             : s.status == ST_DIVERGED ? ADMM_EDIVERGED
+                                       : ADMM_NOT_CONVERGED;
     if (iters_out) iters_out[r] = s.iter;
     if (status_out) status_out[r] = st;
     if (st == ADMM_EDOMAIN) all = ADMM_EDOMAIN;
+    else if (st == ADMM_EDIVERGED && all != ADMM_EDOMAIN) all = ADMM_EDIVERGED;
     else if (st == ADMM_NOT_CONVERGED && all == ADMM_OK) all = ADMM_NOT_CONVERGED;
   }
   return all;
@@ -1176,7 +1267,9 @@ int admm_project_step(admm_ctx *ctx) {
   if (!ctx) return ADMM_EINVAL;
   int rc = activate_all(ctx);
   const IterParams ip = iter_params(ctx, 0);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::StripNull, ip);
   if (rc == ADMM_OK) rc = launch(ctx, Part::Project, ip);
+  if (rc == ADMM_OK) rc = launch(ctx, Part::ComposeU, ip);
   if (rc == ADMM_OK) rc = download_states(ctx);
   return rc;
 }
@@ -1230,10 +1323,11 @@ int admm_cell_info(admm_ctx *ctx, int32_t rve, int32_t *iters, int32_t *status,
   const RveState &s = ctx->state_h[rve];
   if (iters) *iters = s.iter;
   if (status)
-    *status = s.status == ST_CONVERGED ? ADMM_OK
-              : s.status == ST_DOMAIN  ? ADMM_EDOMAIN
-              : s.status == ST_CAP     ? ADMM_NOT_CONVERGED
-                                       : ADMM_OK;
+    *status = s.status == ST_CONVERGED  ? ADMM_OK
+              : s.status == ST_DOMAIN   ? ADMM_EDOMAIN
+              : s.status == ST_DIVERGED ? ADMM_EDIVERGED
+              : s.status == ST_CAP      ? ADMM_NOT_CONVERGED
+                                        : ADMM_OK;
   if (newton_fail) *newton_fail = s.newton_fail;
   if (newton_iters) *newton_iters = (int64_t)s.newton_iters;
   return ADMM_OK;
@@ -1256,6 +1350,17 @@ int admm_profile_enable(admm_ctx *ctx, int32_t on) {
 int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out) {
   if (!ctx || !out || reps < 0) return ADMM_EINVAL;
   int rc = ADMM_OK;
+  const char *cache = reps > 0 ? std::getenv("ADMM_AUTOTUNE_CACHE") : nullptr;
+  const std::string key = tuning_key(ctx);
+  if (cache && *cache) {
+    admm_tuning t{};
+    if (read_tuning(cache, key, &t) && admm_set_tuning(ctx, &t) == ADMM_OK) {
+      report_tuning(ctx, out);
+      out->ms_default = t.ms_default;
+      out->ms_tuned = t.ms_tuned;
+      return ADMM_OK;
+    }
+  }
   if (reps > 0) {
     KernelTimer *timer = ctx->L.timer;
     ctx->L.timer = nullptr;
@@ -1271,7 +1376,48 @@ int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out) {
   } else {
     out->ms_default = out->ms_tuned = 0.0;
   }
+  const double msd = out->ms_default, mst = out->ms_tuned;
   report_tuning(ctx, out);
+  out->ms_default = msd;
+  out->ms_tuned = mst;
+  if (rc == ADMM_OK && cache && *cache) write_tuning(cache, key, *out);
+  return rc;
+}
+
+int admm_set_tuning(admm_ctx *ctx, const admm_tuning *t) {
+  if (!ctx || !t) return ADMM_EINVAL;
+  const size_t csz = ctx->fp64 ? sizeof(double2) : sizeof(float2);
+  if (!tile_compiled(ctx->fp64, t->tile_y) || !tile_compiled(ctx->fp64, t->tile_z) ||
+      2 * (size_t)ctx->L.n2max * t->tile_y * csz > 65536 ||
+      2 * (size_t)ctx->L.n3max * t->tile_z * csz > 65536)
+    return ADMM_EINVAL;
+  if (t->x_points != 256 && t->x_points != 512 && t->x_points != 1024) return ADMM_EINVAL;
+  for (const auto &D : ctx->desc_h)
+    if (2 * (size_t)((3 * rows_per_fft_block(D.n1, t->x_points) + 1) / 2) * D.n1 * csz > 65536)
+      return ADMM_EINVAL;
+  if (t->n_len < 0 || t->n_len > 24) return ADMM_EINVAL;
+  const std::vector<int> lens = lengths_of(ctx);
+  std::vector<Plan1D> plans;
+  for (int k = 0; k < t->n_len; ++k) {
+    const int n = t->len[k];
+    if (std::find(lens.begin(), lens.end(), n) == lens.end()) return ADMM_EINVAL;
+    Plan1D p{};
+    p.n = n;
+    long prod = 1;
+    for (int st = 0; st < 8 && t->radix[k][st]; ++st) {
+      const int R = t->radix[k][st];
+      if ((R != 2 && R != 3 && R != 4 && R != 8) || p.nst >= kMaxStages) return ADMM_EINVAL;
+      p.rad[p.nst++] = R;
+      prod *= R;
+    }
+    if (prod != n) return ADMM_EINVAL;
+    plans.push_back(p);
+  }
+  int rc = ADMM_OK;
+  for (const Plan1D &p : plans)
+    if (rc == ADMM_OK) rc = set_plan(ctx, p);
+  if (rc == ADMM_OK) rc = set_xpoints(ctx, t->x_points);
+  if (rc == ADMM_OK) rc = set_tiles(ctx, t->tile_y, t->tile_z);
   return rc;
 }
 
@@ -1286,6 +1432,206 @@ int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *
   ctx->timer->collect();
   if (total_ms) *total_ms = ctx->timer->total_ms(kernel);
   if (launches) *launches = ctx->timer->count(kernel);
+  return ADMM_OK;
+}
+
+int admm_divergence_check(const admm_params *params, const double *r_p, const double *r_d,
+                          int32_t n, int32_t *at) {
+  if (!params || !at || n < 0 || (n > 0 && (!r_p || !r_d))) return ADMM_EINVAL;
+  *at = -1;
+  double best = HUGE_VAL, ref = HUGE_VAL;
+  int ref_iter = 0;
+  for (int it = 0; it < n; ++it) {
+    if (r_p[it] <= params->tol_p && r_d[it] <= params->tol_d) return ADMM_OK;  // converged
+    if (divergence_watch(r_p[it], r_d[it], params->tol_p, params->tol_d, it, params->div_growth,
+                         params->stall_iters, best, ref, ref_iter)) {
+      *at = it;
+      return ADMM_OK;
+    }
+  }
+  return ADMM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// checkpoint layout: header, then per cell its grid, radix plans, state,
+// load, history and fields (see admm_get_state)
+struct StateHeader {
+  char magic[8];
+  int32_t version, precision, n_rve, hist_cap, state_size, flags;
+  int32_t tile_y, tile_z, xpoints, reserved;
+};
+struct CellHeader {
+  int32_t n[3], nst[3], rad[3][kMaxStages];
+};
+constexpr char kStateMagic[8] = {'A', 'D', 'M', 'M', 'S', 'T', 'A', 'T'};
+enum { SF_DIR = 1, SF_LAG = 2, SF_DSTEP = 4, SF_ESTEP = 8 };
+
+int state_flags(const admm_ctx *c) {
+  const RveDesc &D = c->desc_h[0];
+  return (D.dir ? SF_DIR : 0) | (D.dir_lag ? SF_LAG : 0) | (D.dir_step ? SF_DSTEP : 0) |
+         (D.E_step ? SF_ESTEP : 0);
+}
+
+// the device fields of one cell in blob order: pointer and bytes
+std::vector<std::pair<void *, size_t>> state_fields(const admm_ctx *c, int r) {
+  const RveDesc &D = c->desc_h[r];
+  const size_t V = (size_t)D.V, s = c->fp64 ? 8 : 4;
+  std::vector<std::pair<void *, size_t>> f;
+  f.push_back({D.u[0], 3 * V * sizeof(double)});
+  f.push_back({D.E, 9 * V * s});
+  f.push_back({D.Lam, 9 * V * s});
+  if (D.dir) f.push_back({D.dir, 3 * V * s});
+  if (D.dir_lag) f.push_back({D.dir_lag, 3 * V * s});
+  if (D.dir_step) f.push_back({D.dir_step, 3 * V * s});
+  if (D.E_step) f.push_back({D.E_step, 9 * V * s});
+  return f;
+}
+
+size_t state_bytes(const admm_ctx *c) {
+  size_t b = sizeof(StateHeader);
+  for (int r = 0; r < c->n_rve; ++r) {
+    b += sizeof(CellHeader) + sizeof(RveState) + 9 * sizeof(double) +
+         3 * (size_t)c->hist_cap * sizeof(double);
+    for (const auto &f : state_fields(c, r)) b += f.second;
+  }
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int admm_get_state(admm_ctx *ctx, void *blob, size_t *bytes) {
+  if (!ctx || !bytes) return ADMM_EINVAL;
+  const size_t need = state_bytes(ctx);
+  if (!blob || *bytes < need) {
+    const bool query = !blob;
+    *bytes = need;
+    return query ? ADMM_OK : ADMM_ENOMEM;
+  }
+  int rc = settle(ctx);  // u current in the first buffer, states read back
+  if (rc != ADMM_OK) return rc;
+  char *q = static_cast<char *>(blob);
+  StateHeader h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = 1;
+  h.precision = ctx->fp64 ? ADMM_FP64 : ADMM_FP32_FP64RED;
+  h.n_rve = ctx->n_rve;
+  h.hist_cap = ctx->hist_cap;
+  h.state_size = (int32_t)sizeof(RveState);
+  h.flags = state_flags(ctx);
+  h.tile_y = ctx->L.tile_y;
+  h.tile_z = ctx->L.tile_z;
+  h.xpoints = ctx->xpoints;
+  std::memcpy(q, &h, sizeof(h));
+  q += sizeof(h);
+  for (int r = 0; r < ctx->n_rve; ++r) {
+    const RveDesc &D = ctx->desc_h[r];
+    CellHeader ch{};
+    const Plan1D *pl[3] = {&D.p1, &D.p2, &D.p3};
+    for (int k = 0; k < 3; ++k) {
+      ch.n[k] = pl[k]->n;
+      ch.nst[k] = pl[k]->nst;
+      for (int st = 0; st < kMaxStages; ++st) ch.rad[k][st] = st < pl[k]->nst ? pl[k]->rad[st] : 0;
+    }
+    std::memcpy(q, &ch, sizeof(ch));
+    q += sizeof(ch);
+    std::memcpy(q, &ctx->state_h[r], sizeof(RveState));
+    q += sizeof(RveState);
+    std::memcpy(q, ctx->rves[r].Fbar, 9 * sizeof(double));
+    q += 9 * sizeof(double);
+    const size_t hb = 3 * (size_t)ctx->hist_cap * sizeof(double);
+    HIP_TRY(hipMemcpy(q, ctx->hist_d + (size_t)r * ctx->hist_cap * 3, hb, hipMemcpyDeviceToHost));
+    q += hb;
+    for (const auto &f : state_fields(ctx, r)) {
+      HIP_TRY(hipMemcpy(q, f.first, f.second, hipMemcpyDeviceToHost));
+      q += f.second;
+    }
+  }
+  *bytes = need;
+  return ADMM_OK;
+}
+
+int admm_set_state(admm_ctx *ctx, const void *blob, size_t bytes) {
+  if (!ctx || !blob) return ADMM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const size_t need = state_bytes(ctx);
+  if (bytes != need) return ADMM_EINVAL;
+  const char *q = static_cast<const char *>(blob);
+  StateHeader h;
+  std::memcpy(&h, q, sizeof(h));
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 ||
+      h.precision != (ctx->fp64 ? ADMM_FP64 : ADMM_FP32_FP64RED) || h.n_rve != ctx->n_rve ||
+      h.hist_cap != ctx->hist_cap || h.state_size != (int32_t)sizeof(RveState) ||
+      h.flags != state_flags(ctx) || !tile_compiled(ctx->fp64, h.tile_y) ||
+      !tile_compiled(ctx->fp64, h.tile_z) ||
+      (h.xpoints != 256 && h.xpoints != 512 && h.xpoints != 1024))
+    return ADMM_EINVAL;
+  // validate every cell before changing anything
+  std::vector<CellHeader> cells(ctx->n_rve);
+  {
+    const char *p = q + sizeof(h);
+    for (int r = 0; r < ctx->n_rve; ++r) {
+      std::memcpy(&cells[r], p, sizeof(CellHeader));
+      const RveDesc &D = ctx->desc_h[r];
+      const int nn[3] = {D.n1, D.n2, D.n3};
+      for (int k = 0; k < 3; ++k) {
+        const CellHeader &c = cells[r];
+        if (c.n[k] != nn[k] || c.nst[k] < 0 || c.nst[k] > kMaxStages) return ADMM_EINVAL;
+        long prod = 1;
+        for (int st = 0; st < c.nst[k]; ++st) {
+          const int R = c.rad[k][st];
+          if (R != 2 && R != 3 && R != 4 && R != 8) return ADMM_EINVAL;
+          prod *= R;
+        }
+        if (prod != nn[k]) return ADMM_EINVAL;
+      }
+      p += sizeof(CellHeader) + sizeof(RveState) + 9 * sizeof(double) +
+           3 * (size_t)ctx->hist_cap * sizeof(double);
+      for (const auto &f : state_fields(ctx, r)) p += f.second;
+    }
+  }
+  // launch configuration: radix plans, tiles, x1 points
+  for (int r = 0; r < ctx->n_rve; ++r) {
+    RveDesc &D = ctx->desc_h[r];
+    Plan1D *pl[3] = {&D.p1, &D.p2, &D.p3};
+    for (int k = 0; k < 3; ++k) {
+      pl[k]->nst = cells[r].nst[k];
+      for (int st = 0; st < kMaxStages; ++st) pl[k]->rad[st] = cells[r].rad[k][st];
+      plan_divisors(*pl[k]);
+    }
+  }
+  int rc = set_xpoints(ctx, h.xpoints);  // also uploads the descriptors
+  if (rc == ADMM_OK) rc = set_tiles(ctx, h.tile_y, h.tile_z);
+  if (rc != ADMM_OK) return rc;
+  q += sizeof(h);
+  bool any_free = false;
+  for (int r = 0; r < ctx->n_rve; ++r) {
+    q += sizeof(CellHeader);
+    std::memcpy(&ctx->state_h[r], q, sizeof(RveState));
+    ctx->state_h[r].cur = 0;
+    any_free = any_free || ctx->state_h[r].free_mask != 0;
+    q += sizeof(RveState);
+    std::memcpy(ctx->rves[r].Fbar, q, 9 * sizeof(double));
+    q += 9 * sizeof(double);
+    const size_t hb = 3 * (size_t)ctx->hist_cap * sizeof(double);
+    HIP_TRY(hipMemcpy(ctx->hist_d + (size_t)r * ctx->hist_cap * 3, q, hb, hipMemcpyHostToDevice));
+    q += hb;
+    for (const auto &f : state_fields(ctx, r)) {
+      HIP_TRY(hipMemcpy(f.first, q, f.second, hipMemcpyHostToDevice));
+      q += f.second;
+    }
+  }
+  if (any_free != ctx->L.any_free) {
+    drop_graphs(ctx);
+    ctx->L.any_free = any_free;
+  }
+  rc = upload_states(ctx);
+  if (rc != ADMM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
   return ADMM_OK;
 }
 

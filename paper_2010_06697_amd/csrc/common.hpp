@@ -62,7 +62,10 @@ struct RveDesc {
   FastDiv f_n1, f_n2, f_m1, f_rows_f;  // the same as divisors
   Plan1D p1, p2, p3;
   const uint8_t *phase;
-  void *u[2];               // displacement fluctuation, ping-pong
+  void *u[2];               // displacement fluctuation (double in both
+                            // precisions), ping-pong
+  void *du;                 // float form: the correction u_{i+1} - u_i of
+                            // Step 2 (3V float, in the workspace), else null
   void *E;                  // F - I
   void *Lam;                // multiplier
   void *dir;                // director (LCE) or null
@@ -91,8 +94,33 @@ struct RveState {
   double Ebar[9];       // <F> - I of the current iterate (free components move)
   double Ebar_prev[9];  // <F> - I of the previous iterate (r_d)
   unsigned free_mask;   // bit k: component k of <F> free (mixed conditions)
+  int ref_iter;         // divergence watch: iteration of the last halving
   int pad2;
+  int pad3;
+  double best_merit;    // divergence watch: smallest merit of the load step
+  double ref_merit;     // divergence watch: merit at ref_iter
 };
+
+// Divergence / stagnation watch of admm_solve, applied after each
+// iteration's convergence test. merit = max(r_p / tol_p, r_d / tol_d).
+// Diverged when the merit exceeds growth x the smallest merit of the load
+// step (growth > 0), or when it has not halved for `stall` iterations
+// (stall > 0). best / ref / ref_iter start at +inf / +inf / 0 with each load
+// step. Shared by the device (k_finalize) and the host replay
+// (admm_divergence_check).
+__host__ __device__ inline bool divergence_watch(double rp, double rd, double tol_p, double tol_d,
+                                                 int it, double growth, int stall, double &best,
+                                                 double &ref, int &ref_iter) {
+  const double tp = tol_p > 0.0 ? tol_p : 1e-300, td = tol_d > 0.0 ? tol_d : 1e-300;
+  const double m = rp / tp > rd / td ? rp / tp : rd / td;
+  if (m < best) best = m;
+  if (m <= 0.5 * ref) {
+    ref = m;
+    ref_iter = it;
+  }
+  if (growth > 0.0 && m > growth * best) return true;
+  return stall > 0 && it - ref_iter >= stall;
+}
 
 constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
 constexpr int kLocalPassGrid = 2048;  // workgroups of the later inexact local passes
@@ -125,6 +153,8 @@ struct IterParams {
   int local_passes;
   double local_fraction;  // inexact local step, converged fraction (0: off)
   double dt;              // time step (dissipation)
+  double div_growth;      // divergence watch (admm_solve): growth factor (0: off)
+  int stall_iters;        // divergence watch: stagnation window (0: off)
 };
 
 template <typename T> struct cplx;

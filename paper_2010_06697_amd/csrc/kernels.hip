@@ -34,6 +34,10 @@ namespace admm {
 // helpers
 // ----------------------------------------------------------------------------
 
+// The float form solves Step 2 for the correction u_{i+1} - u_i (defect
+// correction) and keeps u in double; the double form solves for u_{i+1}.
+template <typename T> constexpr bool kDefect = sizeof(T) == 4;
+
 // neighbour offsets of voxel (x1,x2,x3) along +-e1, +-e2, +-e3 (periodic)
 struct Stencil {
   int o[6];
@@ -64,6 +68,14 @@ template <typename T> __device__ __forceinline__ gptr<T> global_view(T *p) {
   return (gptr<T>)p;
 }
 
+// x + 2 and x - 2 modulo n, for n = 1 (plane strain along x3) or n >= 4
+__device__ __forceinline__ int wrap_plus2(int x, int n) {
+  return n == 1 ? 0 : (x + 2 >= n ? x + 2 - n : x + 2);
+}
+__device__ __forceinline__ int wrap_minus2(int x, int n) {
+  return n == 1 ? 0 : (x - 2 < 0 ? x - 2 + n : x - 2);
+}
+
 // central differences (u_i(x+e_j) - u_i(x-e_j))/2 of a 3-vector field; out[3i+j]
 template <typename P>
 __device__ __forceinline__ void grad_u(P u, int V, const Stencil &s, double *out) {
@@ -74,6 +86,30 @@ __device__ __forceinline__ void grad_u(P u, int V, const Stencil &s, double *out
     for (int j = 0; j < 3; ++j)
       out[3 * i + j] = 0.5 * ((double)ui[s.o[2 * j]] - (double)ui[s.o[2 * j + 1]]);
   }
+}
+
+// the same of u + du (float form: u_{i+1} = u_i + du, each value formed as
+// it is stored, so the gradient equals the one of the stored u_{i+1})
+template <typename P, typename Q>
+__device__ __forceinline__ void grad_u_sum(P u, Q du, int V, const Stencil &s, double *out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const auto ui = u + i * V;
+    const auto di = du + i * V;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int p = s.o[2 * j], m = s.o[2 * j + 1];
+      out[3 * i + j] = 0.5 * ((ui[p] + (double)di[p]) - (ui[m] + (double)di[m]));
+    }
+  }
+}
+
+// (x2, first x3) of workgroup b of a cell in the update / mean-stress tiling
+__device__ __forceinline__ void column_tile(const RveDesc &D, int b, int row, int &x2, int &z0) {
+  const int ny = (D.n2 + D.rows - 1) / D.rows;
+  const int zc = b / ny;
+  x2 = (b - zc * ny) * D.rows + row;
+  z0 = zc * kVoxelsPerThread;
 }
 
 // deterministic sum of NV doubles over the workgroup; result valid in thread 0
@@ -166,7 +202,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     const double irho = 1.0 / rho0;
     const int x2 = grow % n2, x3 = grow / n2;
     const int idx = grow * n1 + x1;
-    const auto u = global_view(static_cast<const T *>(D.u[st->cur]));
+    const auto u = global_view(static_cast<const double *>(D.u[st->cur]));
     const auto Eg = global_view(static_cast<T *>(D.E));
     const auto Lg = global_view(static_cast<const T *>(D.Lam));
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
@@ -567,6 +603,24 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     const T *Eg = static_cast<const T *>(D.E);
     const T *Lg = static_cast<const T *>(D.Lam);
+    // float form: the defect D_h^T (H - D_h u_i), in double, whose solve is
+    // the correction u_{i+1} - u_i (the transforms' float rounding then
+    // scales with the correction, not with u itself);
+    // D_h^T D_h u_i = -sum_j (u_i(x + 2 e_j) - 2 u_i(x) + u_i(x - 2 e_j)) / 4
+    int o2[6];
+    if (kDefect<T>) {
+      const int y2 = wrap_plus2(x2, n2), ym = wrap_minus2(x2, n2);
+      const int z2 = wrap_plus2(x3, n3), zm = wrap_minus2(x3, n3);
+      const int x1p = wrap_plus2(x1, n1), x1m = wrap_minus2(x1, n1);
+      const int rw0 = (x3 * n2 + x2) * n1;
+      o2[0] = rw0 + x1p;
+      o2[1] = rw0 + x1m;
+      o2[2] = (x3 * n2 + y2) * n1 + x1;
+      o2[3] = (x3 * n2 + ym) * n1 + x1;
+      o2[4] = (z2 * n2 + x2) * n1 + x1;
+      o2[5] = (zm * n2 + x2) * n1 + x1;
+    }
+    const double *ug = static_cast<const double *>(D.u[st->cur]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       double bi = 0.0;
@@ -577,6 +631,14 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
         const double hm =
             (double)Eg[c + sn.o[2 * j + 1]] - (double)Lg[c + sn.o[2 * j + 1]] * irho;
         bi -= 0.5 * (hp - hm);
+      }
+      if (kDefect<T>) {
+        const double *ui = ug + i * V;
+        const double u0 = ui[grow * n1 + x1];
+        double lap = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lap += (ui[o2[2 * j]] - u0) + (ui[o2[2 * j + 1]] - u0);
+        bi += 0.25 * lap;
       }
       const int ell = i * R + row;
       C *z = za + (ell >> 1) * n1 + x1;
@@ -792,7 +854,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   __syncthreads();
   const C *tw = static_cast<const C *>(a.tw);
   C *res = fft_lines<true>(za, zb, D.p1, tw, ncl, n1, 1, false, t, nthr);
-  T *un = static_cast<T *>(D.u[1 - st->cur]);
+  // double form: u_{i+1}; float form: the correction u_{i+1} - u_i
+  T *un = kDefect<T> ? static_cast<T *>(D.du) : static_cast<T *>(D.u[1 - st->cur]);
   for (int w = t; w < 3 * R * n1; w += nthr) {
     const int ell = fdiv(w, D.f_n1), x1 = w - ell * n1;
     const int c = fdiv(ell, D.f_rows_f), rw = ell - c * R;
@@ -804,6 +867,118 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
   }
 }
 
+// The fluctuation's components that D_h does not see: the mean and the
+// Nyquist checkerboards chi_s(x) = (-1)^(s1 k1 + s2 k2 + s3 k3), s in {0,1}^3
+// (s3 = 0 only when n3 = 1). Step 2 in the double form returns u without
+// them; the float form adds corrections to u_i and would keep whatever u_i
+// holds, so each call of the float form first removes them from u:
+// k_null_sums (per update workgroup, the 24 sums of u_i chi_s), k_null_final
+// (per cell, fixed order, coefficients / V), k_null_sub.
+__device__ __forceinline__ double chi(int s, int k1, int k2, int k3) {
+  const int e = ((s & 1) ? k1 : 0) + ((s & 2) ? k2 : 0) + ((s & 4) ? k3 : 0);
+  return (e & 1) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_null_sums(KernelArgs a) {
+  __shared__ double red[24 * (kThreads / 64)];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_u, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  const int b = blk - a.blk_u[r];
+  const int V = (int)D.V, n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
+  const double *u = static_cast<const double *>(D.u[st->cur]);
+  const int t = threadIdx.x, row = t / n1, x1 = t - row * n1;
+  int x2, z0;
+  column_tile(D, b, row, x2, z0);
+  double v[24];
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = 0.0;
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int x3 = z0 + k;
+    if (row >= R || x2 >= n2 || x3 >= n3) continue;
+    const int idx = (x3 * n2 + x2) * n1 + x1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double ui = u[i * V + idx];
+#pragma unroll
+      for (int sgn = 0; sgn < 8; ++sgn) v[8 * i + sgn] += ui * chi(sgn, x1, x2, x3);
+    }
+  }
+  block_sum<24>(v, red);
+  if (t == 0)
+#pragma unroll
+    for (int k = 0; k < 24; ++k) a.nullpart[(size_t)blk * 24 + k] = v[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_null_final(KernelArgs a) {
+  __shared__ double red[24 * (kThreads / 64)];
+  const int r = blockIdx.x;
+  const int p0 = a.blk_u[r], nb = a.blk_u[r + 1] - p0;
+  double v[24];
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] += a.nullpart[(size_t)(p0 + q) * 24 + k];
+  block_sum<24>(v, red);
+  if (threadIdx.x == 0) {
+    const RveDesc &D = a.desc[r];
+    const double iV = 1.0 / (double)D.V;
+#pragma unroll
+    for (int k = 0; k < 24; ++k)  // with n3 = 1 the patterns with s3 = 1 repeat s3 = 0
+      a.nullc[(size_t)r * 24 + k] = (D.n3 == 1 && (k & 4)) ? 0.0 : v[k] * iV;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_null_sub(KernelArgs a) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_u, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  const int b = blk - a.blk_u[r];
+  const int V = (int)D.V, n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
+  double *u = static_cast<double *>(D.u[st->cur]);
+  const double *c = a.nullc + (size_t)r * 24;
+  const int t = threadIdx.x, row = t / n1, x1 = t - row * n1;
+  int x2, z0;
+  column_tile(D, b, row, x2, z0);
+  for (int k = 0; k < kVoxelsPerThread; ++k) {
+    const int x3 = z0 + k;
+    if (row >= R || x2 >= n2 || x3 >= n3) continue;
+    const int idx = (x3 * n2 + x2) * n1 + x1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double w = 0.0;
+#pragma unroll
+      for (int sgn = 0; sgn < 8; ++sgn) w += c[8 * i + sgn] * chi(sgn, x1, x2, x3);
+      u[i * V + idx] -= w;
+    }
+  }
+}
+
+// float form, single Step 2 call (admm_project_step): u_prev = u + du, so
+// that the call leaves u_{i+1} where the double form leaves it
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_compose_u(KernelArgs a) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_x, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  if (!st->active || !D.du) return;
+  const int b = blk - a.blk_x[r];
+  const int n1 = D.n1, R = D.rows, nrows = D.n2 * D.n3, V = (int)D.V;
+  const int row = threadIdx.x / n1, x1 = threadIdx.x - row * n1;
+  const int grow = b * R + row;
+  if (row >= R || grow >= nrows) return;
+  const int idx = grow * n1 + x1;
+  const double *uo = static_cast<const double *>(D.u[st->cur]);
+  double *un = static_cast<double *>(D.u[1 - st->cur]);
+  const T *du = static_cast<const T *>(D.du);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) un[i * V + idx] = uo[i * V + idx] + (double)du[i * V + idx];
+}
+
 // ----------------------------------------------------------------------------
 // Step 3 + partial sums of Step 4. A workgroup owns R x1-lines (one x2 group)
 // on kVoxelsPerThread consecutive planes: the +-x3 neighbours of its planes
@@ -813,17 +988,65 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
 // which run at the same time.
 // ----------------------------------------------------------------------------
 
-// (x2, first x3) of workgroup b of a cell in the update / mean-stress tiling
-__device__ __forceinline__ void column_tile(const RveDesc &D, int b, int row, int &x2, int &z0) {
-  const int ny = (D.n2 + D.rows - 1) / D.rows;
-  const int zc = b / ny;
-  x2 = (b - zc * ny) * D.rows + row;
-  z0 = zc * kVoxelsPerThread;
+
+// Step 3 at one voxel: grad u_{i+1} (Dn), Lambda_{i+1} written and kept as
+// stored (lamT), and the residual terms |grad u_{i+1} - F_{i+1}|^2 and
+// |grad u_{i+1} - grad u_i|^2 added to v. Double form: u_{i+1} from Step 2;
+// float form: u_{i+1} = u_i + du formed (and stored) here, its gradient as
+// the one of the stored values, the change of the gradient from du alone.
+template <typename T, typename EP>
+__device__ __forceinline__ void update_voxel(const RveDesc &D, const RveState *st, int V, int idx,
+                                             const Stencil &sn, double rho, EP Eg, T *E,
+                                             double *Dn, T *lamT, double *v) {
+  const auto un = global_view(static_cast<double *>(D.u[1 - st->cur]));
+  const auto uo = global_view(static_cast<const double *>(D.u[st->cur]));
+  const auto Lg = global_view(static_cast<T *>(D.Lam));
+  double Dd[9];
+  if (kDefect<T>) {
+    const auto dug = global_view(static_cast<const T *>(D.du));
+    grad_u_sum(uo, dug, V, sn, Dn);
+    grad_u(dug, V, sn, Dd);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) un[i * V + idx] = uo[i * V + idx] + (double)dug[i * V + idx];
+  } else {
+    double Do[9];
+    grad_u(un, V, sn, Dn);
+    grad_u(uo, V, sn, Do);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Dd[c] = Dn[c] - Do[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    E[c] = Eg[c * V + idx];
+    const double e = st->Ebar[c] + Dn[c] - (double)E[c];
+    lamT[c] = (T)((double)Lg[c * V + idx] + rho * e);
+    Lg[c * V + idx] = lamT[c];
+    const double dd = Dd[c] + (st->Ebar[c] - st->Ebar_prev[c]);
+    v[0] += e * e;
+    v[1] += dd * dd;
+  }
 }
 
+// the workgroup's residual partials and the Newton statistics the local
+// step's workgroups left in its slot (plus `f`, `sm`)
+__device__ __forceinline__ void store_partials(KernelArgs &a, int blk, double *v, int f, int sm) {
+  __shared__ double red[2 * (kThreads / 64)];
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    const int2 q = a.newton_part[blk];
+    a.newton_part[blk] = int2{0, 0};
+    a.partials[blk] = double4{v[0], v[1], (double)(q.x + f), (double)(q.y + sm)};
+  }
+}
+
+// Step 3 + partial sums of Step 4. A workgroup owns R x1-lines (one x2 group)
+// on kVoxelsPerThread consecutive planes: the +-x3 neighbours of its planes
+// are its own lines or the two next to them, read within the workgroup's
+// lifetime instead of a plane of streamed fields apart (which an XCD's L2
+// does not hold); the +-x2 neighbours are lines of the adjacent workgroups,
+// which run at the same time.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
-  __shared__ double red[2 * (kThreads / 64)];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_u, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
@@ -832,11 +1055,7 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const int b = blk - a.blk_u[r];
   const int V = (int)D.V;
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
-  const double rho = st->rho;
-  const T *__restrict__ un = static_cast<const T *>(D.u[1 - st->cur]);
-  const T *__restrict__ uo = static_cast<const T *>(D.u[st->cur]);
-  const T *__restrict__ Eg = static_cast<const T *>(D.E);
-  T *__restrict__ Lg = static_cast<T *>(D.Lam);
+  const auto Eg = global_view(static_cast<const T *>(D.E));
   const int t = threadIdx.x;
   const int row = t / n1, x1 = t - row * n1;
   int x2, z0;
@@ -848,25 +1067,11 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
     if (row >= R || x2 >= n2 || x3 >= n3) continue;
     const int idx = (x3 * n2 + x2) * n1 + x1;
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
-    double Dn[9], Do[9];
-    grad_u(un, V, sn, Dn);
-    grad_u(uo, V, sn, Do);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const double e = st->Ebar[c] + Dn[c] - (double)Eg[c * V + idx];
-      Lg[c * V + idx] = (T)((double)Lg[c * V + idx] + rho * e);
-      const double dd = (Dn[c] - Do[c]) + (st->Ebar[c] - st->Ebar_prev[c]);
-      v[0] += e * e;
-      v[1] += dd * dd;
-    }
+    T E[9], lam[9];
+    double Dn[9];
+    update_voxel<T>(D, st, V, idx, sn, st->rho, Eg, E, Dn, lam, v);
   }
-  block_sum<2>(v, red);
-  if (threadIdx.x == 0) {
-    // Newton statistics the local step's workgroups left in this slot
-    const int2 q = a.newton_part[blk];
-    a.newton_part[blk] = int2{0, 0};
-    a.partials[blk] = double4{v[0], v[1], (double)q.x, (double)q.y};
-  }
+  store_partials(a, blk, v, 0, 0);
 }
 
 // ----------------------------------------------------------------------------
@@ -935,6 +1140,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
       !(ip.local_ratio > 0.0 || ip.local_fraction > 0.0) || st->rl <= ip.tol_d;
   if (ip.test_conv && rp <= ip.tol_p && rd <= ip.tol_d && local_ok) {
     st->status = 2;  // converged
+    st->active = 0;
+    return;
+  }
+  if (ip.test_conv && divergence_watch(rp, rd, ip.tol_p, ip.tol_d, it, ip.div_growth,
+                                       ip.stall_iters, st->best_merit, st->ref_merit,
+                                       st->ref_iter)) {
+    st->status = -6;  // diverged or stagnated: the last iterate is kept
     st->active = 0;
     return;
   }
@@ -1176,6 +1388,18 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
         Timed tm(L, K_FINALIZE);
         hipLaunchKernelGGL(k_finalize, dim3(a.n_rve), blk, 0, L.stream, a, ip);
       }
+      break;
+    }
+    case Part::StripNull: {
+      if (kDefect<T>) {
+        hipLaunchKernelGGL(k_null_sums, dim3(L.nblk_u), blk, 0, L.stream, a);
+        hipLaunchKernelGGL(k_null_final, dim3(a.n_rve), blk, 0, L.stream, a);
+        hipLaunchKernelGGL(k_null_sub, dim3(L.nblk_u), blk, 0, L.stream, a);
+      }
+      break;
+    }
+    case Part::ComposeU: {
+      if (kDefect<T>) hipLaunchKernelGGL((k_compose_u<T>), dim3(L.nblk_x), blk, 0, L.stream, a);
       break;
     }
     case Part::MeanStress: {

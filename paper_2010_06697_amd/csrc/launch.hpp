@@ -28,6 +28,8 @@ struct KernelArgs {
                         // the free components of <F>
   int2 *newton_part;    // per update workgroup: failed solves and Newton iterations
                         // of the local-step workgroups in its tile
+  double *nullpart;     // per update workgroup: 24 sums of u_i chi_s (float form)
+  double *nullc;        // per cell: 24 null-mode coefficients of u
   int n_rve;
   int n_mat;
 };
@@ -59,7 +61,10 @@ struct LaunchCfg {
   bool any_free;  // some cell leaves components of <F> free
 };
 
-enum class Part { Local, Project, Update, MeanStress };
+// ComposeU: after a single Step 2 call of the float form, u_prev = u + du.
+// StripNull: the float form removes the mean and the Nyquist checkerboards
+// of u (which D_h does not see) before it iterates.
+enum class Part { Local, Project, Update, MeanStress, ComposeU, StripNull };
 
 // Bloch-wave stability modulus of one cell (double precision; bloch.hip).
 // p: 3V complex (interleaved) start in, unit mode out. Returns 0, -1 (HIP

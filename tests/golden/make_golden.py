@@ -86,7 +86,46 @@ def wavy32():
             "u_norm": float(np.linalg.norm(u)), "F_norm": float(np.linalg.norm(F))}
 
 
+def fibres256x2():
+    """The 256^3 fibre cell's cross-section, two voxels along x3. Fibres along
+    x3 and shear in the x1-x2 plane: the solution of the 256^3 cell does not
+    depend on x3 (and u_3 = 0), and neither do its ADMM iterates, so the
+    256 x 256 x 2 run stands for the 256^3 one (periodic setting of
+    Sec. 2.3)."""
+    case = M.fibres256_case(n3=2)
+    mats = omats(case["materials"])
+    out = {"source": "oracle ADMM (Sec. 2.1, adaptive penalty, kappa 1.3, tau 10, rho in "
+                     "[1, 50], rho0 = 10, mu_ref = 15.7) on the 256 x 256 x 2 cross-section of "
+                     "the fibre cell (fibres along x3, r = 8, area fraction 0.3, fibre (50, 500), "
+                     "matrix (1, 10)), Fbar = I + 0.01 e1 e2: 40 iterations, and the same run "
+                     "continued to r_p, r_d <= 1e-8",
+           "runs": {}}
+    u, F, L = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=40, fixed_iters=True, mu_ref=case["mu_ref"], adapt_rho=True,
+                 rho_min=1.0, rho_max=50.0, newton=O.newton_opts(**NEWTON64))
+    r = O.admm_run(case["phase"], mats, case["loads"][0].ravel(), p, u, F, L, case["rho0"])
+    out["runs"]["fixed40"] = {"iters": r["iters"], "r_p": r["r_p"].tolist(),
+                              "r_d": r["r_d"].tolist(), "rho": r["rho_hist"].tolist(),
+                              "P_mean": O.mean_stress(case["phase"], mats, F).tolist()}
+    u, F, L = O.initial_state(case["phase"].shape)
+    p = O.params(max_iter=2000, tol_p=1e-8, tol_d=1e-8, mu_ref=case["mu_ref"], adapt_rho=True,
+                 rho_min=1.0, rho_max=50.0, newton=O.newton_opts(**NEWTON64))
+    r = O.admm_run(case["phase"], mats, case["loads"][0].ravel(), p, u, F, L, case["rho0"])
+    out["runs"]["converged"] = {"iters": r["iters"], "rc": r["rc"],
+                                "r_p": r["r_p"][-5:].tolist(), "r_d": r["r_d"][-5:].tolist(),
+                                "P_mean": O.mean_stress(case["phase"], mats, F).tolist(),
+                                "max_abs_u3": float(np.abs(u[2]).max())}
+    return out
+
+
 if __name__ == "__main__":
+    # the 256 x 256 x 2 run takes minutes: written only when named
+    # (python tests/golden/make_golden.py fibres256x2)
+    if sys.argv[1:] == ["fibres256x2"]:
+        with open(os.path.join(HERE, "oracle_fibres256x2.json"), "w") as f:
+            json.dump(fibres256x2(), f, indent=1)
+        print("wrote oracle_fibres256x2", flush=True)
+        sys.exit(0)
     for name, fn in (("oracle_laminate16", laminate16), ("oracle_lce16", lce16),
                      ("oracle_wavy32", wavy32)):
         rec = fn()

@@ -34,13 +34,15 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(admm.Material) == 40 + 4 * 8
     assert ctypes.sizeof(admm.Rve) == 16 + 7 * 8 + 72
-    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4 + 8 + 2 * 4 + 8 + 8
+    assert ctypes.sizeof(admm.Params) == 10 * 8 + 6 * 4 + 8 + 2 * 4 + 8 + 8 + 8 + 2 * 4
 
 
 @pytest.mark.parametrize("n,ok", [((16, 16, 16), True), ((256, 256, 256), True),
                                   ((48, 96, 32), True), ((6, 12, 18), True),
                                   ((4, 4, 4), True), ((2, 4, 4), False), ((512, 8, 8), False),
-                                  ((10, 8, 8), False), ((15, 8, 8), False), ((8, 8, 1), False)])
+                                  ((10, 8, 8), False), ((15, 8, 8), False), ((8, 8, 1), True),
+                                  ((64, 48, 1), True), ((8, 1, 8), False), ((1, 8, 8), False),
+                                  ((8, 8, 3), False)])
 def test_check_grid(n, ok):
     rc = admm.admm_check_grid(*n)
     assert (rc == admm.OK) == ok
@@ -66,7 +68,7 @@ def test_workspace_bytes():
     b64 = admm.admm_workspace_bytes([_rve((n1, n2, n3))], admm.FP64)
     b32 = admm.admm_workspace_bytes([_rve((n1, n2, n3))], admm.FP32_FP64RED)
     assert b64 >= 3 * S * 16 and b64 % 256 == 0
-    assert b32 >= 3 * S * 8 and b32 < b64
+    assert b32 >= 3 * S * 8 + 3 * n1 * n2 * n3 * 4 and b32 % 256 == 0
     two = admm.admm_workspace_bytes([_rve((n1, n2, n3)), _rve((32, 32, 32))], admm.FP64)
     assert two > b64
     assert admm.admm_workspace_bytes([_rve((10, 8, 8))], admm.FP64) == 0
@@ -76,11 +78,14 @@ def test_workspace_bytes():
 def test_workspace_holds_padded_half_spectra(n):
     # three half-spectrum components whose rows of n1/2 + 1 entries are
     # padded to 32 bytes (2 complex128 or 4 complex64), 256-byte aligned
+    # (float form: then the 3V floats of Step 2's correction, 256-aligned)
     n1, n2, n3 = n
     m1 = n1 // 2 + 1
     for prec, csz, q in ((admm.FP64, 16, 2), (admm.FP32_FP64RED, 8, 4)):
         m1s = -(-m1 // q) * q
         want = -(-(3 * n3 * n2 * m1s * csz) // 256) * 256
+        if prec == admm.FP32_FP64RED:
+            want += -(-(3 * n1 * n2 * n3 * 4) // 256) * 256
         assert admm.admm_workspace_bytes([_rve(n)], prec) == want
 
 
@@ -107,6 +112,8 @@ def test_init_rejects_invalid_arguments_before_touching_the_gpu():
     assert _init(good, m, admm.default_params(local_fraction=-0.5)) == admm.EINVAL
     assert _init(good, m, admm.default_params(local_fraction=0.5, local_chunk=0)) == admm.EINVAL
     assert _init(good, m, admm.default_params(local_ratio=0.3, local_fraction=0.5)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(div_growth=-1.0)) == admm.EINVAL
+    assert _init(good, m, admm.default_params(stall_iters=-1)) == admm.EINVAL
     assert _init(good, [admm.material(mu=-1.0)], p) == admm.EINVAL
     # an LCE phase needs a director field
     assert _init(good, [admm.material("lce", mu=1.0, a=2.0, kappa=1.0)], p) == admm.EINVAL
@@ -138,5 +145,5 @@ def test_init_rejects_invalid_arguments_before_touching_the_gpu():
 
 
 def test_strerror():
-    for code in (0, 1, -1, -2, -3, -4, -5, -7):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert isinstance(admm.admm_strerror(code), str) and admm.admm_strerror(code)

@@ -449,3 +449,41 @@ def test_composed_parity_case_is_far_from_ties():
                    director0=d0)
         out.append(F)
     assert np.array_equal(out[1], out[0]) and np.array_equal(out[2], out[0])
+
+
+def test_resume_is_bitwise():
+    """Algorithm 1 carries (u, F, Lambda, the director, rho) from one
+    iteration to the next: a run of 7 iterations continued from its output
+    state for 5 more equals a run of 12 bit for bit (adaptive penalty, LCE
+    director), and the ratio strategy of the inexact step continues with its
+    iteration index and previous r_d."""
+    shape = (8, 6, 4)
+    g, dirs = M.voronoi_grains(n=8, n_grains=3, seed=5)
+    phase = np.zeros(shape, np.uint8)
+    phase[:, :, :3] = 1
+    d0 = M.director_field(g, dirs)[:, :8, :6, :4]
+    d0 = np.ascontiguousarray(d0)
+    mats = [O.material("lce", mu=1.0, a=2.0, kappa=20.0), O.material("neohooke", mu=5.0, lam=20.0)]
+    Fbar = np.diag([1.1, 1.1 ** -0.5, 1.1 ** -0.5]).ravel()
+    newton = O.newton_opts(gtol=1e-14, step_tol=1e-10)
+    for loc in ({}, dict(local_ratio=0.3, local_chunk=1, local_passes=3)):
+        mk = dict(fixed_iters=True, mu_ref=1.0, newton=newton, adapt_rho=True, rho_min=1.0,
+                  rho_max=100.0, **loc)
+        u, F, L = O.initial_state(shape)
+        d = d0.copy()
+        whole = O.admm_run(phase, mats, Fbar, O.params(max_iter=12, **mk), u, F, L, 3.0,
+                           director_field=d)
+        u2, F2, L2 = O.initial_state(shape)
+        d2 = d0.copy()
+        first = O.admm_run(phase, mats, Fbar, O.params(max_iter=7, **mk), u2, F2, L2, 3.0,
+                           director_field=d2)
+        more = dict(mk)
+        if loc:
+            more.update(local_start_iter=7, local_rd_prev=first["r_d"][-1])
+        second = O.admm_run(phase, mats, Fbar, O.params(max_iter=5, **more), u2, F2, L2,
+                            first["rho"], director_field=d2)
+        for a, b in ((u, u2), (F, F2), (L, L2), (d, d2)):
+            assert np.array_equal(a, b), loc
+        assert whole["rho"] == second["rho"]
+        assert np.array_equal(whole["r_p"], np.concatenate([first["r_p"], second["r_p"]]))
+        assert np.array_equal(whole["r_d"], np.concatenate([first["r_d"], second["r_d"]]))
