@@ -620,6 +620,190 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
   return OR_NOT_CONVERGED;
 }
 
+/* Ideal LCE (no site terms): with the director eliminated the energy depends
+   on F only through its singular values f1 >= f2 >= f3 > 0 (the director is
+   the top left singular vector, |F^T n|^2 = f1^2):
+       W_r(f) = mu a^(1/3)/2 (f1^2 + f2^2 + f3^2 + (1/a - 1) f1^2) - 3 mu/2
+                + kappa/2 (f1 f2 f3 - 1)^2.
+   For an energy of the singular values alone the local problem shares A's
+   singular vectors. Write A = sum_i a_i u_i v_i^T with {u_i}, {v_i}
+   right-handed orthonormal, a1 >= a2 >= |a3| and a3 of the sign of det A.
+   For every F with det F > 0, tr(F^T A) <= sum_i f_i a_i (von Neumann's trace
+   inequality in its form for proper rotations), with equality at
+   F = sum_i f_i u_i v_i^T; |F|^2 and W_r depend on f alone. Hence
+       min_F W_r(F) + rho/2 |F - A|^2 = min_f W_r(f) + rho/2 |f - a|^2,
+   a problem in three unknowns whose minimiser is ordered like a (exchanging
+   two unordered entries lowers both the coupling to a and, for the first
+   entry, the director term). The singular basis comes from the eigenvectors
+   of A A^T; where the top singular value is tied, u1 follows the previous
+   director as in director_eig (every such u1 gives a minimiser). Newton's
+   method on the three unknowns with the same stopping rules and the same
+   backtracking as newton_relaxed; the 9-component gradient at
+   F = sum f_i u_i v_i^T is sum_i (dh/df_i) u_i v_i^T, so its norm is that of
+   the 3-component gradient and the gradient test means the same. The start
+   is the current F's diagonal in the singular basis, or a (with entries
+   below a1/16 raised to a1/16) where that has the lower objective. */
+static double spec_h(double mua, double beta, double mu, double kap, double rho,
+                     const double *f, const double *a) {
+  double J = f[0] * f[1] * f[2];
+  if (!(J > 0.0)) return INFINITY;
+  double s = 0.0, d = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    s += f[i] * f[i];
+    d += (f[i] - a[i]) * (f[i] - a[i]);
+  }
+  return 0.5 * mua * (s + beta * f[0] * f[0]) - 1.5 * mu + 0.5 * kap * (J - 1.0) * (J - 1.0) +
+         0.5 * rho * d;
+}
+
+static void spec_grad(double mua, double beta, double kap, double rho, const double *f,
+                      const double *a, double *g) {
+  double J = f[0] * f[1] * f[2];
+  double p[3] = {f[1] * f[2], f[0] * f[2], f[0] * f[1]};
+  for (int i = 0; i < 3; ++i) g[i] = mua * f[i] + rho * (f[i] - a[i]) + kap * (J - 1.0) * p[i];
+  g[0] += mua * beta * f[0];
+}
+
+static int prox_spectral(const or_material *m, double rho, const double A[9],
+                         const or_newton *opt, double F[9], double n[3], int *it) {
+  const double mua = m->mu * cbrt(m->a), beta = 1.0 / m->a - 1.0, kap = m->kappa;
+  double w[3], V[9], u[3][3], v[3][3], a[3];
+  director_eig(NULL, NULL, A, n, u[0], w, V);
+  /* u2: the eigenvector (of the top two) least aligned with u1, made
+     orthogonal to it; u3 = u1 x u2 */
+  double r[2][3], rn[2];
+  for (int e = 0; e < 2; ++e) {
+    double c = V[e] * u[0][0] + V[3 + e] * u[0][1] + V[6 + e] * u[0][2];
+    for (int k = 0; k < 3; ++k) r[e][k] = V[3 * k + e] - c * u[0][k];
+    rn[e] = r[e][0] * r[e][0] + r[e][1] * r[e][1] + r[e][2] * r[e][2];
+  }
+  int e2 = rn[0] > rn[1] ? 0 : 1;
+  for (int k = 0; k < 3; ++k) u[1][k] = r[e2][k] / sqrt(rn[e2]);
+  u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+  u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+  u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+  /* v_i = A^T u_i / a_i for i = 1, 2 (orthogonalised); v3 = v1 x v2 and
+     a3 = u3 . A v3, signed */
+  for (int i = 0; i < 2; ++i) {
+    for (int J = 0; J < 3; ++J) v[i][J] = A[J] * u[i][0] + A[3 + J] * u[i][1] + A[6 + J] * u[i][2];
+    if (i == 1) {
+      double c = v[1][0] * v[0][0] + v[1][1] * v[0][1] + v[1][2] * v[0][2];
+      for (int J = 0; J < 3; ++J) v[1][J] -= c * v[0][J];
+    }
+    a[i] = sqrt(v[i][0] * v[i][0] + v[i][1] * v[i][1] + v[i][2] * v[i][2]);
+    if (!(a[i] > 0.0)) {
+      *it = 0;
+      return OR_EDOMAIN;
+    }
+    for (int J = 0; J < 3; ++J) v[i][J] /= a[i];
+  }
+  v[2][0] = v[0][1] * v[1][2] - v[0][2] * v[1][1];
+  v[2][1] = v[0][2] * v[1][0] - v[0][0] * v[1][2];
+  v[2][2] = v[0][0] * v[1][1] - v[0][1] * v[1][0];
+  a[2] = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int J = 0; J < 3; ++J) a[2] += u[2][i] * A[3 * i + J] * v[2][J];
+  /* start */
+  double f[3], fa[3];
+  for (int i = 0; i < 3; ++i) {
+    f[i] = 0.0;
+    for (int k = 0; k < 3; ++k)
+      for (int J = 0; J < 3; ++J) f[i] += u[i][k] * F[3 * k + J] * v[i][J];
+    fa[i] = a[i] > a[0] / 16.0 ? a[i] : a[0] / 16.0;
+  }
+  if (!(spec_h(mua, beta, m->mu, kap, rho, f, a) <= spec_h(mua, beta, m->mu, kap, rho, fa, a)))
+    memcpy(f, fa, sizeof(f));
+  const double scale_mod = moduli_sum(m) + rho;
+  const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  int rc = OR_NOT_CONVERGED, iter;
+  for (iter = 0; iter < opt->max_iter; ++iter) {
+    double g[3];
+    spec_grad(mua, beta, kap, rho, f, a, g);
+    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (gn <= opt->gtol * scale_mod * (1.0 + nf + na)) {
+      rc = OR_OK;
+      break;
+    }
+    /* Hessian of h, plus the smallest tau of 0, rho/16, rho/8, ... that
+       makes it positive definite */
+    double J = f[0] * f[1] * f[2], p[3] = {f[1] * f[2], f[0] * f[2], f[0] * f[1]};
+    double H[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        H[3 * i + j] = kap * p[i] * p[j] + (i == j ? mua + rho : kap * (J - 1.0) * f[3 - i - j]);
+    H[0] += mua * beta;
+    double L[9], tau = 0.0;
+    int pd = 0;
+    for (int tries = 0; tries < 64 && !pd; ++tries) {
+      memcpy(L, H, sizeof(L));
+      for (int i = 0; i < 3; ++i) L[4 * i] += tau;
+      pd = 1;
+      for (int j = 0; j < 3 && pd; ++j) {
+        double d = L[4 * j];
+        for (int k = 0; k < j; ++k) d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 0.0)) pd = 0;
+        else {
+          L[4 * j] = sqrt(d);
+          for (int i = j + 1; i < 3; ++i) {
+            double x = L[3 * i + j];
+            for (int k = 0; k < j; ++k) x -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = x / L[4 * j];
+          }
+        }
+      }
+      if (!pd) tau = tau == 0.0 ? rho / 16.0 : 2.0 * tau;
+    }
+    if (!pd) break;
+    double y[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+      double x = -g[i];
+      for (int k = 0; k < i; ++k) x -= L[3 * i + k] * y[k];
+      y[i] = x / L[4 * i];
+    }
+    for (int i = 2; i >= 0; --i) {
+      double x = y[i];
+      for (int k = i + 1; k < 3; ++k) x -= L[3 * k + i] * d[k];
+      d[i] = x / L[4 * i];
+    }
+    double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
+    int small = -slope <= 1e-12 * scale_mod * (1.0 + nf * nf);
+    double h0 = spec_h(mua, beta, m->mu, kap, rho, f, a), t = 1.0, ft[3];
+    int acc = 0;
+    for (int ls = 0; ls < 60 && !acc; ++ls) {
+      for (int i = 0; i < 3; ++i) ft[i] = f[i] + t * d[i];
+      if (ft[0] * ft[1] * ft[2] > 0.0) {
+        if (!small) {
+          acc = spec_h(mua, beta, m->mu, kap, rho, ft, a) <= h0 + 1e-4 * t * slope;
+        } else {
+          double gt[3];
+          spec_grad(mua, beta, kap, rho, ft, a, gt);
+          acc = sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]) <= (1.0 - 1e-4 * t) * gn;
+        }
+      }
+      if (!acc) t *= 0.5;
+    }
+    if (!acc) {
+      ++iter;
+      break;
+    }
+    memcpy(f, ft, sizeof(f));
+    double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (t == 1.0 && nd <= opt->step_tol * (nf > 1.0 ? nf : 1.0)) {
+      ++iter;
+      rc = OR_OK;
+      break;
+    }
+  }
+  *it = iter;
+  for (int k = 0; k < 3; ++k)
+    for (int J = 0; J < 3; ++J)
+      F[3 * k + J] = f[0] * u[0][k] * v[0][J] + f[1] * u[1][k] * v[1][J] + f[2] * u[2][k] * v[2][J];
+  for (int k = 0; k < 3; ++k) n[k] = u[0][k];
+  return rc;
+}
+
 int or_prox(const or_material *m, double rho, const double A[9], const or_site *site,
             const or_newton *opt, double F[9], double n[3], int *iters) {
   if (!m || !A || !opt || !F || !(rho > 0.0)) return OR_EINVAL;
@@ -628,7 +812,10 @@ int or_prox(const or_material *m, double rho, const double A[9], const or_site *
     rc = newton_fixed_n(m, rho, A, opt, F, n, NULL, &it);
   } else {
     if (!n || !lce_site_ok(m, site)) return OR_EINVAL;
-    rc = newton_relaxed(m, rho, A, opt, F, n, site, &it);
+    if (!site)
+      rc = prox_spectral(m, rho, A, opt, F, n, &it);
+    else
+      rc = newton_relaxed(m, rho, A, opt, F, n, site, &it);
   }
   if (iters) *iters = it;
   return rc;

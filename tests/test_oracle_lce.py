@@ -17,6 +17,10 @@ solver or its formula for the eigenvector sensitivity:
 - the joint prox is stationary, beats joint perturbations of F and n, and
   equals an independent minimisation of W_r(F) + rho/2 |F - A|^2 by scipy's
   BFGS with W_r from numpy.
+The oracle solves the ideal model (no site terms) in the singular basis of
+A (three unknowns) and every other LCE form by Newton's method on the nine
+components of F; both paths are held to the pins above, and the two paths
+agree on the ideal model where a zero site sends it down the second.
 """
 import numpy as np
 import pytest
@@ -99,8 +103,9 @@ def phi_np(F, A, rho):
     return W_relaxed_np(F) + 0.5 * rho * np.sum((F - A) ** 2)
 
 
+@pytest.mark.parametrize("path", ["spectral", "newton"])
 @pytest.mark.parametrize("case", ["stretch", "random", "rotated"])
-def test_joint_prox_is_the_minimiser(case):
+def test_joint_prox_is_the_minimiser(case, path):
     rho = 10.0
     if case == "stretch":
         A = np.diag([1.25, 0.9, 0.9]) + 0.02 * np.random.default_rng(1).standard_normal((3, 3))
@@ -111,7 +116,7 @@ def test_joint_prox_is_the_minimiser(case):
     else:
         A = rot(5) @ np.diag([1.3, 0.88, 0.88]) @ rot(6)
         F0, n0 = A.ravel() + 0.01, unit(7)
-    F, n, it, rc = O.prox(LCE, rho, A.ravel(), F0, n0)
+    F, n, it, rc = O.prox(LCE, rho, A.ravel(), F0, n0, **PATHS[path])
     assert rc == O.OK and it <= 25, (rc, it)
     # stationary, with the director the top eigenvector of F F^T
     g = O.stress(LCE, F, n) + rho * (F - A.ravel())
@@ -183,15 +188,21 @@ NONCONVEX = [(1.0, 0.0, 10.0), (1.02, 0.005, 10.0), (1.001, 0.005, 10.0), (1.0, 
              (1.02, 0.0, 30.0), (1.0, 0.003, 30.0)]
 
 
+# the ideal model's two solvers: the singular-basis one (no site) and the
+# nine-component Newton solve (a zero site gives the same energy)
+PATHS = {"spectral": {}, "newton": {"Sc": np.zeros(9)}}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("k", range(len(NONCONVEX)))
-def test_joint_prox_is_a_local_minimiser_where_not_convex(k):
+def test_joint_prox_is_a_local_minimiser_where_not_convex(k, path):
     s, noise, rho = NONCONVEX[k]
     rng = np.random.default_rng(100 + k)
     A = (np.diag([s, s ** -0.5, s ** -0.5]) + noise * rng.standard_normal((3, 3))).ravel()
     n0 = rng.standard_normal(3)
     n0 /= np.linalg.norm(n0)
     F0 = np.eye(3).ravel()
-    F, n, it, rc = O.prox(LCE, rho, A, F0, n0)
+    F, n, it, rc = O.prox(LCE, rho, A, F0, n0, **PATHS[path])
     assert rc == O.OK and it <= 20, (rc, it)
     # jointly stationary: the fixed-director gradient vanishes at the top
     # eigenvector of F F^T (numpy's)
@@ -236,3 +247,65 @@ def test_nonconvex_cases_exercise_the_hessian_modification():
         low += ev[0] < rho / 16
         neg += ev[0] < 0
     assert low >= len(NONCONVEX) // 2 and neg >= 1, (low, neg)
+
+
+def test_spectral_and_newton_paths_agree():
+    """The ideal model through its two solvers, from F = I and a random
+    director, on data from mild to strong distortion and three penalties:
+    the same F and the same director (up to sign) wherever the Newton solve
+    converges, and the singular-basis solve converges everywhere in fewer
+    iterations. The Newton solve stops at |g| <= gtol * scale, so on weakly
+    curved problems (rho = 1) the two differ by that residual over the
+    smallest curvature, hence the tolerance."""
+    rng = np.random.default_rng(3)
+    opts = O.newton_opts(gtol=1e-14, step_tol=1e-10)
+    its_s = its_n = 0
+    for k in range(90):
+        amp = (0.02, 0.1, 0.3)[k % 3]
+        rho = (1.0, 10.0, 30.0)[(k // 3) % 3]
+        A = (np.eye(3) + rng.uniform(-amp, amp, (3, 3))).ravel()
+        n0 = rng.standard_normal(3)
+        n0 /= np.linalg.norm(n0)
+        Fs, ns, it_s, rc_s = O.prox(LCE, rho, A, np.eye(3).ravel(), n0, opts)
+        Fn, nn, it_n, rc_n = O.prox(LCE, rho, A, np.eye(3).ravel(), n0, opts, Sc=np.zeros(9))
+        assert rc_s == O.OK, k
+        g = O.stress(LCE, Fs, ns) + rho * (Fs - A)
+        assert np.linalg.norm(g) <= 1e-10, k
+        its_s += it_s
+        if rc_n != O.OK:
+            continue
+        its_n += it_n
+        assert np.max(np.abs(Fs - Fn)) <= (1e-9 if rho == 1.0 else 1e-10), k
+        assert abs(abs(ns @ nn) - 1.0) <= 1e-10, k
+    assert its_s < its_n
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_spectral_prox_is_coaxial_with_the_data(k):
+    """F shares A's singular vectors: F A^T and A^T F are symmetric, and the
+    director is A's top left singular vector (numpy's SVD)."""
+    rng = np.random.default_rng(40 + k)
+    A = rot(k) @ np.diag([1.25, 1.0, 0.85]) @ rot(k + 10) + 0.05 * rng.standard_normal((3, 3))
+    F, n, _, rc = O.prox(LCE, 10.0, A.ravel(), np.eye(3).ravel(), unit(k))
+    assert rc == O.OK
+    F = F.reshape(3, 3)
+    for M in (F @ A.T, A.T @ F):
+        assert np.max(np.abs(M - M.T)) <= 1e-12
+    U, _, _ = np.linalg.svd(A)
+    assert abs(abs(U[:, 0] @ n) - 1.0) <= 1e-12
+
+
+def test_spectral_prox_at_tied_data_follows_the_previous_director():
+    """A = c I: every direction is a minimiser's director; the solve keeps
+    the previous one and returns the uniaxial stretch along it,
+    F = f_perp I + (f_par - f_perp) n n^T with f_par > f_perp."""
+    for k in range(3):
+        n0 = unit(k + 30)
+        F, n, _, rc = O.prox(LCE, 10.0, (1.02 * np.eye(3)).ravel(), np.eye(3).ravel(), n0)
+        assert rc == O.OK
+        assert np.max(np.abs(n - n0)) <= 1e-14
+        F = F.reshape(3, 3)
+        f_par = n0 @ F @ n0
+        f_perp = (np.trace(F) - f_par) / 2
+        assert f_par > f_perp + 0.05
+        assert np.max(np.abs(F - (f_perp * np.eye(3) + (f_par - f_perp) * np.outer(n0, n0)))) <= 1e-13
