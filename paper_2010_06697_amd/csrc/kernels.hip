@@ -286,7 +286,14 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
           }
           fp = &form;
         }
-        rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its, fp);
+        if (fp) {
+          rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its, fp);
+        } else {
+          // the ideal model: the local problem in A's singular basis
+          rc = lce_spectral<T>(E, At, m.mua, m.beta, m.kappa, m.mu, rho, n, cap, ip.gtol,
+                               ip.step_tol);
+          n_its += rc >= 0 ? rc : cap;
+        }
         dg[idx] = (T)n[0];
         dg[V + idx] = (T)n[1];
         dg[2 * V + idx] = (T)n[2];

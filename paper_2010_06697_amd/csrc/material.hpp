@@ -826,4 +826,217 @@ __device__ int lce_newton(T *E, const T *A, Lce<T> &M, double c2, T rho, double 
   return ret;
 }
 
+// ---------------------------------------------------------------------------
+// Ideal LCE (no non-ideality, Frank or director-dissipation term): with the
+// director eliminated the energy is a function of the singular values
+// f1 >= f2 >= f3 > 0 of F alone (the director is the top left singular
+// vector), W_r = mua/2 (|f|^2 + beta f1^2) - 3 mu/2 + kappa/2 (f1 f2 f3 - 1)^2,
+// mua = mu a^(1/3), beta = 1/a - 1. The minimiser of W_r(F) + rho/2 |F - A|^2
+// then has A's singular vectors (von Neumann's trace inequality over proper
+// rotations: tr(F^T A) <= sum f_i a_i when det F > 0, a3 carrying the sign of
+// det A), and Step 1 reduces to the three unknowns f:
+//     h(f) = W_r(f) + rho/2 |f - a|^2,
+// minimised by Newton's method (Hessian shifted by the smallest of 0, rho/16,
+// rho/8, ... that makes it positive definite; Armijo backtracking on h, or on
+// |grad h| once the predicted decrease is below rounding). At
+// F = sum f_i u_i v_i^T the 9-component gradient is sum_i (dh/df_i) u_i v_i^T,
+// so the stopping test on |grad h| is the nine-component one. Everything in
+// double, whatever T. The basis: eigenvectors of A A^T (director_eig, which
+// resolves a tied top singular value towards the previous director), u2 the
+// one of the top two eigenvectors least aligned with u1, made orthogonal to
+// it, u3 = u1 x u2; v_i = A^T u_i / a_i (i = 1, 2), v3 = v1 x v2,
+// a3 = u3 . A v3. The start is the current F's diagonal in that basis, or a
+// with entries below a1/16 raised to it, whichever has the lower h.
+// E: F - I in/out; Am: A - I; n: previous director in, new one out.
+// Returns the Newton iterations, -1 when not converged, -2 for rank(A) < 2.
+// ---------------------------------------------------------------------------
+struct SpecH {
+  double mua, beta, kap, rho, c0;  // c0 = -3 mu / 2
+  double a[3];
+  __device__ __forceinline__ double h(const double *f) const {
+    const double J = f[0] * f[1] * f[2];
+    if (!(J > 0.0)) return __builtin_huge_val();
+    double s = 0.0, d = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      s += f[i] * f[i];
+      d += (f[i] - a[i]) * (f[i] - a[i]);
+    }
+    return 0.5 * mua * (s + beta * f[0] * f[0]) + c0 + 0.5 * kap * (J - 1.0) * (J - 1.0) +
+           0.5 * rho * d;
+  }
+  __device__ __forceinline__ void grad(const double *f, double *g) const {
+    const double Jm1 = f[0] * f[1] * f[2] - 1.0;
+    g[0] = mua * (1.0 + beta) * f[0] + rho * (f[0] - a[0]) + kap * Jm1 * (f[1] * f[2]);
+    g[1] = mua * f[1] + rho * (f[1] - a[1]) + kap * Jm1 * (f[0] * f[2]);
+    g[2] = mua * f[2] + rho * (f[2] - a[2]) + kap * Jm1 * (f[0] * f[1]);
+  }
+};
+
+template <typename T>
+__device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double kap, double mu,
+                            double rho, double *n, int maxit, double gtol, double step_tol) {
+  double w[3], Ve[9], u[9], v[9];  // u, v: singular vectors in rows (u[3i + k])
+  director_eig(Am, n, u, w, Ve);
+  double Ad[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ad[k] = (double)Am[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+  {
+    double r0[3], r1[3];
+    const double c0 = Ve[0] * u[0] + Ve[3] * u[1] + Ve[6] * u[2];
+    const double c1 = Ve[1] * u[0] + Ve[4] * u[1] + Ve[7] * u[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r0[k] = Ve[3 * k] - c0 * u[k];
+      r1[k] = Ve[3 * k + 1] - c1 * u[k];
+    }
+    const double q0 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+    const double q1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
+    const bool use0 = q0 > q1;
+    const double inv = 1.0 / sqrt(use0 ? q0 : q1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[3 + k] = (use0 ? r0[k] : r1[k]) * inv;
+  }
+  u[6] = u[1] * u[5] - u[2] * u[4];
+  u[7] = u[2] * u[3] - u[0] * u[5];
+  u[8] = u[0] * u[4] - u[1] * u[3];
+  SpecH H;
+  H.mua = mua;
+  H.beta = beta;
+  H.kap = kap;
+  H.rho = rho;
+  H.c0 = -1.5 * mu;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      v[3 * i + J] = Ad[J] * u[3 * i] + Ad[3 + J] * u[3 * i + 1] + Ad[6 + J] * u[3 * i + 2];
+    if (i == 1) {
+      const double c = v[3] * v[0] + v[4] * v[1] + v[5] * v[2];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) v[3 + J] -= c * v[J];
+    }
+    const double ai = sqrt(v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
+                           v[3 * i + 2] * v[3 * i + 2]);
+    if (!(ai > 0.0)) return -2;
+    H.a[i] = ai;
+    const double inv = 1.0 / ai;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) v[3 * i + J] *= inv;
+  }
+  v[6] = v[1] * v[5] - v[2] * v[4];
+  v[7] = v[2] * v[3] - v[0] * v[5];
+  v[8] = v[0] * v[4] - v[1] * v[3];
+  {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) s += u[6 + i] * Ad[3 * i + J] * v[6 + J];
+    H.a[2] = s;
+  }
+  // start
+  double f[3], fa[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int J = 0; J < 3; ++J)
+        s += u[3 * i + k] * ((double)E[3 * k + J] + (k == J ? 1.0 : 0.0)) * v[3 * i + J];
+    f[i] = s;
+    fa[i] = fmax(H.a[i], H.a[0] * 0.0625);
+  }
+  if (!(H.h(f) <= H.h(fa))) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = fa[i];
+  }
+  const double smod = mua + kap + rho;
+  const double na = sqrt(H.a[0] * H.a[0] + H.a[1] * H.a[1] + H.a[2] * H.a[2]);
+  int ret = -1;
+  for (int it = 0; it < maxit; ++it) {
+    double g[3];
+    H.grad(f, g);
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (gn <= gtol * smod * (1.0 + nf + na)) {
+      ret = it;
+      break;
+    }
+    const double Jm1 = f[0] * f[1] * f[2] - 1.0;
+    const double p0 = f[1] * f[2], p1 = f[0] * f[2], p2 = f[0] * f[1];
+    const double d00 = mua * (1.0 + beta) + rho + kap * p0 * p0;
+    const double d11 = mua + rho + kap * p1 * p1, d22 = mua + rho + kap * p2 * p2;
+    const double o10 = kap * (p1 * p0 + Jm1 * f[2]);
+    const double o20 = kap * (p2 * p0 + Jm1 * f[1]);
+    const double o21 = kap * (p2 * p1 + Jm1 * f[0]);
+    double tau = 0.0, l00 = 0.0, l10 = 0.0, l20 = 0.0, l11 = 0.0, l21 = 0.0, l22 = 0.0;
+    bool pd = false;
+    for (int tries = 0; tries < 64 && !pd; ++tries) {
+      const double e0 = d00 + tau;
+      pd = e0 > 0.0;
+      if (pd) {
+        l00 = sqrt(e0);
+        l10 = o10 / l00;
+        l20 = o20 / l00;
+        const double e1 = d11 + tau - l10 * l10;
+        pd = e1 > 0.0;
+        if (pd) {
+          l11 = sqrt(e1);
+          l21 = (o21 - l20 * l10) / l11;
+          const double e2 = d22 + tau - l20 * l20 - l21 * l21;
+          pd = e2 > 0.0;
+          if (pd) l22 = sqrt(e2);
+        }
+      }
+      if (!pd) tau = tau == 0.0 ? 0.0625 * rho : 2.0 * tau;
+    }
+    if (!pd) break;
+    const double y0 = -g[0] / l00, y1 = (-g[1] - l10 * y0) / l11;
+    const double y2 = (-g[2] - l20 * y0 - l21 * y1) / l22;
+    double d[3];
+    d[2] = y2 / l22;
+    d[1] = (y1 - l21 * d[2]) / l11;
+    d[0] = (y0 - l10 * d[1] - l20 * d[2]) / l00;
+    const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
+    const bool small = -slope <= 1e-12 * smod * (1.0 + nf * nf);
+    const double h0 = small ? 0.0 : H.h(f);
+    double t = 1.0, ft[3];
+    bool acc = false;
+    for (int ls = 0; ls < 60 && !acc; ++ls) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ft[i] = f[i] + t * d[i];
+      if (ft[0] * ft[1] * ft[2] > 0.0) {
+        if (!small) {
+          acc = H.h(ft) <= h0 + 1e-4 * t * slope;
+        } else {
+          double gt[3];
+          H.grad(ft, gt);
+          acc = sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]) <= (1.0 - 1e-4 * t) * gn;
+        }
+      }
+      if (!acc) t *= 0.5;
+    }
+    if (!acc) break;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = ft[i];
+    const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (t == 1.0 && nd <= step_tol * fmax(nf, 1.0)) {
+      ret = it + 1;
+      break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      E[3 * k + J] = (T)(f[0] * u[k] * v[J] + f[1] * u[3 + k] * v[3 + J] +
+                         f[2] * u[6 + k] * v[6 + J] - (k == J ? 1.0 : 0.0));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = u[k];
+  return ret;
+}
+
 }  // namespace admm
