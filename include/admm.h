@@ -352,7 +352,8 @@ int admm_profile_read(admm_ctx *ctx, int32_t kernel, double *total_ms, int32_t *
  * a vendor FFT; here the transforms are the library's own, and these are
  * their free parameters). */
 typedef struct {
-  int32_t tile_y, tile_z;   /* columns per workgroup of the x2 / x3 passes */
+  int32_t tile_y, tile_z;   /* columns per workgroup of the x2 / x3 passes,
+                               or ADMM_TILE_REG16 (below) */
   int32_t n_len;            /* distinct edge lengths of the context's cells */
   int32_t x_points;         /* points per workgroup of the x1 transforms
                                (256, 512 or 1024; lines = points / n1) */
@@ -363,11 +364,18 @@ typedef struct {
   double ms_tuned;          /* and after tuning */
 } admm_tuning;
 
+/* Tile width of the register-resident x2 / x3 pass of length 256: a
+ * workgroup takes 16 columns, each thread 16 points of one column; a
+ * transform is a length-16 DFT in registers, a twiddle, one exchange
+ * through LDS and a second length-16 DFT (256 = 16 x 16, Cooley-Tukey). */
+#define ADMM_TILE_REG16 (-16)
+
 /* Autotuner (a performance control with no counterpart in the method): times
  * Step 2 over all cells on the context's stream, `reps` calls per candidate
  * (best of three), and keeps the fastest number of points per workgroup of
  * the x1 transforms, then the fastest tile width of the x2 pass, then of
- * the x3 pass (a quarter, half, default or double width, LDS <= 64 KiB), then the
+ * the x3 pass (a quarter, half, default or double width, LDS <= 64 KiB, or
+ * ADMM_TILE_REG16 where every cell's length along that axis is 256), then the
  * fastest radix sequence of each transform length in turn (every order of
  * the radix-8/4/2/3 splits, at most 24 per length). Results change only by
  * rounding (the transforms' operation order). Step 2 writes each cell's
@@ -385,7 +393,8 @@ int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out);
 
 /* Applies a Step 2 launch configuration (a tuning admm_autotune reported,
  * or any other): tile widths of the x2 / x3 passes (compiled widths, LDS
- * <= 64 KiB), points per workgroup of the x1 transforms (256, 512, 1024)
+ * <= 64 KiB, or ADMM_TILE_REG16 where every cell's length along that axis
+ * is 256), points per workgroup of the x1 transforms (256, 512, 1024)
  * and, for each of the n_len lengths listed, its radix sequence (2, 3, 4,
  * 8, product equal to the length; lengths the context does not have are
  * refused). ms_default / ms_tuned are ignored. ADMM_EINVAL, with nothing

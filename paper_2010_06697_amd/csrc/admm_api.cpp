@@ -366,16 +366,37 @@ void drop_graphs(admm_ctx *c) {
   }
 }
 
+// the register-resident x2 / x3 pass (k_col16, tile width kTileCol16) is
+// open to an axis when every cell's length along it is 256
+bool col16_ok(const admm_ctx *c, int axis) {
+  for (const RveDesc &D : c->desc_h)
+    if ((axis == 2 ? D.n2 : D.n3) != 256) return false;
+  return true;
+}
+
+// a tile width of the x2 (axis 2) or x3 (axis 3) pass: a compiled width
+// within 64 KiB of LDS, or kTileCol16 where every cell's length is 256
+bool tile_ok(const admm_ctx *c, int axis, int B) {
+  if (B == kTileCol16) return col16_ok(c, axis);
+  const size_t csz = c->fp64 ? sizeof(double2) : sizeof(float2);
+  const int nmax = axis == 2 ? c->L.n2max : c->L.n3max;
+  return tile_compiled(c->fp64, B) && 2 * (size_t)nmax * B * csz <= 65536;
+}
+
 // tile widths of the x2 / x3 passes: workgroup prefix tables (blk_h holds
-// the x, y, z, u and f tables, n_rve + 1 entries each), grid sizes, upload
+// the x, y, z, u and f tables, n_rve + 1 entries each), grid sizes, upload.
+// Under kTileCol16 an axis's workgroups take 16 columns each of the
+// flattened (x3, m1) or (m2, m1) set.
+static_assert(kTileCol16 == ADMM_TILE_REG16, "tile width of the register-resident pass");
+
 int set_tiles(admm_ctx *c, int ty, int tz) {
   const int n = c->n_rve;
   int *by = c->blk_h.data() + (n + 1), *bz = c->blk_h.data() + 2 * (n + 1);
   by[0] = bz[0] = 0;
   for (int r = 0; r < n; ++r) {
     const RveDesc &D = c->desc_h[r];
-    by[r + 1] = by[r] + D.n3 * ((D.m1 + ty - 1) / ty);
-    bz[r + 1] = bz[r] + (D.n2 * D.m1s + tz - 1) / tz;
+    by[r + 1] = by[r] + (ty == kTileCol16 ? (D.n3 * D.m1 + 15) / 16 : D.n3 * ((D.m1 + ty - 1) / ty));
+    bz[r + 1] = bz[r] + (tz == kTileCol16 ? (D.n2 * D.m1 + 15) / 16 : (D.n2 * D.m1s + tz - 1) / tz);
   }
   c->L.tile_y = ty;
   c->L.tile_z = tz;
@@ -611,12 +632,14 @@ int tune(admm_ctx *c, int reps, admm_tuning *out) {
     rc = set_xpoints(c, keep);
     if (rc != ADMM_OK) return rc;
   }
-  // tile width of the x2 pass, then of the x3 pass (LDS <= 64 KiB)
+  // tile width of the x2 pass, then of the x3 pass (LDS <= 64 KiB), and the
+  // register-resident pass where every cell's length along the axis is 256
   for (int pass = 0; pass < 2 && rc == ADMM_OK; ++pass) {
-    const int nmax = pass == 0 ? c->L.n2max : c->L.n3max;
     int keep = pass == 0 ? c->L.tile_y : c->L.tile_z;
-    for (int B : cand) {
-      if (B == keep || 2 * (size_t)nmax * B * csz > 65536) continue;
+    std::vector<int> cands(cand, cand + 4);
+    cands.push_back(kTileCol16);
+    for (int B : cands) {
+      if (B == keep || !tile_ok(c, pass == 0 ? 2 : 3, B)) continue;
       rc = pass == 0 ? set_tiles(c, B, c->L.tile_z) : set_tiles(c, c->L.tile_y, B);
       double t = 0.0;
       if (rc == ADMM_OK) rc = time_project(c, reps, &t);
@@ -1387,10 +1410,7 @@ int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out) {
 int admm_set_tuning(admm_ctx *ctx, const admm_tuning *t) {
   if (!ctx || !t) return ADMM_EINVAL;
   const size_t csz = ctx->fp64 ? sizeof(double2) : sizeof(float2);
-  if (!tile_compiled(ctx->fp64, t->tile_y) || !tile_compiled(ctx->fp64, t->tile_z) ||
-      2 * (size_t)ctx->L.n2max * t->tile_y * csz > 65536 ||
-      2 * (size_t)ctx->L.n3max * t->tile_z * csz > 65536)
-    return ADMM_EINVAL;
+  if (!tile_ok(ctx, 2, t->tile_y) || !tile_ok(ctx, 3, t->tile_z)) return ADMM_EINVAL;
   if (t->x_points != 256 && t->x_points != 512 && t->x_points != 1024) return ADMM_EINVAL;
   for (const auto &D : ctx->desc_h)
     if (2 * (size_t)((3 * rows_per_fft_block(D.n1, t->x_points) + 1) / 2) * D.n1 * csz > 65536)
@@ -1566,8 +1586,7 @@ int admm_set_state(admm_ctx *ctx, const void *blob, size_t bytes) {
   if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 ||
       h.precision != (ctx->fp64 ? ADMM_FP64 : ADMM_FP32_FP64RED) || h.n_rve != ctx->n_rve ||
       h.hist_cap != ctx->hist_cap || h.state_size != (int32_t)sizeof(RveState) ||
-      h.flags != state_flags(ctx) || !tile_compiled(ctx->fp64, h.tile_y) ||
-      !tile_compiled(ctx->fp64, h.tile_z) ||
+      h.flags != state_flags(ctx) || !tile_ok(ctx, 2, h.tile_y) || !tile_ok(ctx, 3, h.tile_z) ||
       (h.xpoints != 256 && h.xpoints != 512 && h.xpoints != 1024))
     return ADMM_EINVAL;
   // validate every cell before changing anything

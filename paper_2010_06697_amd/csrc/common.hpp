@@ -123,6 +123,10 @@ __host__ __device__ inline bool divergence_watch(double rp, double rd, double to
 }
 
 constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
+// tile width that selects the register-resident x2 / x3 pass of length 256
+// (16 columns per workgroup, 16 points per thread, one LDS exchange per
+// transform); open to an axis when every cell's length along it is 256
+constexpr int kTileCol16 = -16;
 constexpr int kLocalPassGrid = 2048;  // workgroups of the later inexact local passes
 
 struct Material {

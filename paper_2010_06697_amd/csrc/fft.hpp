@@ -80,6 +80,43 @@ template <bool INV, typename C> __device__ __forceinline__ void dft8(C *v) {
   }
 }
 
+// length-16 DFT as 4 x 4 (the register-resident x2 / x3 passes of length
+// 256): with n = n1 + 4 n2 and k = 4 k1 + k2,
+// X[4 k1 + k2] = sum_n1 w16^(n1 k2) (sum_n2 x[n1 + 4 n2] w4^(n2 k2)) w4^(n1 k1);
+// the inner length-4 transforms run on v[n1], v[n1+4], v[n1+8], v[n1+12],
+// the outer ones on the twiddled results of each k2
+template <bool INV, typename C> __device__ __forceinline__ void dft16(C *v) {
+  using T = decltype(v[0].x);
+  const T c1 = (T)0.92387953251128675613;  // cos(pi/8)
+  const T s1 = (T)0.38268343236508977173;  // sin(pi/8)
+  const T h = (T)0.70710678118654752440;   // sqrt(2)/2
+  // w16^m = (cos(2 pi m/16), -+ sin(2 pi m/16)) for the m = n1 k2 that occur
+  const T wr[10] = {(T)1, c1, h, s1, (T)0, (T)0, -h, (T)0, (T)0, -c1};
+  const T wi[10] = {(T)0, s1, h, c1, (T)1, (T)0, h, (T)0, (T)0, -s1};
+  C a[4][4];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    C q[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+    dft4<INV>(q);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      const int m = n1 * k2;
+      if (m == 0) {
+        a[k2][n1] = q[k2];
+      } else {
+        const C w = C{wr[m], INV ? wi[m] : -wi[m]};
+        a[k2][n1] = cmul(q[k2], w);
+      }
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    dft4<INV>(a[k2]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) v[4 * k1 + k2] = a[k2][k1];
+  }
+}
+
 template <int R, bool INV, typename C> __device__ __forceinline__ void dftR(C *v) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 3) dft3<INV>(v);

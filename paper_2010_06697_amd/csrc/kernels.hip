@@ -808,6 +808,96 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// x2 and x3 passes of length 256 at the tile width kTileCol16, register
+// resident: a workgroup takes 16 columns (flattened over the cell's (x3, m1)
+// for x2, (m2, m1) for x3, padding columns excluded); thread (c, j) =
+// (t % 16, t / 16) holds elements j + 16 r (r = 0..15) of column c. With
+// n = j + 16 r and k = 16 k1 + k2,
+//     X[16 k1 + k2] = sum_j w16^(j k1) w256^(j k2) sum_r x[j + 16 r] w16^(r k2):
+// a length-16 DFT over r in registers, the twiddle w256^(j k2), one exchange
+// through LDS (thread (c, j) then holds k2 = j for every j'), a length-16 DFT
+// over j'. Thread (c, j) ends with X[j + 16 k1], k1 = 0..15: the layout it
+// loaded, so results go back in place and an inverse transform can follow.
+// ----------------------------------------------------------------------------
+
+// LDS slab of one k2 (16 x 16 values) padded by 8 values in float, so that
+// the 4 rows a wave reads in the exchange fall in different banks (64 KiB
+// without padding in double)
+template <typename C> constexpr int col16_slab() { return sizeof(C) == 8 ? 264 : 256; }
+template <typename C> constexpr size_t col16_lds() { return 16 * col16_slab<C>() * sizeof(C); }
+
+template <bool INV, typename C>
+__device__ __forceinline__ void col256(C *v, C *X, const C *__restrict__ tw, int c, int j) {
+  constexpr int SL = col16_slab<C>();
+  dft16<INV>(v);
+#pragma unroll
+  for (int k2 = 1; k2 < 16; ++k2) {
+    const C w = tw[j * k2];  // j k2 <= 225
+    v[k2] = INV ? cmulc(v[k2], w) : cmul(v[k2], w);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) X[k2 * SL + j * 16 + c] = v[k2];
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) v[jj] = X[j * SL + jj * 16 + c];
+  dft16<INV>(v);
+}
+
+// MODE 0: x2 forward, 1: x2 inverse, 2: x3 forward, u_hat = b_hat/(|K|^2 V),
+// x3 inverse (blockIdx.y = component)
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_col16(KernelArgs a) {
+  using C = typename cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *X = reinterpret_cast<C *>(smem);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int *tab = MODE == 2 ? a.blk_z : a.blk_y;
+  const int r = find_rve(tab, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  if (!a.state[r].active) return;
+  const int b = blk - tab[r];
+  const int n2 = D.n2, m1 = D.m1, m1s = D.m1s;
+  const int t = threadIdx.x, c = t & 15, j = t >> 4;
+  const int ncol = (MODE == 2 ? n2 : D.n3) * m1;
+  const int g = b * 16 + c;
+  const bool ok = g < ncol;
+  const int outer = ok ? g / m1 : 0, q = ok ? g - outer * m1 : 0;
+  // x2: column (x3 = outer, m1 = q), elements m1s apart; x3: column
+  // (m2 = outer, m1 = q), elements one plane (n2 m1s) apart
+  const long long es = MODE == 2 ? (long long)n2 * m1s : (long long)m1s;
+  C *col = static_cast<C *>(D.spec) + blockIdx.y * D.S +
+           (MODE == 2 ? (long long)outer * m1s : (long long)outer * n2 * m1s) + q;
+  const C *tw = static_cast<const C *>(a.tw);
+  const C *tw256 = tw + (MODE == 2 ? D.p3.tw : D.p2.tw);
+  C v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = ok ? col[(j + 16 * k) * es] : C{(T)0, (T)0};
+  col256<MODE == 1>(v, X, tw256, c, j);
+  if (MODE == 2) {
+    // thread (c, j) holds m3 = j + 16 k1
+    const double iV = 1.0 / (double)D.V;
+    const double K1 = (double)tw[D.p1.tw + q].y;
+    const double K2 = (double)tw[D.p2.tw + outer].y;
+    const double K12 = K1 * K1 + K2 * K2;
+    const bool null12 = (q == 0 || 2 * q == D.n1) && (outer == 0 || 2 * outer == n2);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int m3 = j + 16 * k;
+      const double K3 = (double)tw256[m3].y;
+      const bool null = !ok || (null12 && (m3 == 0 || 2 * m3 == 256));
+      const T s = null ? (T)0 : (T)(iV / (K12 + K3 * K3));
+      v[k] = C{v[k].x * s, v[k].y * s};
+    }
+    __syncthreads();  // every thread has read the exchange buffer
+    col256<true>(v, X, tw256, c, j);
+  }
+  if (ok) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) col[(j + 16 * k) * es] = v[k];
+  }
+}
+
+// ----------------------------------------------------------------------------
 // inverse complex-to-real FFT along x1 into u_{i+1}
 // ----------------------------------------------------------------------------
 
@@ -1295,6 +1385,10 @@ static void launch_fft_y(const LaunchCfg &L, const KernelArgs &a) {
   using C = typename cplx<T>::type;
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_y, 3);
+  if (L.tile_y == kTileCol16) {
+    hipLaunchKernelGGL((k_col16<T, INV ? 1 : 0>), grid, blk, col16_lds<C>(), L.stream, a);
+    return;
+  }
   const size_t lds = 2 * (size_t)L.n2max * L.tile_y * sizeof(C);
   if (L.tile_y == B / 4)
     hipLaunchKernelGGL((k_fft_y<T, B / 4, INV>), grid, blk, lds, L.stream, a);
@@ -1311,6 +1405,10 @@ static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
   using C = typename cplx<T>::type;
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_z, 3);
+  if (L.tile_z == kTileCol16) {
+    hipLaunchKernelGGL((k_col16<T, 2>), grid, blk, col16_lds<C>(), L.stream, a);
+    return;
+  }
   const size_t lds = 2 * (size_t)L.n3max * L.tile_z * sizeof(C);
   if (L.tile_z == B / 4)
     hipLaunchKernelGGL((k_poisson_z<T, B / 4>), grid, blk, lds, L.stream, a);

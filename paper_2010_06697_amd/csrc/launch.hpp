@@ -52,7 +52,8 @@ struct LaunchCfg {
   KernelTimer *timer;  // null unless profiling
   hipStream_t stream;
   int nblk_x, nblk_y, nblk_z, nblk_u, nblk_f;
-  int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes
+  int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes,
+                       // or kTileCol16 (the register-resident pass)
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
   bool any_lce;   // some phase uses the LCE energy

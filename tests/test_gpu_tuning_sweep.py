@@ -2,7 +2,9 @@
 computes the projection of Step 2: on thin cells whose one long edge is 48,
 96 or 256 along x1, x2 or x3, each radix sequence of that length (every
 order of every split into radix 8, 4, 2 and 3 stages, at most 8 stages),
-each compiled tile width of the x2 and x3 passes and each x1 workgroup size
+each compiled tile width of the x2 and x3 passes (and the register-resident
+width on an axis of length 256, refused on the others) and each x1
+workgroup size
 give the oracle's projection (Sec. 2.3) to 1e-12 in double and 2e-5 in
 float. Invalid configurations are refused without a change; the autotuner's
 persisted table (ADMM_AUTOTUNE_CACHE) is written and read back.
@@ -95,6 +97,14 @@ def test_every_configuration_projects(precision, n):
             s.set_tuning(ty, tz, 256, {})
             worst = max(worst, projection(s, precision, shape, ref))
             count += 1
+        for ty, tz, ax in [(admm.TILE_REG16, B, 1), (B, admm.TILE_REG16, 2)]:
+            if n != 256 or axis != ax:
+                with pytest.raises(admm.AdmmError):  # length along the axis is not 256
+                    s.set_tuning(ty, tz, 256, {})
+                continue
+            s.set_tuning(ty, tz, 256, {})
+            worst = max(worst, projection(s, precision, shape, ref))
+            count += 1
         for pts in (256, 512, 1024):
             s.set_tuning(B, B, pts, {})
             worst = max(worst, projection(s, precision, shape, ref))
@@ -111,6 +121,7 @@ def test_invalid_configurations_are_refused(tmp_path):
     for bad in [dict(tile_y=3, tile_z=8, x_points=256), dict(tile_y=8, tile_z=8, x_points=300),
                 dict(tile_y=8, tile_z=8, x_points=256, plans={48: [8, 8]}),
                 dict(tile_y=8, tile_z=8, x_points=256, plans={48: [8, 5]}),
+                dict(tile_y=8, tile_z=8, x_points=256, plans={48: [16, 3]}),
                 dict(tile_y=8, tile_z=8, x_points=256, plans={64: [8, 8]})]:
         with pytest.raises(admm.AdmmError) as e:
             s.set_tuning(**bad)
@@ -130,3 +141,33 @@ def test_invalid_configurations_are_refused(tmp_path):
     finally:
         del os.environ["ADMM_AUTOTUNE_CACHE"]
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_register_resident_passes_on_both_column_axes(precision):
+    """x2 and x3 both of length 256 at the register-resident tile width:
+    both column passes (the forward and inverse x2 transforms and the x3
+    transform with the Fourier-space solve) run register resident in one
+    Step 2, against the oracle and against the tiled passes; x1 = 6 leaves
+    partial 16-column groups (m1 = 4 columns per row)."""
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    B = 8 if precision == "fp64" else 16
+    shape = (256, 256, 6)
+    phase = M.random_two_phase(shape, 0.4, seed=11)
+    u, F, L = random_state(shape, seed=12)
+    rho = 2.5
+    ref = O.project(F - L / rho)
+    p = admm.default_params(precision, rho0=rho)
+    s = admm.Solver([phase], MATS, [np.eye(3)], p, precision=precision)
+    s.set_state(0, u=0 * u, F=F, Lambda=L)
+    s.set_tuning(admm.TILE_REG16, admm.TILE_REG16, 256, {})
+    got = s.autotune(reps=0)
+    assert got["tile_y"] == admm.TILE_REG16 and got["tile_z"] == admm.TILE_REG16
+    err = projection(s, precision, shape, ref)
+    u_reg = s.state(0)["u_prev"]
+    s.set_tuning(B, B, 256, {})
+    err_tiled = projection(s, precision, shape, ref)
+    d = rel(u_reg, s.state(0)["u_prev"])
+    s.close()
+    say(f"  register-resident x2 and x3, {precision}: rel {err:.2e} (tiled {err_tiled:.2e}, apart {d:.2e})")
+    assert err <= tol and err_tiled <= tol and d <= tol
