@@ -384,7 +384,7 @@ bool tile_ok(const admm_ctx *c, int axis, int B) {
 }
 
 // tile widths of the x2 / x3 passes: workgroup prefix tables (blk_h holds
-// the x, y, z, u and f tables, n_rve + 1 entries each), grid sizes, upload.
+// the x, y, z, u, f and i tables, n_rve + 1 entries each), grid sizes, upload.
 // Under kTileCol16 an axis's workgroups take 16 columns each of the
 // flattened (x3, m1) or (m2, m1) set.
 static_assert(kTileCol16 == ADMM_TILE_REG16, "tile width of the register-resident pass");
@@ -895,7 +895,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   // descriptors and workgroup prefix tables
   const int B = tile_b(fp64);
   c->desc_h.resize(n_rve);
-  std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1), bf(n_rve + 1);
+  std::vector<int> bx(n_rve + 1), by(n_rve + 1), bz(n_rve + 1), bu(n_rve + 1), bf(n_rve + 1),
+      bi(n_rve + 1);
   bx[0] = by[0] = bz[0] = bu[0] = bf[0] = 0;
   size_t spec_off = 0;
   int n2max = 0, n3max = 0, lds_x = 0;
@@ -937,6 +938,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     const int nrows = D.n2 * D.n3;
     bx[r + 1] = bx[r] + (nrows + D.rows - 1) / D.rows;
     bf[r + 1] = bf[r] + (nrows + D.rows_f - 1) / D.rows_f;
+    bi[r + 1] = bi[r] + (3 * nrows + 31) / 32;
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1s + B - 1) / B;
     bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) *
@@ -961,6 +963,13 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   c->L.tile_y = c->L.tile_z = B;
   c->L.nblk_u = bu[n_rve];
   c->L.nblk_f = bf[n_rve];
+  c->L.nblk_i = bi[n_rve];
+  {
+    // the register-resident inverse x1 pass: float cells, every x1 length 256
+    bool all256 = !fp64;
+    for (const RveDesc &D : c->desc_h) all256 = all256 && D.n1 == 256 && D.m1s >= 129;
+    c->L.inv256 = all256;
+  }
   c->xpoints = default_fft_points(fp64);
   c->L.n2max = n2max;
   c->L.n3max = n3max;
@@ -996,7 +1005,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   }
   INIT_TRY(hipMalloc(&c->desc_d, sizeof(RveDesc) * n_rve));
   INIT_TRY(hipMemcpy(c->desc_d, c->desc_h.data(), sizeof(RveDesc) * n_rve, hipMemcpyHostToDevice));
-  INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 5 * (n_rve + 1)));
+  INIT_TRY(hipMalloc(&c->blk_d, sizeof(int) * 6 * (n_rve + 1)));
   std::vector<int> &blk_h = c->blk_h;
   blk_h.clear();
   blk_h.insert(blk_h.end(), bx.begin(), bx.end());
@@ -1004,6 +1013,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   blk_h.insert(blk_h.end(), bz.begin(), bz.end());
   blk_h.insert(blk_h.end(), bu.begin(), bu.end());
   blk_h.insert(blk_h.end(), bf.begin(), bf.end());
+  blk_h.insert(blk_h.end(), bi.begin(), bi.end());
   INIT_TRY(hipMemcpy(c->blk_d, blk_h.data(), sizeof(int) * blk_h.size(), hipMemcpyHostToDevice));
 
   std::vector<Material> mh(n_mat);
@@ -1056,6 +1066,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.blk_z = c->blk_d + 2 * (n_rve + 1);
   A.blk_u = c->blk_d + 3 * (n_rve + 1);
   A.blk_f = c->blk_d + 4 * (n_rve + 1);
+  A.blk_i = c->blk_d + 5 * (n_rve + 1);
   A.mats = c->mats_d;
   A.tw = c->tw_d;
   A.partials = c->partials_d;

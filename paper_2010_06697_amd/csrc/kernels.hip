@@ -826,9 +826,12 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
 template <typename C> constexpr int col16_slab() { return sizeof(C) == 8 ? 264 : 256; }
 template <typename C> constexpr size_t col16_lds() { return 16 * col16_slab<C>() * sizeof(C); }
 
-template <bool INV, typename C>
+// The exchange buffer holds a slab of SL values per k2; within it the value of
+// (line c, point j) sits at c * 16 + j when JFAST (consecutive lanes take
+// consecutive points), else at j * 16 + c (consecutive lanes take
+// consecutive lines).
+template <bool INV, int SL, bool JFAST, typename C>
 __device__ __forceinline__ void col256(C *v, C *X, const C *__restrict__ tw, int c, int j) {
-  constexpr int SL = col16_slab<C>();
   dft16<INV>(v);
 #pragma unroll
   for (int k2 = 1; k2 < 16; ++k2) {
@@ -836,10 +839,10 @@ __device__ __forceinline__ void col256(C *v, C *X, const C *__restrict__ tw, int
     v[k2] = INV ? cmulc(v[k2], w) : cmul(v[k2], w);
   }
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) X[k2 * SL + j * 16 + c] = v[k2];
+  for (int k2 = 0; k2 < 16; ++k2) X[k2 * SL + (JFAST ? c * 16 + j : j * 16 + c)] = v[k2];
   __syncthreads();
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) v[jj] = X[j * SL + jj * 16 + c];
+  for (int jj = 0; jj < 16; ++jj) v[jj] = X[j * SL + (JFAST ? c * 16 + jj : jj * 16 + c)];
   dft16<INV>(v);
 }
 
@@ -872,7 +875,7 @@ __global__ __launch_bounds__(kThreads) void k_col16(KernelArgs a) {
   C v[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = ok ? col[(j + 16 * k) * es] : C{(T)0, (T)0};
-  col256<MODE == 1>(v, X, tw256, c, j);
+  col256<MODE == 1, col16_slab<C>(), false>(v, X, tw256, c, j);
   if (MODE == 2) {
     // thread (c, j) holds m3 = j + 16 k1
     const double iV = 1.0 / (double)D.V;
@@ -889,7 +892,7 @@ __global__ __launch_bounds__(kThreads) void k_col16(KernelArgs a) {
       v[k] = C{v[k].x * s, v[k].y * s};
     }
     __syncthreads();  // every thread has read the exchange buffer
-    col256<true>(v, X, tw256, c, j);
+    col256<true, col16_slab<C>(), false>(v, X, tw256, c, j);
   }
   if (ok) {
 #pragma unroll
@@ -961,6 +964,68 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
       const C v = res[(ell >> 1) * n1 + x1];
       un[c * V + grow * n1 + x1] = (ell & 1) ? v.y : v.x;
     }
+  }
+}
+
+// Inverse complex-to-real transforms along x1 of length 256 in float,
+// register resident. The cell's 3 n2 n3 real output lines, ordered
+// (component, row), go 32 to a workgroup as 16 complex lines (lines 2p and
+// 2p + 1 as the real and imaginary parts, the same pairing as k_inv_x).
+// Thread (p, j) = (t / 16, t % 16) loads points j + 16 r of complex line p
+// from the two half spectra (completed by Hermitian symmetry; the 16 threads
+// of a line read consecutive entries), runs the length-256 transform of the
+// x2 / x3 passes (col256, one exchange through LDS) and stores x1 = j + 16 k1
+// of both real lines (64 consecutive bytes per line and store).
+// exchange slab stride 257: the lanes of a wave, 16 points of 4 lines, fall
+// in different banks both when they write and when they read the exchange
+constexpr int kInvSlab = 257;
+constexpr size_t kInvLds = 16 * kInvSlab * sizeof(float2);
+
+__global__ __launch_bounds__(kThreads) void k_inv_x256(KernelArgs a) {
+  using C = float2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C *X = reinterpret_cast<C *>(smem);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = find_rve(a.blk_i, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  const RveState *st = a.state + r;
+  if (!st->active) return;
+  const int b = blk - a.blk_i[r];
+  const int nrows = D.n2 * D.n3, nl = 3 * nrows, m1s = D.m1s;
+  const int V = (int)D.V;
+  const long long S = D.S;
+  const int t = threadIdx.x, p = t >> 4, j = t & 15;
+  const int LA = b * 32 + 2 * p, LB = LA + 1;
+  const bool okA = LA < nl, okB = LB < nl;
+  const int cA = LA >= 2 * nrows ? 2 : (LA >= nrows ? 1 : 0), rA = LA - cA * nrows;
+  const int cB = LB >= 2 * nrows ? 2 : (LB >= nrows ? 1 : 0), rB = LB - cB * nrows;
+  const C *spec = static_cast<const C *>(D.spec);
+  const C *sA = spec + cA * S + (long long)rA * m1s;
+  const C *sB = spec + cB * S + (long long)rB * m1s;
+  C v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = j + 16 * q;
+    const int kk = k <= 128 ? k : 256 - k;
+    C Av = okA ? sA[kk] : C{0.0f, 0.0f}, Bv = okB ? sB[kk] : C{0.0f, 0.0f};
+    if (kk == 0 || kk == 128) {
+      Av.y = 0.0f;
+      Bv.y = 0.0f;
+    }
+    if (k > 128) {
+      Av.y = -Av.y;
+      Bv.y = -Bv.y;
+    }
+    v[q] = C{Av.x - Bv.y, Av.y + Bv.x};
+  }
+  const C *tw = static_cast<const C *>(a.tw) + D.p1.tw;
+  col256<true, kInvSlab, true>(v, X, tw, p, j);
+  float *du = static_cast<float *>(D.du);
+  float *oA = du + cA * V + rA * 256, *oB = du + cB * V + rB * 256;
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    if (okA) oA[j + 16 * k1] = v[k1].x;
+    if (okB) oB[j + 16 * k1] = v[k1].y;
   }
 }
 
@@ -1480,7 +1545,10 @@ static hipError_t launch_iteration_part(const LaunchCfg &L, const KernelArgs &a,
       }
       {
         Timed tm(L, K_INV_X);
-        hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
+        if (sizeof(T) == 4 && L.inv256)
+          hipLaunchKernelGGL(k_inv_x256, dim3(L.nblk_i), blk, kInvLds, L.stream, a);
+        else
+          hipLaunchKernelGGL((k_inv_x<T>), dim3(L.nblk_f), blk, L.lds_x, L.stream, a);
       }
       break;
     }

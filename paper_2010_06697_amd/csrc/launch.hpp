@@ -15,6 +15,7 @@ struct KernelArgs {
   const int *blk_z;
   const int *blk_u;
   const int *blk_f;  // the x1-transform kernels (div_fwdx, inv_x)
+  const int *blk_i;  // the register-resident inverse x1 pass (32 real lines each)
   const Material *mats;
   const void *tw;       // twiddle pool (float2 or double2)
   double4 *partials;    // per update workgroup: sum e^2, sum dd^2, and the failed
@@ -52,6 +53,10 @@ struct LaunchCfg {
   KernelTimer *timer;  // null unless profiling
   hipStream_t stream;
   int nblk_x, nblk_y, nblk_z, nblk_u, nblk_f;
+  // float cells all of x1 length 256: the inverse x1 pass runs register
+  // resident (k_inv_x256), nblk_i workgroups
+  bool inv256;
+  int nblk_i;
   int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes,
                        // or kTileCol16 (the register-resident pass)
   int n2max, n3max;
