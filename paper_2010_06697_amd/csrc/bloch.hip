@@ -66,10 +66,16 @@ struct BlochArgs {
   double *Lf;         // per voxel: 45 packed factor entries + 9 reciprocal pivots
   double2 *p, *G, *g, *Dold, *s2;  // p, s2: 3V; G, g, Dold: 9V
   double *part;       // per workgroup partial sums
-  double *scal;       // [0] sigma, [1] r_p, [2] r_d, [3] beta, [4] error flag
+  double *scal;       // [0] sigma, [1] r_p, [2] r_d, [3] beta, [4] error flag,
+                      // [5] |p|^2 of the start, [6] zero-start flag, [7] stop
+                      // (0 iterating, 1 converged, 2 error), [8] iterations run
+  double tol;         // on r_p and r_d
   const double *k2t;  // sin^2(2 pi m/n_j + w_j): n1 + n2 + n3 entries
   double k2min;
 };
+
+// the iterations enqueued after the one that converged (or failed) do nothing
+__device__ __forceinline__ bool bl_stopped(const BlochArgs &a) { return a.scal[7] != 0.0; }
 
 __device__ __forceinline__ void neighbours(const BlochArgs &a, int x, int j, int &xp, int &xm) {
   const int x1 = x % a.n1, x2 = (x / a.n1) % a.n2, x3 = x / (a.n1 * a.n2);
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_bl_factor(BlochArgs a) {
 // Step 1': G = (L + rho I)^{-1} (g + rho D_w p); keeps D_w p for r_d
 __global__ __launch_bounds__(kThreads) void k_bl_local(BlochArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= a.V) return;
+  if (x >= a.V || bl_stopped(a)) return;
   double2 d[9];
   dgrad(a, a.p, x, d);
   double br[9], bi[9], xr[9], xi[9];
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_bl_local(BlochArgs a) {
 // Step 2' right-hand side: b = D_w^H (G - g/rho) into s2
 __global__ __launch_bounds__(kThreads) void k_bl_div(BlochArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= a.V) return;
+  if (x >= a.V || bl_stopped(a)) return;
   const double ir = 1.0 / a.rho;
   double2 b[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
@@ -239,8 +245,9 @@ __global__ __launch_bounds__(kThreads) void k_bl_div(BlochArgs a) {
 template <bool INV>
 __global__ __launch_bounds__(kThreads) void k_bl_fft(double2 *data, int ncomp, int n1, int n2,
                                                     int n3, int axis, Plan1D pl,
-                                                    const double2 *tw, int B) {
+                                                    const double2 *tw, int B, const double *stop) {
   extern __shared__ double2 lds[];
+  if (*stop != 0.0) return;  // uniform over the workgroup
   const int N = pl.n;
   double2 *A = lds, *Bf = lds + B * N;
   const int nlines = ncomp * n1 * n2 * n3 / N;
@@ -295,6 +302,7 @@ __device__ __forceinline__ double k2_at(const BlochArgs &a, int x) {
 __global__ __launch_bounds__(1024) void k_bl_secular(BlochArgs a) {
   __shared__ double red[16];
   __shared__ double lohi[2];
+  if (bl_stopped(a)) return;
   const double V = (double)a.V;
   double bb[1] = {0.0};
   for (int x = threadIdx.x; x < a.V; x += blockDim.x)
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(1024) void k_bl_secular(BlochArgs a) {
 // p^ = b^ / (|K|^2 - sigma), with the 1/V of the inverse transform
 __global__ __launch_bounds__(kThreads) void k_bl_scale(BlochArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= a.V) return;
+  if (x >= a.V || bl_stopped(a)) return;
   const double f = 1.0 / ((k2_at(a, x) - a.scal[0]) * (double)a.V);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -353,6 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_bl_scale(BlochArgs a) {
 // Steps 3' and 4' (partial sums per workgroup)
 __global__ __launch_bounds__(kThreads) void k_bl_update(BlochArgs a) {
   __shared__ double red[2 * (kThreads / 64)];
+  if (bl_stopped(a)) return;  // uniform over the workgroup
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (x < a.V) {
@@ -408,10 +417,12 @@ __global__ __launch_bounds__(kThreads) void k_bl_rayleigh(BlochArgs a) {
   if (threadIdx.x == 0) a.part[2 * blockIdx.x] = q[0];
 }
 
-// fixed-order sum of the partials: NV values per workgroup -> scal[dst..]
-template <int NV>
+// fixed-order sum of the partials: NV values per workgroup -> scal[dst..];
+// ITER: the end of an iteration, which also counts it and decides the stop
+template <int NV, bool ITER = false>
 __global__ __launch_bounds__(kThreads) void k_bl_reduce(BlochArgs a, int nblk, int dst) {
   __shared__ double red[NV * (kThreads / 64)];
+  if (ITER && bl_stopped(a)) return;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
@@ -419,9 +430,17 @@ __global__ __launch_bounds__(kThreads) void k_bl_reduce(BlochArgs a, int nblk, i
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] += a.part[2 * b + k];
   bl_block_sum<NV>(v, red);
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) a.scal[dst + k] = v[k];
+    if (ITER) {
+      a.scal[8] += 1.0;
+      const double rp = sqrt(a.scal[1] / (double)a.V);
+      const double rd = a.rho * sqrt(a.scal[2] / (double)a.V);
+      if (a.scal[4] != 0.0) a.scal[7] = 2.0;
+      else if (rp <= a.tol && rd <= a.tol) a.scal[7] = 1.0;
+    }
+  }
 }
 
 // zero fill of n doubles (the multiplier and the scalars start at zero)
@@ -476,7 +495,7 @@ static __device__ __align__(256) unsigned char scratch[kBlochScratchBytes];
 size_t bloch_work_bytes(const RveDesc &D) {
   const size_t V = (size_t)D.V;
   const size_t nblk = (V + kThreads - 1) / kThreads;
-  return V * 54 * 8 + (3 + 9 + 9 + 9 + 3) * V * 16 + 2 * nblk * 8 + 8 * 8 +
+  return V * 54 * 8 + (3 + 9 + 9 + 9 + 3) * V * 16 + 2 * nblk * 8 + 16 * 8 +
          (size_t)(D.n1 + D.n2 + D.n3) * 8;
 }
 
@@ -515,6 +534,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     a.s[j] = std::sin(omega[j]);
   }
   a.rho = rho;
+  a.tol = tol;
   a.E = static_cast<const double *>(D.E);
   a.dir = static_cast<const double *>(D.dir);
   a.phase = D.phase;
@@ -556,7 +576,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
   a.part = reinterpret_cast<double *>(q);
   q += 2 * (size_t)nblk * 8;
   a.scal = reinterpret_cast<double *>(q);
-  q += 8 * 8;
+  q += 16 * 8;
   a.k2t = reinterpret_cast<const double *>(q);
   int rc = 0;
   auto fail = [&](int code) {
@@ -569,7 +589,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     // buffer may hold an earlier call's values)
     hipLaunchKernelGGL(k_bl_zero, dim3(std::min(nblk * 9, 4096)), blk, 0, st,
                        reinterpret_cast<double *>(a.g), 18 * V);
-    hipLaunchKernelGGL(k_bl_zero, dim3(1), blk, 0, st, a.scal, (size_t)8);
+    hipLaunchKernelGGL(k_bl_zero, dim3(1), blk, 0, st, a.scal, (size_t)16);
     if (hipMemcpyAsync(const_cast<double *>(a.k2t), k2h, (size_t)nk * 8, hipMemcpyHostToDevice,
                        st) != hipSuccess ||
         hipMemcpyAsync(a.p, p, 3 * V * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
@@ -581,7 +601,7 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
     hipLaunchKernelGGL(k_bl_norm, grid, blk, 0, st, a);
     hipLaunchKernelGGL((k_bl_reduce<1>), dim3(1), blk, 0, st, a, nblk, 5);
     hipLaunchKernelGGL(k_bl_normalize, grid, blk, 0, st, a);
-    double scal[8];
+    double scal[16];
     if (hipMemcpyAsync(scal, a.scal, sizeof(scal), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       fail(-1);
@@ -606,46 +626,54 @@ int bloch_solve(hipStream_t st, const RveDesc &D, const Material *mats_d, int n_
         const size_t lds = 2 * (size_t)B * N * sizeof(double2);
         if (inv)
           hipLaunchKernelGGL(k_bl_fft<true>, dim3(g), blk, lds, st, data, 3, a.n1, a.n2, a.n3, ax,
-                             pls[ax], twd, B);
+                             pls[ax], twd, B, a.scal + 7);
         else
           hipLaunchKernelGGL(k_bl_fft<false>, dim3(g), blk, lds, st, data, 3, a.n1, a.n2, a.n3,
-                             ax, pls[ax], twd, B);
+                             ax, pls[ax], twd, B, a.scal + 7);
       }
     };
-    int it = 0;
+    // iterations enqueued in chunks, the host reading the stop word once per
+    // chunk: an iteration after the one that converged (or failed) does
+    // nothing, so the result and the count are those of checking every one
+    constexpr int kChunk = 16;
+    int queued = 0;
     *status = 1;
-    for (; it < max_iter;) {
-      hipLaunchKernelGGL(k_bl_local, grid, blk, 0, st, a);
-      hipLaunchKernelGGL(k_bl_div, grid, blk, 0, st, a);
-      fft3(a.s2, false);
-      hipLaunchKernelGGL(k_bl_secular, dim3(1), dim3(1024), 0, st, a);
-      // p^ = b^ / (|K|^2 - sigma) in place, inverse transform there, and
-      // the two buffers swap roles (p in the transformed one)
-      {
-        BlochArgs b = a;
-        b.p = a.s2;
-        hipLaunchKernelGGL(k_bl_scale, grid, blk, 0, st, b);
+    while (queued < max_iter) {
+      const int m = std::min(kChunk, max_iter - queued);
+      for (int k = 0; k < m; ++k) {
+        hipLaunchKernelGGL(k_bl_local, grid, blk, 0, st, a);
+        hipLaunchKernelGGL(k_bl_div, grid, blk, 0, st, a);
+        fft3(a.s2, false);
+        hipLaunchKernelGGL(k_bl_secular, dim3(1), dim3(1024), 0, st, a);
+        // p^ = b^ / (|K|^2 - sigma) in place, inverse transform there, and
+        // the two buffers swap roles (p in the transformed one)
+        {
+          BlochArgs b = a;
+          b.p = a.s2;
+          hipLaunchKernelGGL(k_bl_scale, grid, blk, 0, st, b);
+        }
+        fft3(a.s2, true);
+        std::swap(a.p, a.s2);
+        hipLaunchKernelGGL(k_bl_update, grid, blk, 0, st, a);
+        hipLaunchKernelGGL((k_bl_reduce<2, true>), dim3(1), blk, 0, st, a, nblk, 1);
       }
-      fft3(a.s2, true);
-      std::swap(a.p, a.s2);
-      hipLaunchKernelGGL(k_bl_update, grid, blk, 0, st, a);
-      hipLaunchKernelGGL((k_bl_reduce<2>), dim3(1), blk, 0, st, a, nblk, 1);
-      ++it;
+      queued += m;
       if (hipMemcpyAsync(scal, a.scal, sizeof(scal), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
         fail(-1);
         break;
       }
-      if (scal[4] != 0.0) {
-        fail(-2);
-        break;
-      }
-      const double rp = std::sqrt(scal[1] / (double)V), rd = rho * std::sqrt(scal[2] / (double)V);
-      if (rp <= tol && rd <= tol) {
-        *status = 0;
-        break;
-      }
+      if (scal[7] != 0.0) break;
     }
+    if (rc) break;
+    // the buffers swapped once per enqueued iteration, p only once per run one
+    const int it = (int)scal[8];
+    if ((queued - it) % 2) std::swap(a.p, a.s2);
+    if (scal[7] == 2.0) {
+      fail(-2);
+      break;
+    }
+    if (scal[7] == 1.0) *status = 0;
     if (rc) break;
     hipLaunchKernelGGL(k_bl_rayleigh, grid, blk, 0, st, a);
     hipLaunchKernelGGL((k_bl_reduce<1>), dim3(1), blk, 0, st, a, nblk, 3);
