@@ -154,7 +154,11 @@ typedef struct {
    * or local_passes passes ran. r_l is reduced inside the local kernel (one
    * partial sum per workgroup) and tested on the device; the host is not
    * involved. At most one of local_ratio and local_fraction is nonzero; both
-   * zero: every local problem solved to the Newton tolerances. With either
+   * zero: every local problem solved to the Newton tolerances. The ideal
+   * LCE's local problem (three unknowns in the singular basis of A) is solved
+   * in full in every pass, at most max(local_chunk, newton_max, 100)
+   * iterations: it costs less than the passes a truncated solve would need
+   * (each rebuilds the singular basis). With either
    * strategy, admm_solve counts a cell as converged only when r_l <= tol_d
    * as well (equilibrium needs the local residual small too). */
   double local_ratio;   /* > 0: from the second iteration of a load step,

@@ -642,7 +642,10 @@ static int newton_relaxed(const or_material *m, double rho, const double A[9],
    F = sum f_i u_i v_i^T is sum_i (dh/df_i) u_i v_i^T, so its norm is that of
    the 3-component gradient and the gradient test means the same. The start
    is the current F's diagonal in the singular basis, or a (with entries
-   below a1/16 raised to a1/16) where that has the lower objective. */
+   below a1/16 raised to a1/16) where that has the lower objective. The
+   solve runs to its stopping rules within max(max_iter, 100) iterations,
+   also in the passes of the inexact step, whose chunk cap it does not
+   take: a truncated solve would cost more passes than it saves. */
 static double spec_h(double mua, double beta, double mu, double kap, double rho,
                      const double *f, const double *a) {
   double J = f[0] * f[1] * f[2];
@@ -716,7 +719,8 @@ static int prox_spectral(const or_material *m, double rho, const double A[9],
   const double scale_mod = moduli_sum(m) + rho;
   const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
   int rc = OR_NOT_CONVERGED, iter;
-  for (iter = 0; iter < opt->max_iter; ++iter) {
+  const int cap = opt->max_iter > 100 ? opt->max_iter : 100;
+  for (iter = 0; iter < cap; ++iter) {
     double g[3];
     spec_grad(mua, beta, kap, rho, f, a, g);
     double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);

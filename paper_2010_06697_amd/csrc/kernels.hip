@@ -289,10 +289,13 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         if (fp) {
           rc = lce_local<T>(E, At, m, rho, n, ip, cap, n_its, fp);
         } else {
-          // the ideal model: the local problem in A's singular basis
-          rc = lce_spectral<T>(E, At, m.mua, m.beta, m.kappa, m.mu, rho, n, cap, ip.gtol,
+          // the ideal model: the local problem in A's singular basis, solved
+          // in full also in an inexact pass (the chunk cap would only add
+          // passes, each rebuilding the basis)
+          const int scap = cap > 100 ? cap : 100;
+          rc = lce_spectral<T>(E, At, m.mua, m.beta, m.kappa, m.mu, rho, n, scap, ip.gtol,
                                ip.step_tol);
-          n_its += rc >= 0 ? rc : cap;
+          n_its += rc >= 0 ? rc : scap;
         }
         dg[idx] = (T)n[0];
         dg[V + idx] = (T)n[1];

@@ -122,8 +122,9 @@ def test_strict_limits_reproduce_the_exact_iteration(limit):
 
 def test_inexact_lce_composite_matches_oracle_fp64():
     """Polydomain LCE with a stiff neo-Hookean inclusion under a stretch 1.2,
-    every joint (F, director) solve and every neo-Hookean one truncated to
-    one Newton iteration per pass."""
+    every neo-Hookean solve truncated to one Newton iteration per pass (the
+    ideal LCE's singular-basis solves run in full in every pass, on both
+    sides)."""
     from test_gpu_lce import iteration_case
     phase, n0, Fbar, mats = iteration_case("composite")
     loc = dict(local_ratio=0.3, local_chunk=1, local_passes=4)
