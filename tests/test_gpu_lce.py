@@ -245,3 +245,41 @@ def test_lce_load_path_matches_oracle_fp64():
     assert du <= 1e-12 * 16 * np.linalg.norm(loads[-1] - np.eye(3)) or errs["u"] <= 1e-10
     assert errs["F"] <= 1e-10 and errs["Lambda"] <= 1e-10
     assert errs["director"] <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lce_local_step_with_negative_det_data(precision):
+    """Local data A with det A < 0 at every voxel (a reflection of one axis
+    times a stretch, from the multiplier, u = 0 and Fbar = I): the local
+    step keeps det F > 0 and gives the oracle's minimiser (the negative
+    signed singular value of A on the kernel side)."""
+    shape = (4, 6, 8)
+    phase = np.zeros(shape, np.uint8)
+    rng = np.random.default_rng(33)
+    rho = 10.0
+    V = int(np.prod(shape))
+    R = np.diag([1.0, 1.0, -1.0])
+    At = (R @ np.diag([1.2, 1.0, 0.3]))[None] + 0.05 * rng.standard_normal((V, 3, 3))
+    assert np.all(np.linalg.det(At) < 0)
+    L = (rho * (At - np.eye(3))).reshape(V, 9).T.reshape((9,) + shape)
+    n0 = rng.standard_normal((3,) + shape)
+    n0 /= np.linalg.norm(n0, axis=0, keepdims=True)
+    s = lce_solver(phase, n0, np.eye(3), precision, rho0=rho)
+    s.set_state(0, u=np.zeros((3,) + shape), F=np.tile(np.eye(3).reshape(9, 1, 1, 1), (1,) + shape),
+                Lambda=L)
+    st0 = s.state(0)
+    s.local_step()
+    out = s.state(0)
+    s.close()
+    A = np.eye(3).reshape(9, 1, 1, 1) + st0["Lambda"] / rho
+    m = omats(LCE)[0]
+    errF = 0.0
+    for x in np.ndindex(shape):
+        sl = (slice(None),) + x
+        Fx, nx, _, rc = O.prox(m, rho, A[sl], st0["F"][sl], st0["director"][sl],
+                               opts=O.newton_opts(**NEWTON64))
+        assert rc == O.OK
+        assert np.linalg.det(out["F"][sl].reshape(3, 3)) > 0
+        errF = max(errF, np.max(np.abs(out["F"][sl] - Fx)))
+    say("  negative det A,", precision, "max |dF|", errF)
+    assert errF <= (1e-12 if precision == "fp64" else 1e-6)
