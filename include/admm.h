@@ -368,10 +368,13 @@ typedef struct {
   double ms_tuned;          /* and after tuning */
 } admm_tuning;
 
-/* Tile width of the register-resident x2 / x3 pass of length 256: a
- * workgroup takes 16 columns, each thread 16 points of one column; a
- * transform is a length-16 DFT in registers, a twiddle, one exchange
- * through LDS and a second length-16 DFT (256 = 16 x 16, Cooley-Tukey). */
+/* Tile width of the register-resident x2 / x3 pass, open to an axis where
+ * every cell's length along it is 32, 48, 64, 96, 128 or 256 (float with
+ * double reductions) or 256 (double). A length N = T P (T dividing P: 2 x 16,
+ * 4 x 12, 4 x 16, 4 x 24, 8 x 16, 16 x 16) is taken by T threads per column,
+ * P points each, 256 / T columns per workgroup: a length-P DFT in
+ * registers, a twiddle, one exchange through LDS and P / T length-T DFTs
+ * (Cooley-Tukey); each thread ends with the points it loaded. */
 #define ADMM_TILE_REG16 (-16)
 
 /* Autotuner (a performance control with no counterpart in the method): times
@@ -379,7 +382,7 @@ typedef struct {
  * (best of three), and keeps the fastest number of points per workgroup of
  * the x1 transforms, then the fastest tile width of the x2 pass, then of
  * the x3 pass (a quarter, half, default or double width, LDS <= 64 KiB, or
- * ADMM_TILE_REG16 where every cell's length along that axis is 256), then the
+ * ADMM_TILE_REG16 where every cell's length along that axis is supported), then the
  * fastest radix sequence of each transform length in turn (every order of
  * the radix-8/4/2/3 splits, at most 24 per length). Results change only by
  * rounding (the transforms' operation order). Step 2 writes each cell's
@@ -398,7 +401,7 @@ int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out);
 /* Applies a Step 2 launch configuration (a tuning admm_autotune reported,
  * or any other): tile widths of the x2 / x3 passes (compiled widths, LDS
  * <= 64 KiB, or ADMM_TILE_REG16 where every cell's length along that axis
- * is 256), points per workgroup of the x1 transforms (256, 512, 1024)
+ * is supported), points per workgroup of the x1 transforms (256, 512, 1024)
  * and, for each of the n_len lengths listed, its radix sequence (2, 3, 4,
  * 8, product equal to the length; lengths the context does not have are
  * refused). ms_default / ms_tuned are ignored. ADMM_EINVAL, with nothing

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libadmm.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, EUNSUPPORTED, EHIP, ENOMEM, EDOMAIN, EDIVERGED, ENOGPU = -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_FP64RED = 0, 1
-TILE_REG16 = -16  # tile width of the register-resident x2 / x3 pass (length 256)
+TILE_REG16 = -16  # tile width of the register-resident x2 / x3 passes
 NEOHOOKE, LCE = 0, 1
 
 # entry points declared in include/admm.h, in order

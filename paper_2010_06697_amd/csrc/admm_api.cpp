@@ -366,11 +366,12 @@ void drop_graphs(admm_ctx *c) {
   }
 }
 
-// the register-resident x2 / x3 pass (k_col16, tile width kTileCol16) is
-// open to an axis when every cell's length along it is 256
+// the register-resident x2 / x3 pass (tile width kTileCol16: k_colreg in
+// float, k_col16 in double) is open to an axis when every cell's length
+// along it is supported (float: 32, 48, 64, 96, 128, 256; double: 256)
 bool col16_ok(const admm_ctx *c, int axis) {
   for (const RveDesc &D : c->desc_h)
-    if ((axis == 2 ? D.n2 : D.n3) != 256) return false;
+    if (!reg_points(c->fp64, axis == 2 ? D.n2 : D.n3)) return false;
   return true;
 }
 
@@ -393,11 +394,26 @@ int set_tiles(admm_ctx *c, int ty, int tz) {
   const int n = c->n_rve;
   int *by = c->blk_h.data() + (n + 1), *bz = c->blk_h.data() + 2 * (n + 1);
   by[0] = bz[0] = 0;
+  int py = 0, pz = 0;
   for (int r = 0; r < n; ++r) {
     const RveDesc &D = c->desc_h[r];
-    by[r + 1] = by[r] + (ty == kTileCol16 ? (D.n3 * D.m1 + 15) / 16 : D.n3 * ((D.m1 + ty - 1) / ty));
-    bz[r + 1] = bz[r] + (tz == kTileCol16 ? (D.n2 * D.m1 + 15) / 16 : (D.n2 * D.m1s + tz - 1) / tz);
+    if (ty == kTileCol16) {
+      const int cw = reg_columns(c->fp64, D.n2);
+      by[r + 1] = by[r] + (D.n3 * D.m1 + cw - 1) / cw;
+      py = std::max(py, reg_points(c->fp64, D.n2));
+    } else {
+      by[r + 1] = by[r] + D.n3 * ((D.m1 + ty - 1) / ty);
+    }
+    if (tz == kTileCol16) {
+      const int cw = reg_columns(c->fp64, D.n3);
+      bz[r + 1] = bz[r] + (D.n2 * D.m1 + cw - 1) / cw;
+      pz = std::max(pz, reg_points(c->fp64, D.n3));
+    } else {
+      bz[r + 1] = bz[r] + (D.n2 * D.m1s + tz - 1) / tz;
+    }
   }
+  c->L.lds_coly = reg_lds(c->fp64, py);
+  c->L.lds_colz = reg_lds(c->fp64, pz);
   c->L.tile_y = ty;
   c->L.tile_z = tz;
   c->L.nblk_y = by[n];

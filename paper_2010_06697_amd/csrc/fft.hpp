@@ -117,11 +117,62 @@ template <bool INV, typename C> __device__ __forceinline__ void dft16(C *v) {
   }
 }
 
+// length-A*B DFT split as n = n1 + A n2, k = k2 + B k1:
+// X[k2 + B k1] = sum_n1 w_A^(n1 k1) w_AB^(n1 k2) sum_n2 x[n1 + A n2] w_B^(n2 k2),
+// inner length-B transforms over n2, the twiddles, outer length-A ones over
+// n1; wc / ws: cos / sin of 2 pi m / (A B) for the m = n1 k2 that occur
+template <int A, int B, bool INV, typename C>
+__device__ __forceinline__ void dft_split(C *v, const double *wc, const double *ws);
+
+// lengths 12 = 4 x 3 and 24 = 8 x 3 (the register-resident x2 / x3 passes
+// of lengths 48 and 96)
+template <bool INV, typename C> __device__ __forceinline__ void dft12(C *v) {
+  const double h3 = 0.866025403784438646764;  // sqrt(3)/2
+  const double wc[7] = {1.0, h3, 0.5, 0.0, -0.5, -h3, -1.0};
+  const double ws[7] = {0.0, 0.5, h3, 1.0, h3, 0.5, 0.0};
+  dft_split<4, 3, INV>(v, wc, ws);
+}
+template <bool INV, typename C> __device__ __forceinline__ void dft24(C *v) {
+  const double c15 = 0.96592582628906828675, s15 = 0.258819045102520762349;
+  const double h3 = 0.866025403784438646764, h2 = 0.707106781186547524401;
+  const double wc[15] = {1.0, c15, h3, h2, 0.5, s15, 0.0, -s15, -0.5, -h2, -h3, -c15, -1.0, -c15, -h3};
+  const double ws[15] = {0.0, s15, 0.5, h2, h3, c15, 1.0, c15, h3, h2, 0.5, s15, 0.0, -s15, -0.5};
+  dft_split<8, 3, INV>(v, wc, ws);
+}
+
 template <int R, bool INV, typename C> __device__ __forceinline__ void dftR(C *v) {
-  if constexpr (R == 2) dft2<INV>(v);
+  if constexpr (R == 1) (void)v;
+  else if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
-  else dft8<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else if constexpr (R == 12) dft12<INV>(v);
+  else if constexpr (R == 16) dft16<INV>(v);
+  else dft24<INV>(v);
+}
+
+template <int A, int B, bool INV, typename C>
+__device__ __forceinline__ void dft_split(C *v, const double *wc, const double *ws) {
+  using T = decltype(v[0].x);
+  C a[B][A];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) {
+    C q[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) q[n2] = v[n1 + A * n2];
+    dftR<B, INV>(q);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const int m = n1 * k2;
+      a[k2][n1] = m == 0 ? q[k2] : cmul(q[k2], C{(T)wc[m], INV ? (T)ws[m] : -(T)ws[m]});
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    dftR<A, INV>(a[k2]);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) v[k2 + B * k1] = a[k2][k1];
+  }
 }
 
 // One radix-R stage over `nlines` lines. Element k of line l lives at

@@ -812,7 +812,8 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
 
 // ----------------------------------------------------------------------------
 // x2 and x3 passes of length 256 at the tile width kTileCol16, register
-// resident: a workgroup takes 16 columns (flattened over the cell's (x3, m1)
+// resident (k_col16 in double; float cells take k_colreg below, which covers
+// 256 the same way and shorter lengths too): a workgroup takes 16 columns (flattened over the cell's (x3, m1)
 // for x2, (m2, m1) for x3, padding columns excluded); thread (c, j) =
 // (t % 16, t / 16) holds elements j + 16 r (r = 0..15) of column c. With
 // n = j + 16 r and k = 16 k1 + k2,
@@ -967,6 +968,118 @@ __global__ __launch_bounds__(kThreads) void k_inv_x(KernelArgs a) {
       const C v = res[(ell >> 1) * n1 + x1];
       un[c * V + grow * n1 + x1] = (ell & 1) ? v.y : v.x;
     }
+  }
+}
+
+// Register-resident x2 / x3 passes in float for the lengths 32, 48, 64, 96,
+// 128 and 256 (cells of different lengths in one launch, each workgroup in
+// one cell): a length N = T P is taken by T threads per column, P points each;
+// a workgroup takes 256 / T columns. Thread (c, j) loads points j + T r
+// (r < P) of column c; with n = j + T r and k = k2 + P k1,
+//     X[P k1 + k2] = sum_j w_T^(j k1) w_N^(j k2) sum_r x[j + T r] w_P^(r k2):
+// a length-P DFT in registers, the twiddle w_N^(j k2), one exchange through
+// LDS, and thread (c, j) then takes the k2 = j + T q (q < P / T), each a
+// length-T DFT over the T threads' values. It ends with X[j + T r'],
+// r' = q + (P / T) k1: the layout it loaded (T divides P), so results go
+// back in place and the x3 pass's inverse transform follows in registers.
+__host__ __device__ constexpr int colreg_points(int n) {
+  return (n == 32 || n == 64 || n == 128 || n == 256) ? 16 : (n == 48 ? 12 : (n == 96 ? 24 : 0));
+}
+// LDS slab of one k2: T x (256 / T) = 256 values padded by 8 (the rows a wave
+// reads in the exchange fall in different banks)
+constexpr int kColSlab = 264;
+
+template <bool INV, int TT, int P>
+__device__ __forceinline__ void colreg(float2 *v, float2 *X, const float2 *__restrict__ tw,
+                                       int c, int j) {
+  constexpr int CW = kThreads / TT;
+  dftR<P, INV>(v);
+#pragma unroll
+  for (int k2 = 1; k2 < P; ++k2) {
+    const float2 w = tw[j * k2];  // j k2 < N
+    v[k2] = INV ? cmulc(v[k2], w) : cmul(v[k2], w);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < P; ++k2) X[k2 * kColSlab + j * CW + c] = v[k2];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < P / TT; ++q) {
+    float2 z[TT];
+#pragma unroll
+    for (int jj = 0; jj < TT; ++jj) z[jj] = X[(j + TT * q) * kColSlab + jj * CW + c];
+    dftR<TT, INV>(z);
+#pragma unroll
+    for (int k1 = 0; k1 < TT; ++k1) v[q + (P / TT) * k1] = z[k1];
+  }
+}
+
+// one workgroup's columns of one cell; MODE as k_col16
+template <int MODE, int TT, int P>
+__device__ __forceinline__ void colreg_tile(const KernelArgs &a, const RveDesc &D, int b,
+                                            float2 *X) {
+  constexpr int CW = kThreads / TT, N = TT * P;
+  const int t = threadIdx.x, c = t % CW, j = t / CW;
+  const int n2 = D.n2, m1 = D.m1, m1s = D.m1s;
+  const int ncol = (MODE == 2 ? n2 : D.n3) * m1;
+  const int g = b * CW + c;
+  const bool ok = g < ncol;
+  const int outer = ok ? g / m1 : 0, q = ok ? g - outer * m1 : 0;
+  const long long es = MODE == 2 ? (long long)n2 * m1s : (long long)m1s;
+  float2 *col = static_cast<float2 *>(D.spec) + blockIdx.y * D.S +
+                (MODE == 2 ? (long long)outer * m1s : (long long)outer * n2 * m1s) + q;
+  const float2 *tw = static_cast<const float2 *>(a.tw);
+  const float2 *twN = tw + (MODE == 2 ? D.p3.tw : D.p2.tw);
+  float2 v[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) v[r] = ok ? col[(j + TT * r) * es] : float2{0.0f, 0.0f};
+  colreg<MODE == 1, TT, P>(v, X, twN, c, j);
+  if (MODE == 2) {
+    // thread (c, j) holds m3 = j + TT r
+    const double iV = 1.0 / (double)D.V;
+    const double K1 = (double)tw[D.p1.tw + q].y;
+    const double K2 = (double)tw[D.p2.tw + outer].y;
+    const double K12 = K1 * K1 + K2 * K2;
+    const bool null12 = (q == 0 || 2 * q == D.n1) && (outer == 0 || 2 * outer == n2);
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int m3 = j + TT * r;
+      const double K3 = (double)twN[m3].y;
+      const bool null = !ok || (null12 && (m3 == 0 || 2 * m3 == N));
+      const float s = null ? 0.0f : (float)(iV / (K12 + K3 * K3));
+      v[r] = float2{v[r].x * s, v[r].y * s};
+    }
+    __syncthreads();  // every thread has read the exchange buffer
+    colreg<true, TT, P>(v, X, twN, c, j);
+  }
+  if (ok) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) col[(j + TT * r) * es] = v[r];
+  }
+}
+
+// MODE 0: x2 forward, 1: x2 inverse, 2: x3 forward, u_hat = b_hat/(|K|^2 V),
+// x3 inverse (blockIdx.y = component). PMAX: the most points per thread any
+// cell of the launch needs; the length 96 (24 points) is compiled only into
+// the PMAX = 24 kernel, so the others keep the registers of 16 points.
+template <int MODE, int PMAX>
+__global__ __launch_bounds__(kThreads) void k_colreg(KernelArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2 *X = reinterpret_cast<float2 *>(smem);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int *tab = MODE == 2 ? a.blk_z : a.blk_y;
+  const int r = find_rve(tab, a.n_rve, blk);
+  const RveDesc &D = a.desc[r];
+  if (!a.state[r].active) return;
+  const int b = blk - tab[r];
+  switch (MODE == 2 ? D.n3 : D.n2) {  // uniform over the workgroup
+    case 32: colreg_tile<MODE, 2, 16>(a, D, b, X); break;
+    case 48: colreg_tile<MODE, 4, 12>(a, D, b, X); break;
+    case 64: colreg_tile<MODE, 4, 16>(a, D, b, X); break;
+    case 96:
+      if constexpr (PMAX == 24) colreg_tile<MODE, 4, 24>(a, D, b, X);
+      break;
+    case 128: colreg_tile<MODE, 8, 16>(a, D, b, X); break;
+    default: colreg_tile<MODE, 16, 16>(a, D, b, X); break;  // 256
   }
 }
 
@@ -1454,7 +1567,14 @@ static void launch_fft_y(const LaunchCfg &L, const KernelArgs &a) {
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_y, 3);
   if (L.tile_y == kTileCol16) {
-    hipLaunchKernelGGL((k_col16<T, INV ? 1 : 0>), grid, blk, col16_lds<C>(), L.stream, a);
+    if constexpr (sizeof(T) == 4) {
+      if (L.lds_coly > reg_lds(false, 16))
+        hipLaunchKernelGGL((k_colreg<INV ? 1 : 0, 24>), grid, blk, L.lds_coly, L.stream, a);
+      else
+        hipLaunchKernelGGL((k_colreg<INV ? 1 : 0, 16>), grid, blk, L.lds_coly, L.stream, a);
+    } else {
+      hipLaunchKernelGGL((k_col16<T, INV ? 1 : 0>), grid, blk, col16_lds<C>(), L.stream, a);
+    }
     return;
   }
   const size_t lds = 2 * (size_t)L.n2max * L.tile_y * sizeof(C);
@@ -1474,7 +1594,14 @@ static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_z, 3);
   if (L.tile_z == kTileCol16) {
-    hipLaunchKernelGGL((k_col16<T, 2>), grid, blk, col16_lds<C>(), L.stream, a);
+    if constexpr (sizeof(T) == 4) {
+      if (L.lds_colz > reg_lds(false, 16))
+        hipLaunchKernelGGL((k_colreg<2, 24>), grid, blk, L.lds_colz, L.stream, a);
+      else
+        hipLaunchKernelGGL((k_colreg<2, 16>), grid, blk, L.lds_colz, L.stream, a);
+    } else {
+      hipLaunchKernelGGL((k_col16<T, 2>), grid, blk, col16_lds<C>(), L.stream, a);
+    }
     return;
   }
   const size_t lds = 2 * (size_t)L.n3max * L.tile_z * sizeof(C);
@@ -1605,6 +1732,17 @@ hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams
 }
 
 int tile_b(bool fp64) { return fp64 ? tileB<double>() : tileB<float>(); }
+
+// register-resident x2 / x3 pass: points per thread for a length (0: not
+// supported), columns per workgroup, LDS bytes for points per thread P
+int reg_points(bool fp64, int n) { return fp64 ? (n == 256 ? 16 : 0) : colreg_points(n); }
+int reg_columns(bool fp64, int n) {
+  const int P = reg_points(fp64, n);
+  return P ? kThreads / (n / P) : 0;
+}
+size_t reg_lds(bool fp64, int pmax) {
+  return fp64 ? col16_lds<double2>() : (size_t)pmax * kColSlab * sizeof(float2);
+}
 
 bool tile_compiled(bool fp64, int B) {
   const int d = tile_b(fp64);

@@ -59,6 +59,7 @@ struct LaunchCfg {
   int nblk_i;
   int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes,
                        // or kTileCol16 (the register-resident pass)
+  size_t lds_coly, lds_colz;  // LDS bytes of the register-resident passes
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
   bool any_lce;   // some phase uses the LCE energy
@@ -103,5 +104,8 @@ hipError_t launch_part(const LaunchCfg &L, const KernelArgs &a, const IterParams
 // quarter, half, default, double)
 int tile_b(bool fp64);
 bool tile_compiled(bool fp64, int B);
+int reg_points(bool fp64, int n);
+int reg_columns(bool fp64, int n);
+size_t reg_lds(bool fp64, int pmax);
 
 }  // namespace admm
