@@ -412,6 +412,11 @@ int set_tiles(admm_ctx *c, int ty, int tz) {
       bz[r + 1] = bz[r] + (D.n2 * D.m1s + tz - 1) / tz;
     }
   }
+  c->L.col256_y = c->L.col256_z = true;
+  for (const RveDesc &D : c->desc_h) {
+    c->L.col256_y = c->L.col256_y && D.n2 == 256;
+    c->L.col256_z = c->L.col256_z && D.n3 == 256;
+  }
   c->L.lds_coly = reg_lds(c->fp64, py);
   c->L.lds_colz = reg_lds(c->fp64, pz);
   c->L.tile_y = ty;
@@ -958,7 +963,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
     by[r + 1] = by[r] + D.n3 * ((D.m1 + B - 1) / B);
     bz[r + 1] = bz[r] + (D.n2 * D.m1s + B - 1) / B;
     bu[r + 1] = bu[r] + ((D.n2 + D.rows - 1) / D.rows) *
-                            ((D.n3 + kVoxelsPerThread - 1) / kVoxelsPerThread);
+                            ((D.n3 + kZSeg - 1) / kZSeg);
     n2max = std::max(n2max, D.n2);
     n3max = std::max(n3max, D.n3);
     lds_x = std::max(lds_x, 2 * ((3 * D.rows_f + 1) / 2) * D.n1);

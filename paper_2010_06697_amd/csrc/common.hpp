@@ -122,7 +122,7 @@ __host__ __device__ inline bool divergence_watch(double rp, double rd, double to
   return stall > 0 && it - ref_iter >= stall;
 }
 
-constexpr int kVoxelsPerThread = 4;  // planes per workgroup of the update tiling
+constexpr int kZSeg = 16;  // planes per workgroup of the update tiling (k_update walks them)
 // tile width that selects the register-resident x2 / x3 pass of length 256
 // (16 columns per workgroup, 16 points per thread, one LDS exchange per
 // transform); open to an axis when every cell's length along it is 256

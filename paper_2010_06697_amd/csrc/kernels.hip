@@ -104,12 +104,31 @@ __device__ __forceinline__ void grad_u_sum(P u, Q du, int V, const Stencil &s, d
   }
 }
 
-// (x2, first x3) of workgroup b of a cell in the update / mean-stress tiling
+// Order of the divergence kernel's workgroups over a cell's ny x2 positions
+// and nz x3 blocks: chunks of kZChunk x3 blocks, within a chunk the x3 block
+// fastest. A workgroup's +-x3 neighbour lines are then read by the
+// workgroups just before and after it, its +-x2 neighbours kZChunk
+// workgroups away, both within what an XCD's L2 still holds (x2 fastest put
+// the x3 neighbours a whole plane of streamed fields apart). The hardware
+// deals workgroups to the XCDs in turn and xcd_remap gives each XCD a
+// contiguous run of this order.
+constexpr int kZChunk = 16;
+__device__ __forceinline__ void chunk_order(int b, int ny, int nz, int &yg, int &zb) {
+  const int ch = b / (ny * kZChunk);
+  const int rem = b - ch * ny * kZChunk;
+  const int zl = min(kZChunk, nz - ch * kZChunk);
+  yg = rem / zl;
+  zb = ch * kZChunk + rem - yg * zl;
+}
+
+// (x2, first x3) of workgroup b of a cell in the update / mean-stress tiling:
+// R x1-lines (one x2 group) on kZSeg consecutive planes, x2 group fastest
+// (the workgroups of neighbouring x2 groups run side by side)
 __device__ __forceinline__ void column_tile(const RveDesc &D, int b, int row, int &x2, int &z0) {
   const int ny = (D.n2 + D.rows - 1) / D.rows;
-  const int zc = b / ny;
-  x2 = (b - zc * ny) * D.rows + row;
-  z0 = zc * kVoxelsPerThread;
+  const int zb = b / ny;
+  x2 = (b - zb * ny) * D.rows + row;
+  z0 = zb * kZSeg;
 }
 
 // deterministic sum of NV doubles over the workgroup; result valid in thread 0
@@ -368,7 +387,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     // folds the counts into its residual partials (a few workgroups share a
     // slot, so these atomics do not contend)
     const int g = b * R, x2 = g % n2, x3 = g / n2;
-    const int slot = a.blk_u[r] + (x3 / kVoxelsPerThread) * ((n2 + R - 1) / R) + x2 / R;
+    const int slot = a.blk_u[r] + (x3 / kZSeg) * ((n2 + R - 1) / R) + x2 / R;
     if (f) atomicAdd(&a.newton_part[slot].x, f);
     if (s) atomicAdd(&a.newton_part[slot].y, s);
   }
@@ -577,7 +596,9 @@ __global__ __launch_bounds__(kThreads) void k_local_check(KernelArgs a, IterPara
 
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
+// six waves per SIMD (what its LDS allows at 1024 x1-points): at that budget
+// the compiler issues a voxel's 73 loads in two batches rather than four
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_div_fwdx(KernelArgs a) {
   using C = typename cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -597,9 +618,11 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
   const int t = threadIdx.x, nthr = blockDim.x;
   // line rw of this workgroup: its R lines are consecutive along x3 at one x2
   // (so the +-x3 neighbours of the divergence are mostly the workgroup's own
-  // lines) when R divides n3, else consecutive rows
+  // lines, the rest those of its neighbours in the chunked order) when R
+  // divides n3, else consecutive rows
   const bool colmode = n3 % R == 0;
-  const int zc = b / n2, x2b = b - zc * n2;
+  int x2b = 0, zc = 0;
+  if (colmode) chunk_order(b, n2, n3 / R, x2b, zc);
   auto row_of = [&](int rw) { return colmode ? (zc * R + rw) * n2 + x2b : b * R + rw; };
 
   for (int w = t; w < ncl * n1; w += nthr) za[w] = C{(T)0, (T)0};
@@ -650,9 +673,13 @@ __global__ __launch_bounds__(kThreads) void k_div_fwdx(KernelArgs a) {
         for (int j = 0; j < 3; ++j) lap += (ui[o2[2 * j]] - u0) + (ui[o2[2 * j + 1]] - u0);
         bi += 0.25 * lap;
       }
+      // line ell packs into the real or imaginary part of complex line
+      // ell / 2; the part is selected by address, not by a branch, so that
+      // the three components' loads share one basic block and are issued
+      // together
       const int ell = i * R + row;
-      C *z = za + (ell >> 1) * n1 + x1;
-      if (ell & 1) z->y = (T)bi; else z->x = (T)bi;
+      T *z = reinterpret_cast<T *>(za + (ell >> 1) * n1 + x1) + (ell & 1);
+      *z = (T)bi;
     }
   }
   __syncthreads();
@@ -812,8 +839,8 @@ __global__ __launch_bounds__(kThreads) void k_poisson_z(KernelArgs a) {
 
 // ----------------------------------------------------------------------------
 // x2 and x3 passes of length 256 at the tile width kTileCol16, register
-// resident (k_col16 in double; float cells take k_colreg below, which covers
-// 256 the same way and shorter lengths too): a workgroup takes 16 columns (flattened over the cell's (x3, m1)
+// resident (k_col16; where a float launch also holds shorter lengths it is
+// k_colreg below, which covers 256 the same way): a workgroup takes 16 columns (flattened over the cell's (x3, m1)
 // for x2, (m2, m1) for x3, padding columns excluded); thread (c, j) =
 // (t % 16, t / 16) holds elements j + 16 r (r = 0..15) of column c. With
 // n = j + 16 r and k = 16 k1 + k2,
@@ -1172,7 +1199,7 @@ __global__ __launch_bounds__(kThreads) void k_null_sums(KernelArgs a) {
   double v[24];
 #pragma unroll
   for (int k = 0; k < 24; ++k) v[k] = 0.0;
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
+  for (int k = 0; k < kZSeg; ++k) {
     const int x3 = z0 + k;
     if (row >= R || x2 >= n2 || x3 >= n3) continue;
     const int idx = (x3 * n2 + x2) * n1 + x1;
@@ -1221,7 +1248,7 @@ __global__ __launch_bounds__(kThreads) void k_null_sub(KernelArgs a) {
   const int t = threadIdx.x, row = t / n1, x1 = t - row * n1;
   int x2, z0;
   column_tile(D, b, row, x2, z0);
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
+  for (int k = 0; k < kZSeg; ++k) {
     const int x3 = z0 + k;
     if (row >= R || x2 >= n2 || x3 >= n3) continue;
     const int idx = (x3 * n2 + x2) * n1 + x1;
@@ -1258,50 +1285,43 @@ __global__ __launch_bounds__(kThreads) void k_compose_u(KernelArgs a) {
 }
 
 // ----------------------------------------------------------------------------
-// Step 3 + partial sums of Step 4. A workgroup owns R x1-lines (one x2 group)
-// on kVoxelsPerThread consecutive planes: the +-x3 neighbours of its planes
-// are its own lines or the two next to them, read within the workgroup's
-// lifetime instead of a plane of streamed fields apart (which an XCD's L2
-// does not hold); the +-x2 neighbours are lines of the adjacent workgroups,
-// which run at the same time.
+// Step 3 + partial sums of Step 4, walking x3. A workgroup owns R x1-lines
+// (one x2 group, every x1) on kZSeg consecutive planes and takes the planes
+// in x3 order. Step 3 needs the central-difference gradients of two 3-vector
+// fields: double form, u_{i+1} and u_i; float form, u_{i+1} = u_i + du
+// (formed in double as it is stored) and du. Each thread keeps both at its
+// voxel on the planes x3 - 1, x3 and x3 + 1 in registers, so a plane is read
+// once (and one more at either end of the segment) instead of once for each
+// of its +-x3 neighbours; the +-x1 neighbours come from the plane's lines in
+// LDS; the +-x2 neighbours are the lines the workgroups of the adjacent x2
+// groups read for themselves at about the same time (the x2 group runs
+// fastest in the workgroup order).
 // ----------------------------------------------------------------------------
 
+// both fields at one voxel: a (double) and b (the float form keeps du in T)
+template <typename T> struct UPair {
+  double a[3];
+  T b[3];
+};
 
-// Step 3 at one voxel: grad u_{i+1} (Dn), Lambda_{i+1} written and kept as
-// stored (lamT), and the residual terms |grad u_{i+1} - F_{i+1}|^2 and
-// |grad u_{i+1} - grad u_i|^2 added to v. Double form: u_{i+1} from Step 2;
-// float form: u_{i+1} = u_i + du formed (and stored) here, its gradient as
-// the one of the stored values, the change of the gradient from du alone.
-template <typename T, typename EP>
-__device__ __forceinline__ void update_voxel(const RveDesc &D, const RveState *st, int V, int idx,
-                                             const Stencil &sn, double rho, EP Eg, T *E,
-                                             double *Dn, T *lamT, double *v) {
-  const auto un = global_view(static_cast<double *>(D.u[1 - st->cur]));
+template <typename T>
+__device__ __forceinline__ void load_pair(const RveDesc &D, const RveState *st, int V, int idx,
+                                          UPair<T> &p) {
   const auto uo = global_view(static_cast<const double *>(D.u[st->cur]));
-  const auto Lg = global_view(static_cast<T *>(D.Lam));
-  double Dd[9];
   if (kDefect<T>) {
     const auto dug = global_view(static_cast<const T *>(D.du));
-    grad_u_sum(uo, dug, V, sn, Dn);
-    grad_u(dug, V, sn, Dd);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) un[i * V + idx] = uo[i * V + idx] + (double)dug[i * V + idx];
+    for (int i = 0; i < 3; ++i) {
+      p.b[i] = dug[i * V + idx];
+      p.a[i] = uo[i * V + idx] + (double)p.b[i];
+    }
   } else {
-    double Do[9];
-    grad_u(un, V, sn, Dn);
-    grad_u(uo, V, sn, Do);
+    const auto un = global_view(static_cast<const double *>(D.u[1 - st->cur]));
 #pragma unroll
-    for (int c = 0; c < 9; ++c) Dd[c] = Dn[c] - Do[c];
-  }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    E[c] = Eg[c * V + idx];
-    const double e = st->Ebar[c] + Dn[c] - (double)E[c];
-    lamT[c] = (T)((double)Lg[c * V + idx] + rho * e);
-    Lg[c * V + idx] = lamT[c];
-    const double dd = Dd[c] + (st->Ebar[c] - st->Ebar_prev[c]);
-    v[0] += e * e;
-    v[1] += dd * dd;
+    for (int i = 0; i < 3; ++i) {
+      p.a[i] = un[i * V + idx];
+      p.b[i] = (T)uo[i * V + idx];
+    }
   }
 }
 
@@ -1317,14 +1337,10 @@ __device__ __forceinline__ void store_partials(KernelArgs &a, int blk, double *v
   }
 }
 
-// Step 3 + partial sums of Step 4. A workgroup owns R x1-lines (one x2 group)
-// on kVoxelsPerThread consecutive planes: the +-x3 neighbours of its planes
-// are its own lines or the two next to them, read within the workgroup's
-// lifetime instead of a plane of streamed fields apart (which an XCD's L2
-// does not hold); the +-x2 neighbours are lines of the adjacent workgroups,
-// which run at the same time.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
+  __shared__ double lineA[2][3][kThreads];
+  __shared__ T lineB[2][3][kThreads];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int r = find_rve(a.blk_u, a.n_rve, blk);
   const RveDesc &D = a.desc[r];
@@ -1334,20 +1350,84 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const int V = (int)D.V;
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
   const auto Eg = global_view(static_cast<const T *>(D.E));
+  const auto Lg = global_view(static_cast<T *>(D.Lam));
+  const auto un = global_view(static_cast<double *>(D.u[1 - st->cur]));
   const int t = threadIdx.x;
   const int row = t / n1, x1 = t - row * n1;
   int x2, z0;
   column_tile(D, b, row, x2, z0);
-  double v[2] = {0.0, 0.0};
+  const int nz = min(kZSeg, n3 - z0);  // uniform over the workgroup
+  const bool act = row < R && x2 < n2;
+  const int x2p = x2 + 1 >= n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
+  const int l1p = row * n1 + (x1 + 1 == n1 ? 0 : x1 + 1);
+  const int l1m = row * n1 + (x1 == 0 ? n1 - 1 : x1 - 1);
+  const double rho = st->rho;
+  UPair<T> pm, pc, pp;
 #pragma unroll
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
-    const int x3 = z0 + k;
-    if (row >= R || x2 >= n2 || x3 >= n3) continue;
+  for (int i = 0; i < 3; ++i) {
+    pc.a[i] = 0.0;
+    pc.b[i] = (T)0;
+  }
+  if (act) {
+    load_pair<T>(D, st, V, ((z0 == 0 ? n3 - 1 : z0 - 1) * n2 + x2) * n1 + x1, pm);
+    load_pair<T>(D, st, V, (z0 * n2 + x2) * n1 + x1, pc);
+  }
+  double v[2] = {0.0, 0.0};
+  for (int k = 0; k < nz; ++k) {
+    const int x3 = z0 + k, buf = k & 1;
+    // plane x3's lines for the +-x1 neighbours (two buffers: the one
+    // written here was last read two planes ago, before the barrier that
+    // every thread has since passed)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lineA[buf][i][t] = pc.a[i];
+      lineB[buf][i][t] = pc.b[i];
+    }
+    __syncthreads();
+    if (!act) continue;
     const int idx = (x3 * n2 + x2) * n1 + x1;
-    const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
-    T E[9], lam[9];
-    double Dn[9];
-    update_voxel<T>(D, st, V, idx, sn, st->rho, Eg, E, Dn, lam, v);
+    // every load of the plane before its first store (a store may alias a
+    // later load as far as the compiler knows)
+    load_pair<T>(D, st, V, ((x3 + 1 == n3 ? 0 : x3 + 1) * n2 + x2) * n1 + x1, pp);
+    UPair<T> q2p, q2m;
+    load_pair<T>(D, st, V, (x3 * n2 + x2p) * n1 + x1, q2p);
+    load_pair<T>(D, st, V, (x3 * n2 + x2m) * n1 + x1, q2m);
+    T E[9], L[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      E[c] = Eg[c * V + idx];
+      L[c] = Lg[c * V + idx];
+    }
+    // component c = 3 i + j: Dn = grad u_{i+1}, Dd its change over the
+    // iteration (float form: grad du; double form: grad u_{i+1} - grad u_i)
+    T lam[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double ap[3] = {lineA[buf][i][l1p], q2p.a[i], pp.a[i]};
+      const double am[3] = {lineA[buf][i][l1m], q2m.a[i], pm.a[i]};
+      const double bp[3] = {(double)lineB[buf][i][l1p], (double)q2p.b[i], (double)pp.b[i]};
+      const double bm[3] = {(double)lineB[buf][i][l1m], (double)q2m.b[i], (double)pm.b[i]};
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int c = 3 * i + j;
+        const double Dn = 0.5 * (ap[j] - am[j]);
+        const double gb = 0.5 * (bp[j] - bm[j]);
+        const double Dd = kDefect<T> ? gb : Dn - gb;
+        const double e = st->Ebar[c] + Dn - (double)E[c];
+        lam[c] = (T)((double)L[c] + rho * e);
+        const double dd = Dd + (st->Ebar[c] - st->Ebar_prev[c]);
+        v[0] += e * e;
+        v[1] += dd * dd;
+      }
+    }
+    if (kDefect<T>) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) un[i * V + idx] = pc.a[i];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Lg[c * V + idx] = lam[c];
+    pm = pc;
+    pc = pp;
   }
   store_partials(a, blk, v, 0, 0);
 }
@@ -1464,7 +1544,7 @@ __global__ __launch_bounds__(kThreads) void k_mean_stress(KernelArgs a) {
 #pragma unroll
   for (int k = 0; k < 18; ++k) v[k] = 0.0;
   int bad = 0;
-  for (int k = 0; k < kVoxelsPerThread; ++k) {
+  for (int k = 0; k < kZSeg; ++k) {
     const int x3 = z0 + k;
     if (row >= R || x2 >= n2 || x3 >= n3) continue;
     const int idx = (x3 * n2 + x2) * n1 + x1;
@@ -1567,7 +1647,7 @@ static void launch_fft_y(const LaunchCfg &L, const KernelArgs &a) {
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_y, 3);
   if (L.tile_y == kTileCol16) {
-    if constexpr (sizeof(T) == 4) {
+    if (sizeof(T) == 4 && !L.col256_y) {
       if (L.lds_coly > reg_lds(false, 16))
         hipLaunchKernelGGL((k_colreg<INV ? 1 : 0, 24>), grid, blk, L.lds_coly, L.stream, a);
       else
@@ -1594,7 +1674,7 @@ static void launch_poisson_z(const LaunchCfg &L, const KernelArgs &a) {
   constexpr int B = tileB<T>();
   const dim3 blk(kThreads), grid(L.nblk_z, 3);
   if (L.tile_z == kTileCol16) {
-    if constexpr (sizeof(T) == 4) {
+    if (sizeof(T) == 4 && !L.col256_z) {
       if (L.lds_colz > reg_lds(false, 16))
         hipLaunchKernelGGL((k_colreg<2, 24>), grid, blk, L.lds_colz, L.stream, a);
       else

@@ -60,6 +60,7 @@ struct LaunchCfg {
   int tile_y, tile_z;  // columns per workgroup of the x2 and x3 passes,
                        // or kTileCol16 (the register-resident pass)
   size_t lds_coly, lds_colz;  // LDS bytes of the register-resident passes
+  bool col256_y, col256_z;     // every length along x2 (x3) is 256: k_col16
   int n2max, n3max;
   size_t lds_x;  // LDS bytes of the x1-pass kernels
   bool any_lce;   // some phase uses the LCE energy
