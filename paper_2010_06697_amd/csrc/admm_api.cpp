@@ -249,6 +249,7 @@ struct admm_ctx {
   double2 *lpart_d = nullptr;
   double *fpart_d = nullptr;
   int2 *newton_part_d = nullptr;
+  unsigned *retry_d = nullptr;
   double *nullpart_d = nullptr;
   double *nullc_d = nullptr;
   std::vector<void *> owned;  // start-of-step copies and lagged directors
@@ -554,6 +555,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->mean_d);
   (void)hipFree(c->hist_d);
   (void)hipFree(c->newton_part_d);
+  (void)hipFree(c->retry_d);
   (void)hipFree(c->nullpart_d);
   (void)hipFree(c->nullc_d);
   (void)hipFree(c->lpart_d);
@@ -1057,6 +1059,8 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   INIT_TRY(hipMalloc(&c->fpart_d, sizeof(double) * 9 * (size_t)c->L.nblk_x));
   INIT_TRY(hipMalloc(&c->newton_part_d, sizeof(int2) * (size_t)c->L.nblk_x));
   INIT_TRY(hipMemset(c->newton_part_d, 0, sizeof(int2) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMalloc(&c->retry_d, sizeof(unsigned) * (kThreads / 32) * (size_t)c->L.nblk_x));
+  INIT_TRY(hipMemset(c->retry_d, 0, sizeof(unsigned) * (kThreads / 32) * (size_t)c->L.nblk_x));
   if (!fp64) {
     INIT_TRY(hipMalloc(&c->nullpart_d, sizeof(double) * 24 * (size_t)c->L.nblk_u));
     INIT_TRY(hipMalloc(&c->nullc_d, sizeof(double) * 24 * (size_t)n_rve));
@@ -1095,6 +1099,7 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   A.mean_out = c->mean_d;
   A.hist = c->hist_d;
   A.newton_part = c->newton_part_d;
+  A.retry_mask = c->retry_d;
   A.nullpart = c->nullpart_d;
   A.nullc = c->nullc_d;
   A.lpart = c->lpart_d;

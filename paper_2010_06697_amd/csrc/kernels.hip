@@ -194,8 +194,13 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // count of converged solves, which k_local_check reduces. Passes after the
 // first do nothing once the cell is done.
 // launch modes of the local step: every problem solved exactly (no inexact
-// strategy configured), the first pass of an inexact step, a later pass
-enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2 };
+// strategy configured), the first pass of an inexact step, a later pass, and
+// the exact step's second pass over the problems its first pass left to the
+// nine-component Newton method (float form without LCE phases: the first
+// pass then compiles only the closed form, at the registers that need)
+enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry = 3 };
+template <typename T, int LK, int MODE>
+constexpr bool kClosedOnly = MODE == kLocalExact && kDefect<T> && LK == 0;
 
 // LK: 0 no LCE phase, 1 the ideal LCE, 2 some term of the full LCE model
 // (non-ideality, Frank, dissipation) or the dissipation of F
@@ -205,7 +210,8 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
   const RveDesc &D = a.desc[r];
   RveState *st = a.state + r;
   if (!st->active) return;
-  const bool inexact = MODE != kLocalExact && local_inexact(ip, st);
+  const bool inexact =
+      MODE != kLocalExact && MODE != kLocalRetry && local_inexact(ip, st);
   if (MODE == kLocalLater && (!inexact || st->local_done)) return;
   const int b = blk - a.blk_x[r];
   const int n1 = D.n1, n2 = D.n2, n3 = D.n3, R = D.rows;
@@ -216,7 +222,11 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
   const int grow = b * R + row;
   int n_fail = 0, n_its = 0;
   double lsum[2] = {0.0, 0.0};  // |local residual|^2, converged
-  if (row < R && grow < nrows) {
+  // the voxels the closed form did not take: one bit per thread and workgroup
+  unsigned *retry = a.retry_mask + (size_t)blk * (kThreads / 32);
+  const bool mine = MODE != kLocalRetry || ((retry[t >> 5] >> (t & 31)) & 1u);
+  bool deferred = false;
+  if (row < R && grow < nrows && mine) {
     const double rho0 = st->rho;
     const double irho = 1.0 / rho0;
     const int x2 = grow % n2, x3 = grow / n2;
@@ -339,15 +349,30 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         NeoHooke<T> M;
         M.mu = (T)m.mu;
         M.lam = (T)m.lam;
-        rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol,
-                           MODE == kLocalExact ? nullptr : &lsum[0]);
+        // float form, exact mode: the minimiser up to one scalar; the
+        // nine-component Newton where that form does not apply, in the
+        // retry pass when the closed form is compiled alone
+        rc = -3;
+        if (MODE == kLocalExact && kDefect<T>)
+          rc = neo_closed<T>(E, At, m.mu, m.lam, rho, cap, 1e-5);
+        if (kClosedOnly<T, LK, MODE>) {
+          if (rc == -3) {
+            atomicOr(&retry[t >> 5], 1u << (t & 31));
+            deferred = true;
+            rc = 0;
+          }
+        } else if (rc == -3) {
+          rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol,
+                             MODE == kLocalExact || MODE == kLocalRetry ? nullptr : &lsum[0]);
+        }
         n_its = rc >= 0 ? rc : cap;
       }
       lsum[1] = rc >= 0 ? 1.0 : 0.0;
       n_fail = rc == -1 && !inexact;  // a pass that ends at its cap is no failure
       if (rc == -2) atomicOr(&st->domain_err, 1);
+      if (!deferred)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
+        for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
     } else {
       atomicOr(&st->domain_err, 2);  // invalid phase index
     }
@@ -401,12 +426,29 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
 template <typename T, int LK, int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(ADMM_LOCAL_WAVES_PER_EU)))
 void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
-  if (MODE != kLocalLater) {
+  if (MODE != kLocalLater && MODE != kLocalRetry) {
     local_tile<T, LK, MODE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
     return;
   }
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
-    local_tile<T, LK, MODE>(a, ip, pass, xcd_remap(lb, nblk));
+    const int blk = xcd_remap(lb, nblk);
+    if (MODE == kLocalRetry) {
+      // only workgroups with a voxel left over; their bits are cleared
+      // once every thread has read its own
+      unsigned *retry = a.retry_mask + (size_t)blk * (kThreads / 32);
+      __shared__ unsigned any;
+      if (threadIdx.x == 0) any = 0u;
+      __syncthreads();
+      if (threadIdx.x < kThreads / 32 && retry[threadIdx.x]) atomicOr(&any, 1u);
+      __syncthreads();
+      if (!any) continue;
+      local_tile<T, LK, MODE>(a, ip, pass, blk);
+      __syncthreads();
+      if (threadIdx.x < kThreads / 32) retry[threadIdx.x] = 0u;
+      __syncthreads();
+      continue;
+    }
+    local_tile<T, LK, MODE>(a, ip, pass, blk);
     __syncthreads();  // LDS of this tile read before the next one writes it
   }
 }
@@ -1700,9 +1742,13 @@ template <typename T, int LK>
 static void launch_local(const LaunchCfg &L, const KernelArgs &a, const IterParams &ip, int pass,
                          bool inexact) {
   const dim3 blk(kThreads);
-  if (!inexact)
+  if (!inexact) {
     hipLaunchKernelGGL((k_local<T, LK, kLocalExact>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, 0,
                        L.nblk_x);
+    if (kClosedOnly<T, LK, kLocalExact>)
+      hipLaunchKernelGGL((k_local<T, LK, kLocalRetry>), dim3(std::min(L.nblk_x, kLocalPassGrid)),
+                         blk, 0, L.stream, a, ip, 0, L.nblk_x);
+  }
   else if (pass == 0)
     hipLaunchKernelGGL((k_local<T, LK, kLocalFirst>), dim3(L.nblk_x), blk, 0, L.stream, a, ip, 0,
                        L.nblk_x);

@@ -29,6 +29,9 @@ struct KernelArgs {
                         // the free components of <F>
   int2 *newton_part;    // per update workgroup: failed solves and Newton iterations
                         // of the local-step workgroups in its tile
+  unsigned *retry_mask; // per local workgroup, kThreads bits: voxels the exact
+                        // pass's closed form left to the retry pass (zero between
+                        // steps)
   double *nullpart;     // per update workgroup: 24 sums of u_i chi_s (float form)
   double *nullc;        // per cell: 24 null-mode coefficients of u
   int n_rve;

@@ -443,6 +443,212 @@ __device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double 
 }
 
 // ---------------------------------------------------------------------------
+// neo-Hookean local problem up to one scalar (exact mode). phi is isotropic,
+// so its minimiser is coaxial with A: with A = U diag(a) V^T (U, V rotations,
+// det A > 0), F = U diag(f) V^T, and the stationarity
+//     m F + c F^-T = rho A,   m = mu + rho,  c = lambda ln J - mu,
+// splits into m f_i^2 - rho a_i f_i + c = 0 with the root
+//     f_i = a_i h(x_i),  h(x) = (rho + S(x)) / (2m),  S(x) = sqrt(rho^2 - 4 m c / x),
+// at the eigenvalues x_i = a_i^2 of B = A A^T (the other root sends ln J to
+// -infinity as c -> 0). gamma = c + mu = lambda ln J then solves
+//     g(gamma) = gamma - lambda (ln det A + sum_i ln h(x_i)) = 0,
+// g' = 1 + lambda sum_i 1 / (x_i S_i h_i) > 0, by Newton's method kept inside
+// a bracket (the upper end where S(x_min) stays real). F = P A with P = h(B),
+// evaluated as the quadratic that interpolates h at x_1 >= x_2 >= x_3
+// (Newton's divided differences, written in forms free of cancellation), so
+// only B's eigenvalues are needed (closed form for a symmetric 3x3 matrix).
+// Everything in double, in the displacement-gradient form: B - I, h - 1 and
+// P - I are formed without subtracting numbers near one. Returns the Newton
+// count; -2 when the warm start has det F <= 0 (as newton()); -3 where the
+// form does not apply (det A <= 0, no root below the bracket's upper end, no
+// convergence), for the caller to run the nine-component Newton instead.
+// ---------------------------------------------------------------------------
+// reciprocal and square root in double from the hardware approximations
+// (v_rcp_f64, v_rsq_f64), each refined by Newton's method: two steps for
+// the reciprocal (the relative error e becomes e^2 each), one for 1/sqrt and
+// one for sqrt itself. For x > 0, finite.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  const double q = x * r;
+  return fma(0.5 * r, fma(-q, q, x), q);
+}
+
+template <typename TG>
+__device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho, int maxit,
+                          double tol) {
+  // det of the warm start F = I + E, decided as the point evaluations decide it
+  double jm1w;
+  {
+    TG cE[9];
+    double tr, q;
+    if (!kinematics(E, cE, jm1w, tr, q)) return -2;
+  }
+  double a[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a[k] = (double)At[k];
+  // det A - 1 = tr a + s2(a) + det a
+  const double m0 = a[4] * a[8] - a[5] * a[7];
+  const double m1 = a[5] * a[6] - a[3] * a[8];
+  const double m2 = a[3] * a[7] - a[4] * a[6];
+  const double jA = (a[0] + a[4] + a[8]) + (m0 + (a[0] * a[8] - a[2] * a[6]) +
+                                            (a[0] * a[4] - a[1] * a[3])) +
+                    (a[0] * m0 + a[1] * m1 + a[2] * m2);
+  if (!(jA > -1.0)) return -3;
+  const double lnA = log1p_near1(jA);
+  // B - I = a + a^T + a a^T
+  double b[6];  // 00 11 22 01 02 12
+  {
+    const int I[6] = {0, 1, 2, 0, 0, 1}, J[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int i = I[k], j = J[k];
+      b[k] = a[3 * i + j] + a[3 * j + i] + a[3 * i] * a[3 * j] + a[3 * i + 1] * a[3 * j + 1] +
+             a[3 * i + 2] * a[3 * j + 2];
+    }
+  }
+  // eigenvalues e_1 >= e_2 >= e_3 of B - I: the roots t = 2 p cos(angle) of
+  // the deviator's characteristic cubic t^3 - 3 p2 t - det = 0 from the
+  // angle in float, then one Newton step each in double (the error goes
+  // from float's to double's; at a double root the step is skipped, and
+  // there an error in the nodes moves g and P only at second order); their
+  // sum is exact by construction
+  const double qm = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
+  const double c00 = b[0] - qm, c11 = b[1] - qm, c22 = b[2] - qm;
+  const double p2 = (c00 * c00 + c11 * c11 + c22 * c22 +
+                     2.0 * (b[3] * b[3] + b[4] * b[4] + b[5] * b[5])) * (1.0 / 6.0);
+  double e1 = qm, e2 = qm, e3 = qm;
+  if (p2 > 1e-60) {
+    const double dC = c00 * (c11 * c22 - b[5] * b[5]) - b[3] * (b[3] * c22 - b[5] * b[4]) +
+                      b[4] * (b[3] * b[5] - c11 * b[4]);
+    const float p2f = (float)p2, pf = __builtin_amdgcn_sqrtf(p2f);
+    const float r = fminf(1.0f, fmaxf(-1.0f, (float)dC * __builtin_amdgcn_rcpf(2.0f * p2f * pf)));
+    const float cpf = __cosf(acosf(r) * (1.0f / 3.0f));  // angle in [0, pi/3]
+    const float spf = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - cpf * cpf));
+    double t1 = (double)(2.0f * pf * cpf);
+    double t3 = (double)(2.0f * pf * (-0.5f * cpf - 0.8660254f * spf));  // angle + 2 pi/3
+    auto refine = [&](double &t) {
+      const double dp = 3.0 * (t * t - p2);
+      if (fabs(dp) > 1e-3 * p2) t -= (t * (t * t - 3.0 * p2) - dC) * rcp_nr(dp);
+    };
+    refine(t1);
+    refine(t3);
+    e1 = qm + t1;
+    e3 = qm + t3;
+    e2 = 3.0 * qm - e1 - e3;
+  }
+  const double x1 = 1.0 + e1, x2 = 1.0 + e2, x3 = 1.0 + e3;
+  if (!(x3 > 0.0)) return -3;
+  const double m = mu + rho, r2 = rho * rho;
+  const double xs[3] = {x1, x2, x3}, es[3] = {e1, e2, e3};
+  const double ixd[3] = {rcp_nr(x1), rcp_nr(x2), rcp_nr(x3)};
+  const double ghi = mu + r2 * x3 / (4.0 * m);  // S(x_3) real up to here
+  // gamma to float accuracy by Newton's method in float (hardware
+  // reciprocal, square root and logarithm: the step in double below removes
+  // their error too), kept inside the bracket [lo, hi] of g's sign change
+  const float lamf = (float)lam, muf = (float)mu;
+  const float r2f = (float)r2, m4f = (float)(4.0 * m), lnAf = (float)lnA;
+  const float c2f = (float)(rho + 2.0 * mu);
+  float ix[3], ef[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ix[i] = (float)ixd[i];
+    ef[i] = (float)es[i];
+  }
+  constexpr float kLn2 = 0.69314718f;
+  float lo = -INFINITY, hi = (float)ghi;
+  float gam = fminf(lamf * kLn2 * __builtin_amdgcn_logf(1.0f + (float)jm1w), 0.5f * hi);
+  int it = 0;
+  bool done = false;
+  for (; it < maxit; ++it) {
+    float Sf[3], df[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Sf[i] = __builtin_amdgcn_sqrtf(fmaxf(0.0f, r2f - m4f * (gam - muf) * ix[i]));
+      df[i] = -2.0f * (gam + muf * ef[i]) * ix[i] * __builtin_amdgcn_rcpf(Sf[i] + c2f);
+    }
+    const float dp = df[0] + df[1] + df[2] + (df[0] * df[1] + df[0] * df[2] + df[1] * df[2]) +
+                     df[0] * df[1] * df[2];
+    const float g = gam - lamf * (lnAf + kLn2 * __builtin_amdgcn_logf(1.0f + dp));
+    if (g > 0.0f) hi = gam; else lo = gam;
+    const float gp = 1.0f + lamf * (ix[0] * __builtin_amdgcn_rcpf(Sf[0] * (1.0f + df[0])) +
+                                    ix[1] * __builtin_amdgcn_rcpf(Sf[1] * (1.0f + df[1])) +
+                                    ix[2] * __builtin_amdgcn_rcpf(Sf[2] * (1.0f + df[2])));
+    const float step = g * __builtin_amdgcn_rcpf(gp);
+    if (fabsf(step) <= (float)tol * (1.0f + fabsf(gam))) {
+      gam -= step;
+      done = true;
+      ++it;
+      break;
+    }
+    float nx = gam - step;
+    if (!(nx > lo && nx < hi)) nx = lo == -INFINITY ? gam - 2.0f * fabsf(step) - 1.0f : 0.5f * (lo + hi);
+    gam = nx;
+  }
+  if (!done) return -3;
+  // one Newton step in double from there (the error goes from float's to
+  // its square), with S_i and h_i - 1 carried to the new gamma to first
+  // order (dS/dgamma = -2m / (x S), dh/dgamma = -1 / (x S))
+  double G = (double)gam;
+  double S[3], d[3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    S[i] = sqrt_nr(r2 - 4.0 * m * (G - mu) * ixd[i]);
+    d[i] = -2.0 * (G + mu * es[i]) * ixd[i] * rcp_nr(S[i] + rho + 2.0 * mu);
+    w[i] = ixd[i] * rcp_nr(S[i]);  // -dh_i/dgamma
+  }
+  {
+    const double dp = d[0] + d[1] + d[2] + (d[0] * d[1] + d[0] * d[2] + d[1] * d[2]) +
+                      d[0] * d[1] * d[2];
+    const double g = G - lam * (lnA + log1p_near1(dp));
+    const double sw = w[0] * rcp_nr(1.0 + d[0]) + w[1] * rcp_nr(1.0 + d[1]) +
+                      w[2] * rcp_nr(1.0 + d[2]);
+    const double delta = -g * rcp_nr(1.0 + lam * sw);
+    G += delta;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      S[i] -= 2.0 * m * w[i] * delta;
+      d[i] -= w[i] * delta;
+    }
+  }
+  if (!(G < ghi)) return -3;
+  // P - I = (h_1 - 1) I + h[x1,x2] (B - x1 I) + h[x1,x2,x3] (B - x1 I)(B - x2 I)
+  const double km = 2.0 * (G - mu);  // 4 m c / (2 m)
+  const double i12 = ixd[0] * ixd[1] * rcp_nr(S[0] + S[1]);
+  const double h12 = km * i12;
+  const double h123 = -km * i12 * ixd[2] * rcp_nr(S[1] + S[2]) *
+                      (S[1] + (r2 * (x1 + x3) - 2.0 * m * km) * rcp_nr(x3 * S[2] + x1 * S[0]));
+  // C1 = B - x1 I, C2 = B - x2 I (symmetric, in the order of b)
+  const double C1[6] = {b[0] - e1, b[1] - e1, b[2] - e1, b[3], b[4], b[5]};
+  const double C2[6] = {b[0] - e2, b[1] - e2, b[2] - e2, b[3], b[4], b[5]};
+  auto sym = [](const double *M, int i, int j) {
+    return i == j ? M[i] : M[i + j + 2];  // (0,1) -> 3, (0,2) -> 4, (1,2) -> 5
+  };
+  double Pm[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double q = sym(C1, i, 0) * sym(C2, 0, j) + sym(C1, i, 1) * sym(C2, 1, j) +
+                       sym(C1, i, 2) * sym(C2, 2, j);
+      Pm[3 * i + j] = (i == j ? d[0] : 0.0) + h12 * sym(C1, i, j) + h123 * q;
+    }
+  // E = F - I = (P - I) + (P - I) a + a
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      E[3 * i + j] = (TG)(Pm[3 * i + j] + a[3 * i + j] +
+                          (Pm[3 * i] * a[j] + Pm[3 * i + 1] * a[3 + j] + Pm[3 * i + 2] * a[6 + j]));
+  return it;
+}
+
+// ---------------------------------------------------------------------------
 // director: the unit top eigenvector of F F^T (double), cyclic Jacobi on the
 // symmetric 3x3 matrix; sign chosen so that n . n_prev >= 0; when the top
 // eigenvalue is degenerate (relative gap <= 1e-12) every unit vector of the

@@ -84,6 +84,49 @@ def test_local_step_matches_oracle(shape, precision):
     assert err <= (1e-12 if precision == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_local_step_with_negative_det_data(precision):
+    """Data A = grad u + Lambda/rho with det A < 0 on a third of the voxels
+    (A_33 pushed below zero through Lambda): the float exact step's closed
+    form (coaxial minimiser, det A > 0 only) leaves those voxels to the
+    nine-component Newton of a second pass over the workgroups that have
+    any; both kinds of voxel, in both precisions, match the oracle's prox
+    from the same inputs and warm start (Sec. 2.1, Step 1)."""
+    shape = (12, 16, 24)
+    say("local step, det A < 0 on a third of the voxels", precision)
+    phase = M.random_two_phase(shape, 0.5, seed=14)
+    Fbar = M.random_fbar(0.04, seed=15)
+    u, F, L = random_state(shape, seed=16)
+    rho = 12.0
+    rng = np.random.default_rng(17)
+    neg = rng.random(shape) < 1.0 / 3.0
+    L[8][neg] = -rho * rng.uniform(1.2, 1.6, size=int(neg.sum()))
+    s = gpu_solver([phase], MATS, [Fbar], precision, rho0=rho)
+    s.set_state(0, u=u, F=F, Lambda=L)
+    st0 = s.state(0)
+    s.local_step()
+    got = s.state(0)["F"]
+    it, status, nfail, newton_its = s.info(0)
+    s.close()
+    assert nfail == 0
+    G = O.gradient(st0["u"], Fbar.ravel())
+    A = G + st0["Lambda"] / rho
+    detA = np.linalg.det(np.moveaxis(A.reshape((3, 3) + shape), (0, 1), (-2, -1)))
+    assert (detA < 0).sum() >= neg.sum() // 2
+    om = omats(MATS)
+    ref = np.empty_like(got)
+    for x in np.ndindex(shape):
+        Fx, _, _, rc = O.prox(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x],
+                              opts=O.newton_opts(**NEWTON64))
+        assert rc == O.OK
+        ref[(slice(None),) + x] = Fx
+    detF = np.linalg.det(np.moveaxis(got.reshape((3, 3) + shape), (0, 1), (-2, -1)))
+    assert detF.min() > 0.0
+    err = np.max(np.abs(got - ref))
+    say("  max |F - F_oracle| =", err)
+    assert err <= (1e-12 if precision == "fp64" else 1e-6)
+
+
 @pytest.mark.parametrize("shape", SHAPES[:3])
 def test_update_matches_definition(shape):
     say("update", shape)
@@ -268,12 +311,14 @@ def test_set_load_warm_start_and_load_path():
     assert rel(st["u"], u) <= 1e-10 and rel(st["F"], F) <= 1e-10 and rel(st["Lambda"], L) <= 1e-10
 
 
-def test_domain_error_is_reported():
-    """A load with det F <= 0 reachable in one Newton step is flagged, not hidden."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_domain_error_is_reported(precision):
+    """A warm start with det F <= 0 is flagged, not hidden (both the Newton
+    solve and the float step's closed form check it first)."""
     shape = (8, 8, 8)
-    say("domain error", shape)
+    say("domain error", shape, precision)
     phase = np.zeros(shape, np.uint8)
-    s = gpu_solver([phase], [M.neohooke(1.0, 1.0)], [np.eye(3)], "fp64", rho0=5.0)
+    s = gpu_solver([phase], [M.neohooke(1.0, 1.0)], [np.eye(3)], precision, rho0=5.0)
     F = np.zeros((9,) + shape)
     F[0] = F[4] = 1.0
     F[8] = -0.5  # det F < 0 as warm start
