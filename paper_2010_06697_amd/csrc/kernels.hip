@@ -197,7 +197,9 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // strategy configured), the first pass of an inexact step, a later pass, and
 // the exact step's second pass over the problems its first pass left to the
 // nine-component Newton method (float form without LCE phases: the first
-// pass then compiles only the closed form, at the registers that need)
+// pass then compiles only the neo-Hookean closed form, at the registers
+// that need). The double form keeps the Newton solve, whose stopping rule
+// its parity bounds are set against.
 enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry = 3 };
 template <typename T, int LK, int MODE>
 constexpr bool kClosedOnly = MODE == kLocalExact && kDefect<T> && LK == 0;

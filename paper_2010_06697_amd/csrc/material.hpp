@@ -17,6 +17,9 @@
 // (Fi = F^-1), a Cholesky factorisation (steepest descent when it is not
 // positive definite) and backtracking (Armijo on phi, or on |grad phi| once
 // the predicted decrease is below phi's rounding floor), rejecting det F <= 0.
+// The float form's exact step solves the neo-Hookean problem in closed form
+// up to one scalar instead (neo_closed), the LCE's ideal model in A's
+// singular basis (lce_spectral).
 //
 // Precision: J - 1, ln J and phi are double in both modes. The iterate, the
 // stress and the gradient are TG, the tangent, its factorisation and the
