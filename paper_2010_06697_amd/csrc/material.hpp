@@ -481,6 +481,11 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   const double q = x * r;
   return fma(0.5 * r, fma(-q, q, x), q);
 }
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
 
 template <typename TG>
 __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho, int maxit,
@@ -668,29 +673,33 @@ __device__ __forceinline__ void jacobi3(double *B, double *Vv) {
     if (off <= 1e-34 * dia || off == 0.0) break;
 #pragma unroll
     for (int pq = 0; pq < 3; ++pq) {
-      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2, r = 3 - p - q;
       const double bpq = B[3 * p + q];
-      if (bpq == 0.0) continue;
-      const double theta = (B[3 * q + q] - B[3 * p + p]) / (2.0 * bpq);
-      const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double bkp = B[3 * k + p], bkq = B[3 * k + q];
-        B[3 * k + p] = c * bkp - sn * bkq;
-        B[3 * k + q] = sn * bkp + c * bkq;
+      // (a rotation by an angle below 1e-30 changes nothing in double)
+      if (!(fabs(bpq) > 1e-30 * (fabs(B[3 * p + p]) + fabs(B[3 * q + q])))) continue;
+      // the rotation's tangent t = sign(theta) / (|theta| + sqrt(theta^2 + 1))
+      // (1 / (2 theta) where theta^2 would overflow), cosine and sine, on the
+      // refined hardware reciprocal and square roots; B stays symmetric and
+      // is updated in the form with tau = s / (1 + c) (B_pq becomes zero)
+      const double theta = (B[3 * q + q] - B[3 * p + p]) * rcp_nr(2.0 * bpq);
+      const double at = fabs(theta);
+      const double t = at > 1e100 ? 0.5 * rcp_nr(theta)
+                                  : (theta >= 0 ? 1.0 : -1.0) * rcp_nr(at + sqrt_nr(fma(theta, theta, 1.0)));
+      const double c = rsqrt_nr(fma(t, t, 1.0)), sn = t * c;
+      const double tau = sn * rcp_nr(1.0 + c);
+      B[3 * p + p] -= t * bpq;
+      B[3 * q + q] += t * bpq;
+      B[3 * p + q] = B[3 * q + p] = 0.0;
+      {
+        const double g = B[3 * r + p], h = B[3 * r + q];
+        B[3 * r + p] = B[3 * p + r] = g - sn * (h + g * tau);
+        B[3 * r + q] = B[3 * q + r] = h + sn * (g - h * tau);
       }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double bpk = B[3 * p + k], bqk = B[3 * q + k];
-        B[3 * p + k] = c * bpk - sn * bqk;
-        B[3 * q + k] = sn * bpk + c * bqk;
-      }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double vkp = Vv[3 * k + p], vkq = Vv[3 * k + q];
-        Vv[3 * k + p] = c * vkp - sn * vkq;
-        Vv[3 * k + q] = sn * vkp + c * vkq;
+        const double g = Vv[3 * k + p], h = Vv[3 * k + q];
+        Vv[3 * k + p] = g - sn * (h + g * tau);
+        Vv[3 * k + q] = h + sn * (g - h * tau);
       }
     }
   }
