@@ -250,6 +250,7 @@ struct admm_ctx {
   double *fpart_d = nullptr;
   int2 *newton_part_d = nullptr;
   unsigned *retry_d = nullptr;
+  void *at_d = nullptr;  // RveDesc::At of every cell (float form, no LCE)
   double *nullpart_d = nullptr;
   double *nullc_d = nullptr;
   std::vector<void *> owned;  // start-of-step copies and lagged directors
@@ -294,6 +295,7 @@ int snapshot_step(admm_ctx *c) {
 }
 
 int upload_states(admm_ctx *c) {
+  for (auto &s : c->state_h) s.at_rho = 0.0;  // Step 1 reads the caller's fields
   HIP_TRY(hipMemcpyAsync(c->state_d, c->state_h.data(), sizeof(RveState) * c->n_rve,
                          hipMemcpyHostToDevice, c->stream));
   return ADMM_OK;
@@ -556,6 +558,7 @@ void free_ctx(admm_ctx *c) {
   (void)hipFree(c->hist_d);
   (void)hipFree(c->newton_part_d);
   (void)hipFree(c->retry_d);
+  (void)hipFree(c->at_d);
   (void)hipFree(c->nullpart_d);
   (void)hipFree(c->nullc_d);
   (void)hipFree(c->lpart_d);
@@ -973,6 +976,19 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   // the spectra's padding columns stay zero: no kernel writes them but the
   // x3 pass, which maps zero to zero there
   INIT_TRY(hipMemset(c->workspace, 0, spec_off));
+  // float form without LCE phases or dissipation of F: Step 1's data as the
+  // update forms it (9 floats per voxel), read by the next local step at the
+  // same penalty instead of the stencil gradient of u and Lambda
+  if (!fp64 && !any_lce && !any_ext) {
+    size_t tot = 0;
+    for (const RveDesc &D : c->desc_h) tot += 9 * (size_t)D.V;
+    INIT_TRY(hipMalloc(&c->at_d, tot * sizeof(float)));
+    size_t off = 0;
+    for (RveDesc &D : c->desc_h) {
+      D.At = static_cast<float *>(c->at_d) + off;
+      off += 9 * (size_t)D.V;
+    }
+  }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   c->L.timer = nullptr;
   c->L.any_lce = any_lce;

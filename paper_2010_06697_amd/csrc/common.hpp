@@ -74,6 +74,10 @@ struct RveDesc {
   void *dir_step;           // directors at the start of the load step (nu_n) or null
   void *E_step;             // F - I at the start of the load step (nu_F) or null
   void *spec;               // 9 spectral components, layout [c][x3][x2][m1]
+  void *At;                 // float form without LCE phases: Step 1's data
+                            // A - I = grad u + Ebar + Lambda/rho of the next
+                            // iteration as the update formed it (9V float),
+                            // valid while RveState::at_rho is the penalty; else null
 };
 
 // per-cell iteration state, updated on the device
@@ -99,6 +103,10 @@ struct RveState {
   int pad3;
   double best_merit;    // divergence watch: smallest merit of the load step
   double ref_merit;     // divergence watch: merit at ref_iter
+  double at_rho;        // penalty RveDesc::At was formed with by the last
+                        // update (0: not formed in this call; reset by every
+                        // state upload, so fields the caller wrote in between
+                        // are read afresh)
 };
 
 // Divergence / stagnation watch of admm_solve, applied after each

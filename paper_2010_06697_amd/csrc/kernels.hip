@@ -238,12 +238,22 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     const auto Lg = global_view(static_cast<const T *>(D.Lam));
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     T E[9], At[9];
-    double A[9];
-    grad_u(u, V, sn, A);
+    if (kClosedOnly<T, LK, MODE> && D.At && st->at_rho == rho0) {
+      // the update formed this data at this penalty, from the same values
+      const auto Ag = global_view(static_cast<const T *>(D.At));
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      E[c] = Eg[c * V + idx];
-      At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
+      for (int c = 0; c < 9; ++c) {
+        E[c] = Eg[c * V + idx];
+        At[c] = Ag[c * V + idx];
+      }
+    } else {
+      double A[9];
+      grad_u(u, V, sn, A);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        E[c] = Eg[c * V + idx];
+        At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
+      }
     }
     const auto phg = global_view(D.phase);
     const int ph = phg[idx];
@@ -1396,6 +1406,7 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const auto Eg = global_view(static_cast<const T *>(D.E));
   const auto Lg = global_view(static_cast<T *>(D.Lam));
   const auto un = global_view(static_cast<double *>(D.u[1 - st->cur]));
+  const auto Ag = D.At ? global_view(static_cast<T *>(D.At)) : nullptr;
   const int t = threadIdx.x;
   const int row = t / n1, x1 = t - row * n1;
   int x2, z0;
@@ -1405,7 +1416,7 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
   const int x2p = x2 + 1 >= n2 ? 0 : x2 + 1, x2m = x2 == 0 ? n2 - 1 : x2 - 1;
   const int l1p = row * n1 + (x1 + 1 == n1 ? 0 : x1 + 1);
   const int l1m = row * n1 + (x1 == 0 ? n1 - 1 : x1 - 1);
-  const double rho = st->rho;
+  const double rho = st->rho, irho = 1.0 / rho;
   UPair<T> pm, pc, pp;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -1459,6 +1470,9 @@ __global__ __launch_bounds__(kThreads) void k_update(KernelArgs a) {
         const double Dd = kDefect<T> ? gb : Dn - gb;
         const double e = st->Ebar[c] + Dn - (double)E[c];
         lam[c] = (T)((double)L[c] + rho * e);
+        // Step 1's data of the next iteration at this penalty, formed as the
+        // local step forms it (same operands, same order of operations)
+        if (kDefect<T> && Ag) Ag[c * V + idx] = (T)(Dn + st->Ebar[c] + (double)lam[c] * irho);
         const double dd = Dd + (st->Ebar[c] - st->Ebar_prev[c]);
         v[0] += e * e;
         v[1] += dd * dd;
@@ -1529,6 +1543,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
   st->rp = rp;
   st->rd = rd;
   st->rho_used = rho;
+  st->at_rho = a.desc[r].At ? rho : 0.0;
   st->iter = it + 1;
   st->cur ^= 1;
   if (st->domain_err || !(rp == rp) || !(rd == rd)) {
