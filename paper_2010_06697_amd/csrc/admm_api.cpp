@@ -295,7 +295,10 @@ int snapshot_step(admm_ctx *c) {
 }
 
 int upload_states(admm_ctx *c) {
-  for (auto &s : c->state_h) s.at_rho = 0.0;  // Step 1 reads the caller's fields
+  for (auto &s : c->state_h) {
+    s.at_rho = 0.0;  // Step 1 reads the caller's fields
+    s.n_retry = 0;   // (no retry bit survives a retry pass)
+  }
   HIP_TRY(hipMemcpyAsync(c->state_d, c->state_h.data(), sizeof(RveState) * c->n_rve,
                          hipMemcpyHostToDevice, c->stream));
   return ADMM_OK;

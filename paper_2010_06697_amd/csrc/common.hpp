@@ -99,7 +99,8 @@ struct RveState {
   double Ebar_prev[9];  // <F> - I of the previous iterate (r_d)
   unsigned free_mask;   // bit k: component k of <F> free (mixed conditions)
   int ref_iter;         // divergence watch: iteration of the last halving
-  int pad2;
+  int n_retry;          // voxels the exact local pass left to its retry pass
+                        // (cleared by k_finalize)
   int pad3;
   double best_merit;    // divergence watch: smallest merit of the load step
   double ref_merit;     // divergence watch: merit at ref_iter

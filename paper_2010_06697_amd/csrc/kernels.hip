@@ -370,6 +370,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         if (kClosedOnly<T, LK, MODE>) {
           if (rc == -3) {
             atomicOr(&retry[t >> 5], 1u << (t & 31));
+            atomicAdd(&st->n_retry, 1);
             deferred = true;
             rc = 0;
           }
@@ -445,8 +446,9 @@ void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
     const int blk = xcd_remap(lb, nblk);
     if (MODE == kLocalRetry) {
-      // only workgroups with a voxel left over; their bits are cleared
-      // once every thread has read its own
+      // only cells with a voxel left over, and of those only workgroups with
+      // one; their bits are cleared once every thread has read its own
+      if (a.state[find_rve(a.blk_x, a.n_rve, blk)].n_retry == 0) continue;
       unsigned *retry = a.retry_mask + (size_t)blk * (kThreads / 32);
       __shared__ unsigned any;
       if (threadIdx.x == 0) any = 0u;
@@ -1544,6 +1546,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
   st->rd = rd;
   st->rho_used = rho;
   st->at_rho = a.desc[r].At ? rho : 0.0;
+  st->n_retry = 0;  // the local step's retry pass has run
   st->iter = it + 1;
   st->cur ^= 1;
   if (st->domain_err || !(rp == rp) || !(rd == rd)) {

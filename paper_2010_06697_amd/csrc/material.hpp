@@ -487,15 +487,45 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return r * fma(-0.5 * x * r, r, 1.5);
 }
 
+// log1p_near1 with the division on the refined reciprocal
+__device__ __forceinline__ double log1p_near1_nr(double x) {
+  if (x > -0.2 && x < 0.25) {
+    const double s = x * rcp_nr(2.0 + x);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    return 2.0 * s * p;
+  }
+  return log1p(x);
+}
+
 template <typename TG>
 __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho, int maxit,
                           double tol) {
-  // det of the warm start F = I + E, decided as the point evaluations decide it
+  // det of the warm start F = I + E, minus 1, by kinematics()'s formulas
+  // (admissibility decided as the point evaluations decide it), without the
+  // cofactor
   double jm1w;
   {
-    TG cE[9];
-    double tr, q;
-    if (!kinematics(E, cE, jm1w, tr, q)) return -2;
+    double e[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e[k] = (double)E[k];
+    const double c0 = e[4] * e[8] - e[5] * e[7];
+    const double c1 = e[5] * e[6] - e[3] * e[8];
+    const double c2 = e[3] * e[7] - e[4] * e[6];
+    const double c4 = e[0] * e[8] - e[2] * e[6];
+    const double c8 = e[0] * e[4] - e[1] * e[3];
+    const double tr = e[0] + e[4] + e[8];
+    jm1w = tr + ((c0 + c4 + c8) + (e[0] * c0 + e[1] * c1 + e[2] * c2));
+    if (!(1.0 + jm1w > 0.0)) return -2;
   }
   double a[9];
 #pragma unroll
@@ -508,7 +538,7 @@ __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho
                                             (a[0] * a[4] - a[1] * a[3])) +
                     (a[0] * m0 + a[1] * m1 + a[2] * m2);
   if (!(jA > -1.0)) return -3;
-  const double lnA = log1p_near1(jA);
+  const double lnA = log1p_near1_nr(jA);
   // B - I = a + a^T + a a^T
   double b[6];  // 00 11 22 01 02 12
   {
@@ -613,7 +643,7 @@ __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho
   {
     const double dp = d[0] + d[1] + d[2] + (d[0] * d[1] + d[0] * d[2] + d[1] * d[2]) +
                       d[0] * d[1] * d[2];
-    const double g = G - lam * (lnA + log1p_near1(dp));
+    const double g = G - lam * (lnA + log1p_near1_nr(dp));
     const double sw = w[0] * rcp_nr(1.0 + d[0]) + w[1] * rcp_nr(1.0 + d[1]) +
                       w[2] * rcp_nr(1.0 + d[2]);
     const double delta = -g * rcp_nr(1.0 + lam * sw);
