@@ -443,6 +443,16 @@ void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
     local_tile<T, LK, MODE>(a, ip, pass, xcd_remap(blockIdx.x, gridDim.x));
     return;
   }
+  if (MODE == kLocalRetry) {
+    // nothing left over in any cell (the usual case): one round trip
+    __shared__ int any_cell;
+    if (threadIdx.x == 0) any_cell = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < a.n_rve; r += blockDim.x)
+      if (a.state[r].n_retry) any_cell = 1;
+    __syncthreads();
+    if (!any_cell) return;
+  }
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
     const int blk = xcd_remap(lb, nblk);
     if (MODE == kLocalRetry) {
