@@ -1141,7 +1141,7 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
     const double q0 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
     const double q1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
     const bool use0 = q0 > q1;
-    const double inv = 1.0 / sqrt(use0 ? q0 : q1);
+    const double inv = rsqrt_nr(use0 ? q0 : q1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) u[3 + k] = (use0 ? r0[k] : r1[k]) * inv;
   }
@@ -1164,11 +1164,11 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
 #pragma unroll
       for (int J = 0; J < 3; ++J) v[3 + J] -= c * v[J];
     }
-    const double ai = sqrt(v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
+    const double ai = sqrt_nr(v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
                            v[3 * i + 2] * v[3 * i + 2]);
     if (!(ai > 0.0)) return -2;
     H.a[i] = ai;
-    const double inv = 1.0 / ai;
+    const double inv = rcp_nr(ai);
 #pragma unroll
     for (int J = 0; J < 3; ++J) v[3 * i + J] *= inv;
   }
@@ -1201,13 +1201,15 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
     for (int i = 0; i < 3; ++i) f[i] = fa[i];
   }
   const double smod = mua + kap + rho;
-  const double na = sqrt(H.a[0] * H.a[0] + H.a[1] * H.a[1] + H.a[2] * H.a[2]);
+  const double na = sqrt_nr(H.a[0] * H.a[0] + H.a[1] * H.a[1] + H.a[2] * H.a[2]);
   int ret = -1;
   for (int it = 0; it < maxit; ++it) {
     double g[3];
     H.grad(f, g);
-    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    // norms, the Cholesky factor and the solves on the refined hardware
+    // square roots and reciprocals
+    const double gn = sqrt_nr(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double nf = sqrt_nr(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
     if (gn <= gtol * smod * (1.0 + nf + na)) {
       ret = it;
       break;
@@ -1219,34 +1221,35 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
     const double o10 = kap * (p1 * p0 + Jm1 * f[2]);
     const double o20 = kap * (p2 * p0 + Jm1 * f[1]);
     const double o21 = kap * (p2 * p1 + Jm1 * f[0]);
-    double tau = 0.0, l00 = 0.0, l10 = 0.0, l20 = 0.0, l11 = 0.0, l21 = 0.0, l22 = 0.0;
+    // (i00, i11, i22: reciprocals of the factor's diagonal)
+    double tau = 0.0, i00 = 0.0, l10 = 0.0, l20 = 0.0, i11 = 0.0, l21 = 0.0, i22 = 0.0;
     bool pd = false;
     for (int tries = 0; tries < 64 && !pd; ++tries) {
       const double e0 = d00 + tau;
       pd = e0 > 0.0;
       if (pd) {
-        l00 = sqrt(e0);
-        l10 = o10 / l00;
-        l20 = o20 / l00;
+        i00 = rsqrt_nr(e0);
+        l10 = o10 * i00;
+        l20 = o20 * i00;
         const double e1 = d11 + tau - l10 * l10;
         pd = e1 > 0.0;
         if (pd) {
-          l11 = sqrt(e1);
-          l21 = (o21 - l20 * l10) / l11;
+          i11 = rsqrt_nr(e1);
+          l21 = (o21 - l20 * l10) * i11;
           const double e2 = d22 + tau - l20 * l20 - l21 * l21;
           pd = e2 > 0.0;
-          if (pd) l22 = sqrt(e2);
+          if (pd) i22 = rsqrt_nr(e2);
         }
       }
       if (!pd) tau = tau == 0.0 ? 0.0625 * rho : 2.0 * tau;
     }
     if (!pd) break;
-    const double y0 = -g[0] / l00, y1 = (-g[1] - l10 * y0) / l11;
-    const double y2 = (-g[2] - l20 * y0 - l21 * y1) / l22;
+    const double y0 = -g[0] * i00, y1 = (-g[1] - l10 * y0) * i11;
+    const double y2 = (-g[2] - l20 * y0 - l21 * y1) * i22;
     double d[3];
-    d[2] = y2 / l22;
-    d[1] = (y1 - l21 * d[2]) / l11;
-    d[0] = (y0 - l10 * d[1] - l20 * d[2]) / l00;
+    d[2] = y2 * i22;
+    d[1] = (y1 - l21 * d[2]) * i11;
+    d[0] = (y0 - l10 * d[1] - l20 * d[2]) * i00;
     const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
     const bool small = -slope <= 1e-12 * smod * (1.0 + nf * nf);
     const double h0 = small ? 0.0 : H.h(f);
@@ -1261,7 +1264,7 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
         } else {
           double gt[3];
           H.grad(ft, gt);
-          acc = sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]) <= (1.0 - 1e-4 * t) * gn;
+          acc = sqrt_nr(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]) <= (1.0 - 1e-4 * t) * gn;
         }
       }
       if (!acc) t *= 0.5;
@@ -1269,8 +1272,8 @@ __device__ int lce_spectral(T *E, const T *Am, double mua, double beta, double k
     if (!acc) break;
 #pragma unroll
     for (int i = 0; i < 3; ++i) f[i] = ft[i];
-    const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double nd = sqrt_nr(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    nf = sqrt_nr(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
     if (t == 1.0 && nd <= step_tol * fmax(nf, 1.0)) {
       ret = it + 1;
       break;
