@@ -201,6 +201,7 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // that need). The double form keeps the Newton solve, whose stopping rule
 // its parity bounds are set against.
 enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry = 3 };
+static_assert(kThreads / 32 == 8, "the retry pass reads a workgroup's bits as two uint4");
 template <typename T, int LK, int MODE>
 constexpr bool kClosedOnly = MODE == kLocalExact && kDefect<T> && LK == 0;
 
@@ -452,26 +453,35 @@ void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
       if (a.state[r].n_retry) any_cell = 1;
     __syncthreads();
     if (!any_cell) return;
+    // each thread looks at one logical workgroup's retry bits, kThreads
+    // workgroups per round; the marked ones are solved one after the other
+    // and their bits cleared once every thread has read its own
+    __shared__ int list[kThreads];
+    __shared__ int cnt;
+    for (int base = blockIdx.x * kThreads; base < nblk; base += gridDim.x * kThreads) {
+      if (threadIdx.x == 0) cnt = 0;
+      __syncthreads();
+      const int lb = base + (int)threadIdx.x;
+      if (lb < nblk) {
+        const uint4 *w = reinterpret_cast<const uint4 *>(a.retry_mask + (size_t)lb * (kThreads / 32));
+        const uint4 w0 = w[0], w1 = w[1];
+        if (w0.x | w0.y | w0.z | w0.w | w1.x | w1.y | w1.z | w1.w) list[atomicAdd(&cnt, 1)] = lb;
+      }
+      __syncthreads();
+      const int n = cnt;
+      for (int q = 0; q < n; ++q) {
+        const int blk = list[q];
+        local_tile<T, LK, MODE>(a, ip, pass, blk);
+        __syncthreads();
+        if (threadIdx.x < kThreads / 32) a.retry_mask[(size_t)blk * (kThreads / 32) + threadIdx.x] = 0u;
+        __syncthreads();
+      }
+      __syncthreads();  // every thread has read cnt before the next round resets it
+    }
+    return;
   }
   for (int lb = blockIdx.x; lb < nblk; lb += gridDim.x) {
     const int blk = xcd_remap(lb, nblk);
-    if (MODE == kLocalRetry) {
-      // only cells with a voxel left over, and of those only workgroups with
-      // one; their bits are cleared once every thread has read its own
-      if (a.state[find_rve(a.blk_x, a.n_rve, blk)].n_retry == 0) continue;
-      unsigned *retry = a.retry_mask + (size_t)blk * (kThreads / 32);
-      __shared__ unsigned any;
-      if (threadIdx.x == 0) any = 0u;
-      __syncthreads();
-      if (threadIdx.x < kThreads / 32 && retry[threadIdx.x]) atomicOr(&any, 1u);
-      __syncthreads();
-      if (!any) continue;
-      local_tile<T, LK, MODE>(a, ip, pass, blk);
-      __syncthreads();
-      if (threadIdx.x < kThreads / 32) retry[threadIdx.x] = 0u;
-      __syncthreads();
-      continue;
-    }
     local_tile<T, LK, MODE>(a, ip, pass, blk);
     __syncthreads();  // LDS of this tile read before the next one writes it
   }
