@@ -127,6 +127,36 @@ def test_local_step_with_negative_det_data(precision):
     assert err <= (1e-12 if precision == "fp64" else 1e-6)
 
 
+def test_fields_written_between_calls_are_read():
+    """Within a call the float form's local step reads its data as the
+    previous update formed it; a call must still start from the fields the
+    caller holds. Four iterations, then new u, F and Lambda written into the
+    caller's buffers and three more iterations: bit for bit the result of a
+    fresh context started from those fields (fixed penalty, so the contexts'
+    histories do not matter)."""
+    shape = (16, 12, 24)
+    say("fields written between calls")
+    phase = M.random_two_phase(shape, 0.5, seed=31)
+    Fbar = M.random_fbar(0.04, seed=32)
+    u1, F1, L1 = random_state(shape, seed=33)
+    u2, F2, L2 = random_state(shape, seed=34)
+    kw = dict(rho0=6.0, adapt_rho=0, mu_ref=4.0, div_growth=0.0, stall_iters=0)
+    s = gpu_solver([phase], MATS, [Fbar], "fp32", **kw)
+    s.set_state(0, u=u1, F=F1, Lambda=L1)
+    s.step(4)
+    s.set_state(0, u=u2, F=F2, Lambda=L2)
+    s.step(3)
+    a = s.state(0)
+    s.close()
+    s = gpu_solver([phase], MATS, [Fbar], "fp32", **kw)
+    s.set_state(0, u=u2, F=F2, Lambda=L2)
+    s.step(3)
+    b = s.state(0)
+    s.close()
+    for k in ("u", "F", "Lambda"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("shape", SHAPES[:3])
 def test_update_matches_definition(shape):
     say("update", shape)
