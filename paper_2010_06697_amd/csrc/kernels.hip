@@ -453,19 +453,21 @@ void k_local(KernelArgs a, IterParams ip, int pass, int nblk) {
       if (a.state[r].n_retry) any_cell = 1;
     __syncthreads();
     if (!any_cell) return;
-    // each thread looks at one logical workgroup's retry bits, kThreads
-    // workgroups per round; the marked ones are solved one after the other
-    // and their bits cleared once every thread has read its own
+    // this workgroup's logical workgroups are blockIdx.x, blockIdx.x +
+    // gridDim.x, ... (as in a later inexact pass); each thread looks at one
+    // of them, kThreads per round, and the marked ones are solved one after
+    // the other, their bits cleared once every thread has read its own
     __shared__ int list[kThreads];
     __shared__ int cnt;
-    for (int base = blockIdx.x * kThreads; base < nblk; base += gridDim.x * kThreads) {
+    for (int k0 = 0; blockIdx.x + k0 * gridDim.x < nblk; k0 += kThreads) {
       if (threadIdx.x == 0) cnt = 0;
       __syncthreads();
-      const int lb = base + (int)threadIdx.x;
+      const int lb = blockIdx.x + (k0 + (int)threadIdx.x) * gridDim.x;
       if (lb < nblk) {
-        const uint4 *w = reinterpret_cast<const uint4 *>(a.retry_mask + (size_t)lb * (kThreads / 32));
+        const int blk = xcd_remap(lb, nblk);
+        const uint4 *w = reinterpret_cast<const uint4 *>(a.retry_mask + (size_t)blk * (kThreads / 32));
         const uint4 w0 = w[0], w1 = w[1];
-        if (w0.x | w0.y | w0.z | w0.w | w1.x | w1.y | w1.z | w1.w) list[atomicAdd(&cnt, 1)] = lb;
+        if (w0.x | w0.y | w0.z | w0.w | w1.x | w1.y | w1.z | w1.w) list[atomicAdd(&cnt, 1)] = blk;
       }
       __syncthreads();
       const int n = cnt;
