@@ -157,6 +157,40 @@ def test_fields_written_between_calls_are_read():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_cached_local_data_equals_recomputed():
+    """The float form's local step reads its data as the update formed it
+    while the penalty stays, and recomputes it from u and Lambda when the
+    adaptive rule changes the penalty (and at every call's start). Fourteen
+    iterations in one call against fourteen calls of one iteration each
+    (every local step recomputing): the same penalty sequence, with changes
+    during the run, and the same iterates up to float rounding (the null-mode
+    removal each call repeats moves u by rounding and flips float ulps of
+    the local data, which fourteen iterations carry to ~1e-8 in u); a stale
+    or wrongly formed cache moves them by the size of an iteration's change."""
+    shape = (16, 12, 24)
+    say("cached local data vs recomputed")
+    phase = M.random_two_phase(shape, 0.5, seed=41)
+    Fbar = M.random_fbar(0.04, seed=42)
+    u, F, L = random_state(shape, seed=43)
+    kw = dict(rho0=2.0, adapt_rho=1, rho_min=0.5, rho_max=200.0, mu_ref=4.0, tau=2.0,
+              div_growth=0.0, stall_iters=0)
+    out = []
+    for calls in ([14], [1] * 14):
+        s = gpu_solver([phase], MATS, [Fbar], "fp32", **kw)
+        s.set_state(0, u=u, F=F, Lambda=L)
+        for n in calls:
+            s.step(n)
+        out.append((s.state(0), s.history(0)[2]))
+        s.close()
+    (a, rho_a), (b, rho_b) = out
+    say("  rho sequence", rho_a)
+    assert len(set(rho_a.tolist())) >= 2  # the penalty changed during the run
+    assert np.array_equal(rho_a, rho_b)
+    du, dF, dL = rel(a["u"], b["u"]), rel(a["F"], b["F"]), rel(a["Lambda"], b["Lambda"])
+    say("  apart: u", du, "F", dF, "Lambda", dL)
+    assert du <= 1e-7 and dF <= 1e-6 and dL <= 1e-5
+
+
 @pytest.mark.parametrize("shape", SHAPES[:3])
 def test_update_matches_definition(shape):
     say("update", shape)
