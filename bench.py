@@ -71,7 +71,7 @@ def iteration_bytes_alg(s, c, forward_components=9, u_bytes=None):
     """Minimum bytes per voxel-iteration of the method: the state once in and
     out (u_{i+1}, u_i, F, Lambda in; F, Lambda, u out: 45 scalars) plus one HBM
     round trip of the forward and of the inverse spectrum. With 9 forward
-    components and u in s-byte scalars this is the survey's basis,
+    components and u in s-byte scalars this is the plain method's count,
     s (45 + 48 c) + 1 (277.75 B in float at 256^3); this design forms the
     right-hand side of Step 2 as a divergence in real space (3 forward
     components) and keeps u in double (u_bytes = 8)."""
@@ -591,7 +591,7 @@ def main():
             "alg_bytes_per_launch": bytes_launch, "avg_ms": avg_ms}
     b_sv = iteration_bytes_alg(4, c, 9)
     b_it = iteration_bytes_alg(4, c, 3, u_bytes=8)
-    it_roof = {"basis": "survey: s (45 + 48 c) + 1 bytes per voxel-iteration",
+    it_roof = {"basis": "plain method: s (45 + 48 c) + 1 bytes per voxel-iteration",
                "bytes_per_voxel_iteration": b_sv,
                "achieved_GBs": b_sv * f32["value"] / 1e9,
                "frac": b_sv * f32["value"] / (HBM_PEAK_GBS * 1e9),
