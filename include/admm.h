@@ -140,7 +140,14 @@ typedef struct {
   int32_t max_iter;     /* iteration cap of admm_solve */
   int32_t check_every;  /* admm_solve: iterations between host checks; also
                            the length of the captured graph (10) */
-  int32_t newton_max;   /* local Newton iteration cap (100) */
+  int32_t newton_max;   /* local Newton iteration cap (100). In
+                           ADMM_FP32_FP64RED without an inexact strategy the
+                           neo-Hookean local problem is solved in closed form
+                           up to one scalar (the minimiser is coaxial with the
+                           data; Sec. 2.1, Step 1), whose Newton iteration this
+                           also caps; newton_gtol and newton_step_tol apply
+                           where that form does not (det of the data <= 0),
+                           to the LCE and to the double precision mode. */
   int32_t use_graph;    /* 1: admm_step / admm_solve replay check_every
                            iterations as one captured hipGraph (built on
                            first use, kept by the context); 0: launch every
