@@ -46,13 +46,14 @@ def kernel_bytes_per_voxel(s, c):
     costs 2 c s per voxel). u is double in both forms; the float form solves
     Step 2 for the correction du (float), formed into u by the update. The
     float form without LCE phases (the fibre cell) also has the update store
-    the next local step's data A - I (9 float), which that step reads at an
-    unchanged penalty (every iteration of a call but its first) in place of
-    u and Lambda."""
+    the next local step's data A - I (9 float) and the det F - 1 of its warm
+    start (1 float), which that step reads at an unchanged penalty (every
+    iteration of a call but its first) in place of u, Lambda and F."""
     f32 = s == 4
     return {
-        # float: A - I 9, F 9, phase in; F 9 out. double: u 3, F 9, Lambda 9, phase in
-        "local": 27 * s + 1 if f32 else 3 * 8 + 27 * s + 1,
+        # float: A - I 9, det F - 1 of the warm start 1, phase in; F 9 out.
+        # double: u 3, F 9, Lambda 9, phase in; F 9 out
+        "local": 19 * s + 1 if f32 else 3 * 8 + 27 * s + 1,
         # F 9, Lambda 9 (and u 3 for the float form's defect) in; 3 half spectra out
         "div_fwdx": 18 * s + (3 * 8 if f32 else 0) + 6 * c * s,
         "fft_y_fwd": 12 * c * s,         # 3 components in and out
@@ -60,8 +61,8 @@ def kernel_bytes_per_voxel(s, c):
         "fft_y_inv": 12 * c * s,
         "inv_x": 6 * c * s + 3 * s if f32 else 6 * c * s + 3 * 8,  # spectra in; du or u out
         # u_i 3 (double) and du 3 in, u_{i+1} 3 out (float form) or u_{i+1}, u_i in;
-        # F 9, Lambda 9 in; Lambda 9 out (float form: and A - I 9 out)
-        "update": (3 * 8 + 3 * s + 3 * 8 + 9 * s if f32 else 6 * 8) + 27 * s,
+        # F 9, Lambda 9 in; Lambda 9 out (float form: and A - I 9, det F - 1 1 out)
+        "update": (3 * 8 + 3 * s + 3 * 8 + 10 * s if f32 else 6 * 8) + 27 * s,
         "finalize": 0.0,
         "mean_stress": 18 * s + 1,
     }

@@ -77,7 +77,9 @@ struct RveDesc {
   void *At;                 // float form without LCE phases: Step 1's data
                             // A - I = grad u + Ebar + Lambda/rho of the next
                             // iteration as the update formed it (9V float),
-                            // valid while RveState::at_rho is the penalty; else null
+                            // then the warm start's det F - 1 (V float, in
+                            // warm_code's form), valid while RveState::at_rho
+                            // is the penalty; else null
 };
 
 // per-cell iteration state, updated on the device
@@ -101,7 +103,10 @@ struct RveState {
   int ref_iter;         // divergence watch: iteration of the last halving
   int n_retry;          // voxels the exact local pass left to its retry pass
                         // (cleared by k_finalize)
-  int pad3;
+  int at_div;           // 1: RveDesc::At holds Step 1's data of the current
+                        // fields and penalty (the local step read or formed
+                        // it), which Step 2 then reads; cleared by k_finalize
+                        // and by every state upload
   double best_merit;    // divergence watch: smallest merit of the load step
   double ref_merit;     // divergence watch: merit at ref_iter
   double at_rho;        // penalty RveDesc::At was formed with by the last

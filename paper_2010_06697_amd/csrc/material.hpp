@@ -507,26 +507,38 @@ __device__ __forceinline__ double log1p_near1_nr(double x) {
   return log1p(x);
 }
 
+// det(I + E) - 1 of the warm start F = I + E, by kinematics()'s formulas
+// (admissibility decided as the point evaluations decide it), without the
+// cofactor
 template <typename TG>
-__device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho, int maxit,
-                          double tol) {
-  // det of the warm start F = I + E, minus 1, by kinematics()'s formulas
-  // (admissibility decided as the point evaluations decide it), without the
-  // cofactor
-  double jm1w;
-  {
-    double e[9];
+__device__ __forceinline__ double warm_jm1(const TG *E) {
+  double e[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) e[k] = (double)E[k];
-    const double c0 = e[4] * e[8] - e[5] * e[7];
-    const double c1 = e[5] * e[6] - e[3] * e[8];
-    const double c2 = e[3] * e[7] - e[4] * e[6];
-    const double c4 = e[0] * e[8] - e[2] * e[6];
-    const double c8 = e[0] * e[4] - e[1] * e[3];
-    const double tr = e[0] + e[4] + e[8];
-    jm1w = tr + ((c0 + c4 + c8) + (e[0] * c0 + e[1] * c1 + e[2] * c2));
-    if (!(1.0 + jm1w > 0.0)) return -2;
-  }
+  for (int k = 0; k < 9; ++k) e[k] = (double)E[k];
+  const double c0 = e[4] * e[8] - e[5] * e[7];
+  const double c1 = e[5] * e[6] - e[3] * e[8];
+  const double c2 = e[3] * e[7] - e[4] * e[6];
+  const double c4 = e[0] * e[8] - e[2] * e[6];
+  const double c8 = e[0] * e[4] - e[1] * e[3];
+  const double tr = e[0] + e[4] + e[8];
+  return tr + ((c0 + c4 + c8) + (e[0] * c0 + e[1] * c1 + e[2] * c2));
+}
+
+// warm_jm1 as one float that keeps both of its uses: NaN where the warm
+// start is inadmissible, else the nearest float above -1 (the closed form
+// tests 1 + j > 0 and starts its scalar iteration from the float value)
+__device__ __forceinline__ float warm_code(double jm1) {
+  if (!(1.0 + jm1 > 0.0)) return __builtin_nanf("");
+  const float f = (float)jm1;
+  return f > -1.0f ? f : -0x1.fffffep-1f;
+}
+
+// E: out (written only when the return value is >= 0); jw: warm_code of
+// det(I + E) - 1 of the warm start
+template <typename TG>
+__device__ int neo_closed(TG *E, const TG *At, float jw, double mu, double lam, double rho,
+                          int maxit, double tol) {
+  if (!(1.0 + (double)jw > 0.0)) return -2;
   double a[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) a[k] = (double)At[k];
@@ -583,7 +595,7 @@ __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho
   const double x1 = 1.0 + e1, x2 = 1.0 + e2, x3 = 1.0 + e3;
   if (!(x3 > 0.0)) return -3;
   const double m = mu + rho, r2 = rho * rho;
-  const double xs[3] = {x1, x2, x3}, es[3] = {e1, e2, e3};
+  const double es[3] = {e1, e2, e3};
   const double ixd[3] = {rcp_nr(x1), rcp_nr(x2), rcp_nr(x3)};
   const double ghi = mu + r2 * x3 / (4.0 * m);  // S(x_3) real up to here
   // gamma to float accuracy by Newton's method in float (hardware
@@ -600,7 +612,7 @@ __device__ int neo_closed(TG *E, const TG *At, double mu, double lam, double rho
   }
   constexpr float kLn2 = 0.69314718f;
   float lo = -INFINITY, hi = (float)ghi;
-  float gam = fminf(lamf * kLn2 * __builtin_amdgcn_logf(1.0f + (float)jm1w), 0.5f * hi);
+  float gam = fminf(lamf * kLn2 * __builtin_amdgcn_logf(1.0f + jw), 0.5f * hi);
   int it = 0;
   bool done = false;
   for (; it < maxit; ++it) {

@@ -157,6 +157,35 @@ def test_fields_written_between_calls_are_read():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_projection_after_iterations_reads_the_fields():
+    """Within a call the float form's Step 2 forms its right-hand side from
+    Step 1's data A - I as the local step left it; a projection called on
+    its own must form it from the fields the caller holds. Four iterations,
+    new u, F and Lambda written, one projection: bit for bit the projection
+    of a fresh context started from those fields."""
+    shape = (16, 12, 24)
+    say("projection after iterations")
+    phase = M.random_two_phase(shape, 0.5, seed=35)
+    Fbar = M.random_fbar(0.04, seed=36)
+    u1, F1, L1 = random_state(shape, seed=37)
+    u2, F2, L2 = random_state(shape, seed=38)
+    kw = dict(rho0=6.0, adapt_rho=0, mu_ref=4.0, div_growth=0.0, stall_iters=0)
+    s = gpu_solver([phase], MATS, [Fbar], "fp32", **kw)
+    s.set_state(0, u=u1, F=F1, Lambda=L1)
+    s.step(4)
+    s.set_state(0, u=u2, F=F2, Lambda=L2)
+    s.project_step()
+    a = s.state(0)["u_prev"]  # the projection's u_{i+1}
+    s.close()
+    s = gpu_solver([phase], MATS, [Fbar], "fp32", **kw)
+    s.set_state(0, u=u2, F=F2, Lambda=L2)
+    s.project_step()
+    b = s.state(0)["u_prev"]
+    s.close()
+    assert np.array_equal(a, b)
+    assert rel(a, O.project(F2 - L2 / 6.0)) <= 2e-5
+
+
 def test_cached_local_data_equals_recomputed():
     """The float form's local step reads its data as the update formed it
     while the penalty stays, and recomputes it from u and Lambda when the
