@@ -48,14 +48,16 @@ def kernel_bytes_per_voxel(s, c):
     float form without LCE phases (the fibre cell) also has the update store
     the next local step's data A - I (9 float) and the det F - 1 of its warm
     start (1 float), which that step reads at an unchanged penalty (every
-    iteration of a call but its first) in place of u, Lambda and F."""
+    iteration of a call but its first) in place of u, Lambda and F; and the
+    local step store F - A (9 float), from which Step 2 forms its defect in
+    place of F, Lambda and u."""
     f32 = s == 4
     return {
-        # float: A - I 9, det F - 1 of the warm start 1, phase in; F 9 out.
+        # float: A - I 9, det F - 1 of the warm start 1, phase in; F 9, F - A 9 out.
         # double: u 3, F 9, Lambda 9, phase in; F 9 out
-        "local": 19 * s + 1 if f32 else 3 * 8 + 27 * s + 1,
-        # F 9, Lambda 9 (and u 3 for the float form's defect) in; 3 half spectra out
-        "div_fwdx": 18 * s + (3 * 8 if f32 else 0) + 6 * c * s,
+        "local": 28 * s + 1 if f32 else 3 * 8 + 27 * s + 1,
+        # float: F - A 9 in; double: F 9, Lambda 9 in; 3 half spectra out
+        "div_fwdx": (9 * s if f32 else 18 * s) + 6 * c * s,
         "fft_y_fwd": 12 * c * s,         # 3 components in and out
         "poisson_z": 12 * c * s,
         "fft_y_inv": 12 * c * s,

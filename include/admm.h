@@ -216,10 +216,10 @@ size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precisi
  * The penalty of every cell starts at params->rho0, the iteration count at 0.
  * The fields are used as given (the caller zeroes u, F - I and Lambda for a
  * fresh start). In ADMM_FP32_FP64RED without LCE materials or nu_F the
- * context also allocates 40 bytes per voxel for the local step's data as
- * the multiplier update forms it (reused by the next iteration of the same
- * call; every call reads the fields afresh, so the caller may write them
- * between calls). Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOGPU. */
+ * context also allocates 76 bytes per voxel: the local step's data as the
+ * multiplier update forms it and F - A as the local step leaves it for
+ * Step 2 (reused within one call; every call reads the fields afresh, so
+ * the caller may write them between calls). Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOGPU. */
 int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve,
               const admm_material *mats, int32_t n_mat, const admm_params *params,
               int32_t precision, void *workspace, size_t workspace_bytes,

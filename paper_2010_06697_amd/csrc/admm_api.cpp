@@ -294,11 +294,11 @@ int snapshot_step(admm_ctx *c) {
   return ADMM_OK;
 }
 
-int upload_states(admm_ctx *c, int at_div = 0) {
+int upload_states(admm_ctx *c, int q_cur = 0) {
   for (auto &s : c->state_h) {
     s.at_rho = 0.0;  // Step 1 reads the caller's fields
     s.n_retry = 0;   // (no retry bit survives a retry pass)
-    s.at_div = at_div;  // and Step 2 too, unless told otherwise
+    s.q_cur = q_cur;  // and Step 2 too, unless told otherwise
   }
   HIP_TRY(hipMemcpyAsync(c->state_d, c->state_h.data(), sizeof(RveState) * c->n_rve,
                          hipMemcpyHostToDevice, c->stream));
@@ -983,15 +983,18 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   // float form without LCE phases or dissipation of F: Step 1's data as the
   // update forms it (9 floats per voxel) and det F - 1 of the local step's
   // warm start (one float), read by the next local step at the same penalty
-  // instead of the stencil gradient of u, Lambda and F
+  // instead of the stencil gradient of u, Lambda and F; and F - A as the
+  // local step leaves it (9 floats), read by Step 2 instead of F, Lambda
+  // and u
   if (!fp64 && !any_lce && !any_ext) {
     size_t tot = 0;
-    for (const RveDesc &D : c->desc_h) tot += 10 * (size_t)D.V;
+    for (const RveDesc &D : c->desc_h) tot += 19 * (size_t)D.V;
     INIT_TRY(hipMalloc(&c->at_d, tot * sizeof(float)));
     size_t off = 0;
     for (RveDesc &D : c->desc_h) {
       D.At = static_cast<float *>(c->at_d) + off;
-      off += 10 * (size_t)D.V;
+      D.Q = static_cast<float *>(c->at_d) + off + 10 * (size_t)D.V;
+      off += 19 * (size_t)D.V;
     }
   }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
@@ -1447,9 +1450,9 @@ int admm_autotune(admm_ctx *ctx, int32_t reps, admm_tuning *out) {
     ctx->L.timer = nullptr;
     const std::vector<RveState> saved = ctx->state_h;
     for (auto &s : ctx->state_h) s.active = 1;  // Step 2 skips inactive cells
-    // Step 2 timed in the form the iterations run it: reading Step 1's data
-    // where the context holds it (the spectra and correction it computes
-    // are scratch, overwritten by the next iteration)
+    // Step 2 timed in the form the iterations run it: reading the local
+    // step's F - A where the context holds it (the spectra and correction
+    // it computes are scratch, overwritten by the next iteration)
     rc = upload_states(ctx, ctx->at_d ? 1 : 0);
     if (rc == ADMM_OK) rc = tune(ctx, reps, out);
     ctx->state_h = saved;

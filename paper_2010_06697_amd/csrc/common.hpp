@@ -80,6 +80,8 @@ struct RveDesc {
                             // then the warm start's det F - 1 (V float, in
                             // warm_code's form), valid while RveState::at_rho
                             // is the penalty; else null
+  void *Q;                  // with At: F - A of the last local pass (9V
+                            // float), whose D_h^T is Step 2's defect; else null
 };
 
 // per-cell iteration state, updated on the device
@@ -103,10 +105,10 @@ struct RveState {
   int ref_iter;         // divergence watch: iteration of the last halving
   int n_retry;          // voxels the exact local pass left to its retry pass
                         // (cleared by k_finalize)
-  int at_div;           // 1: RveDesc::At holds Step 1's data of the current
-                        // fields and penalty (the local step read or formed
-                        // it), which Step 2 then reads; cleared by k_finalize
-                        // and by every state upload
+  int q_cur;           // 1: RveDesc::Q holds F - A of the current fields
+                        // and penalty (the local step of this iteration
+                        // wrote it), which Step 2 then reads; cleared by
+                        // k_finalize and by every state upload
   double best_merit;    // divergence watch: smallest merit of the load step
   double ref_merit;     // divergence watch: merit at ref_iter
   double at_rho;        // penalty RveDesc::At was formed with by the last

@@ -204,11 +204,11 @@ enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry 
 static_assert(kThreads / 32 == 8, "the retry pass reads a workgroup's bits as two uint4");
 template <typename T, int LK, int MODE>
 constexpr bool kClosedOnly = MODE == kLocalExact && kDefect<T> && LK == 0;
-// the passes that leave RveDesc::At current for the divergence that follows
-// (when the context holds it): they read it where the update formed it at
-// this penalty and write it where they form it themselves
+// the passes over every voxel in the float form without LCE phases: they
+// read Step 1's data where the update formed it at this penalty, and their
+// F - A (RveDesc::Q, written by every pass) is what Step 2 then reads
 template <typename T, int LK, int MODE>
-constexpr bool kAtPass = kDefect<T> && LK == 0 && (MODE == kLocalExact || MODE == kLocalFirst);
+constexpr bool kFullPass = kDefect<T> && LK == 0 && (MODE == kLocalExact || MODE == kLocalFirst);
 
 // LK: 0 no LCE phase, 1 the ideal LCE, 2 some term of the full LCE model
 // (non-ideality, Frank, dissipation) or the dissipation of F
@@ -245,7 +245,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     T E[9], At[9];
     float jw = 0.0f;  // warm_code of the warm start's det F - 1 (closed form)
-    if (kAtPass<T, LK, MODE> && D.At && st->at_rho == rho0) {
+    if (kFullPass<T, LK, MODE> && D.At && st->at_rho == rho0) {
       // the update formed this data at this penalty, from the same values,
       // and the warm start's det F - 1 beside it: the closed form does not
       // read F itself
@@ -267,14 +267,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
       }
       if (MODE == kLocalExact && kDefect<T>) jw = warm_code(warm_jm1(E));
-      if (kAtPass<T, LK, MODE> && D.At) {
-        const auto Ag = global_view(static_cast<T *>(D.At));
-#pragma unroll
-        for (int c = 0; c < 9; ++c) Ag[c * V + idx] = At[c];
-      }
     }
-    // (every workgroup of the cell stores the same flag; Step 2 reads it)
-    if (kAtPass<T, LK, MODE> && D.At && t == 0) st->at_div = 1;
     const auto phg = global_view(D.phase);
     const int ph = phg[idx];
     if (ph < a.n_mat) {
@@ -403,14 +396,31 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
       lsum[1] = rc >= 0 ? 1.0 : 0.0;
       n_fail = rc == -1 && !inexact;  // a pass that ends at its cap is no failure
       if (rc == -2) atomicOr(&st->domain_err, 1);
-      // (the closed form alone leaves F as it was where it returns no point)
-      if (!deferred && !(kClosedOnly<T, LK, MODE> && rc < 0))
+      if (!deferred) {
+        if (kClosedOnly<T, LK, MODE> && rc < 0) {
+          // the closed form returned no point: F stays as it was
 #pragma unroll
-        for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
+          for (int c = 0; c < 9; ++c) E[c] = Eg[c * V + idx];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) Eg[c * V + idx] = E[c];
+        }
+      }
     } else {
       atomicOr(&st->domain_err, 2);  // invalid phase index
+#pragma unroll
+      for (int c = 0; c < 9; ++c) E[c] = Eg[c * V + idx];
+    }
+    // Step 2's field F - A of every voxel this pass settled (the retry pass
+    // writes those it takes over)
+    if (kDefect<T> && LK == 0 && D.Q && !deferred) {
+      const auto Qg = global_view(static_cast<T *>(D.Q));
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Qg[c * V + idx] = (T)((double)E[c] - (double)At[c]);
     }
   }
+  // (every workgroup of the cell stores the same flag; Step 2 reads it)
+  if (kFullPass<T, LK, MODE> && D.Q && t == 0) st->q_cur = 1;
   // local residual of the inexact passes: one sum per workgroup (a fence
   // and arrival counter per workgroup, to let the last one decide, cost
   // more than a separate one-workgroup-per-cell kernel: the agent-scope
@@ -736,21 +746,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 6))
     const T *Lg = static_cast<const T *>(D.Lam);
     // float form: the defect D_h^T (H - D_h u_i), in double, whose solve is
     // the correction u_{i+1} - u_i (the transforms' float rounding then
-    // scales with the correction, not with u itself). Where the context
-    // holds Step 1's data A - I = D_h u_i + Ebar + Lambda/rho (current: the
-    // local step just read or formed it), H - D_h u_i = F - A + Ebar, and
-    // D_h^T of the constant Ebar vanishes: the defect is D_h^T (E - At).
-    if (kDefect<T> && D.At && st->at_div) {
-      const T *Ag = static_cast<const T *>(D.At);
+    // scales with the correction, not with u itself). With Step 1's data
+    // A = I + D_h u_i + Ebar + Lambda/rho, H - D_h u_i = F - A + Ebar, and
+    // D_h^T of the constant Ebar vanishes: where the local step of this
+    // iteration left Q = F - A, the defect is D_h^T Q.
+    if (kDefect<T> && D.Q && st->q_cur) {
+      const T *Qg = static_cast<const T *>(D.Q);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         double bi = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           const int c = (3 * i + j) * V;
-          const double hp = (double)Eg[c + sn.o[2 * j]] - (double)Ag[c + sn.o[2 * j]];
-          const double hm = (double)Eg[c + sn.o[2 * j + 1]] - (double)Ag[c + sn.o[2 * j + 1]];
-          bi -= 0.5 * (hp - hm);
+          bi -= 0.5 * ((double)Qg[c + sn.o[2 * j]] - (double)Qg[c + sn.o[2 * j + 1]]);
         }
         const int ell = i * R + row;
         T *z = reinterpret_cast<T *>(za + (ell >> 1) * n1 + x1) + (ell & 1);
@@ -1612,7 +1620,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KernelArgs a, IterParams 
   st->rho_used = rho;
   st->at_rho = a.desc[r].At ? rho : 0.0;
   st->n_retry = 0;  // the local step's retry pass has run
-  st->at_div = 0;   // the next local step decides
+  st->q_cur = 0;   // the next local step decides
   st->iter = it + 1;
   st->cur ^= 1;
   if (st->domain_err || !(rp == rp) || !(rd == rd)) {
