@@ -215,11 +215,12 @@ size_t admm_workspace_bytes(const admm_rve *rves, int32_t n_rve, int32_t precisi
  *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
  * The penalty of every cell starts at params->rho0, the iteration count at 0.
  * The fields are used as given (the caller zeroes u, F - I and Lambda for a
- * fresh start). In ADMM_FP32_FP64RED without LCE materials or nu_F the
- * context also allocates 76 bytes per voxel: the local step's data as the
- * multiplier update forms it and F - A as the local step leaves it for
- * Step 2 (reused within one call; every call reads the fields afresh, so
- * the caller may write them between calls). Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOGPU. */
+ * fresh start). In ADMM_FP32_FP64RED without nu_F or the full LCE model's
+ * terms the context also allocates 36 bytes per voxel for F - A as the
+ * local step leaves it for Step 2, and without LCE materials 40 more for
+ * the local step's data as the multiplier update forms it (reused within
+ * one call; every call reads the fields afresh, so the caller may write
+ * them between calls). Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOGPU. */
 int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve,
               const admm_material *mats, int32_t n_mat, const admm_params *params,
               int32_t precision, void *workspace, size_t workspace_bytes,

@@ -980,21 +980,23 @@ int admm_init(admm_ctx **out, const admm_rve *rves, int32_t n_rve, const admm_ma
   // the spectra's padding columns stay zero: no kernel writes them but the
   // x3 pass, which maps zero to zero there
   INIT_TRY(hipMemset(c->workspace, 0, spec_off));
-  // float form without LCE phases or dissipation of F: Step 1's data as the
-  // update forms it (9 floats per voxel) and det F - 1 of the local step's
-  // warm start (one float), read by the next local step at the same penalty
-  // instead of the stencil gradient of u, Lambda and F; and F - A as the
-  // local step leaves it (9 floats), read by Step 2 instead of F, Lambda
-  // and u
-  if (!fp64 && !any_lce && !any_ext) {
+  // float form without the full LCE model's terms or dissipation of F:
+  // F - A as the local step leaves it (9 floats per voxel), read by Step 2
+  // instead of F, Lambda and u; without LCE phases also Step 1's data as the
+  // update forms it (9 floats) and det F - 1 of the local step's warm start
+  // (one float), read by the next local step at the same penalty instead of
+  // the stencil gradient of u, Lambda and F
+  if (!fp64 && !any_ext) {
+    const size_t per = any_lce ? 9 : 19;
     size_t tot = 0;
-    for (const RveDesc &D : c->desc_h) tot += 19 * (size_t)D.V;
+    for (const RveDesc &D : c->desc_h) tot += per * (size_t)D.V;
     INIT_TRY(hipMalloc(&c->at_d, tot * sizeof(float)));
     size_t off = 0;
     for (RveDesc &D : c->desc_h) {
-      D.At = static_cast<float *>(c->at_d) + off;
-      D.Q = static_cast<float *>(c->at_d) + off + 10 * (size_t)D.V;
-      off += 19 * (size_t)D.V;
+      float *base = static_cast<float *>(c->at_d) + off;
+      if (!any_lce) D.At = base;
+      D.Q = base + (any_lce ? 0 : 10 * (size_t)D.V);
+      off += per * (size_t)D.V;
     }
   }
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);

@@ -80,8 +80,9 @@ struct RveDesc {
                             // then the warm start's det F - 1 (V float, in
                             // warm_code's form), valid while RveState::at_rho
                             // is the penalty; else null
-  void *Q;                  // with At: F - A of the last local pass (9V
-                            // float), whose D_h^T is Step 2's defect; else null
+  void *Q;                  // float form without the full LCE model's terms:
+                            // F - A of the last local pass (9V float), whose
+                            // D_h^T is Step 2's defect; else null
 };
 
 // per-cell iteration state, updated on the device

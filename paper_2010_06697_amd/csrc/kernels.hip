@@ -9,9 +9,12 @@
 // leaves three components to transform instead of nine.
 //
 // Per iteration, over every active cell of the batch, in this order:
-//   k_local        Step 1: the local Newton solve per voxel (F)
-//   k_div_fwdx     b = D_h^T (F - Lambda/rho) and its forward real-to-complex
-//                  FFT along x1 (two real rows per complex transform)
+//   k_local        Step 1: the local solve per voxel (F; in the float form
+//                  without the full LCE model's terms also F - A for Step 2)
+//   k_div_fwdx     b = D_h^T (F - Lambda/rho) (float form: the defect
+//                  D_h^T (F - A), whose solve is u_{i+1} - u_i) and its
+//                  forward real-to-complex FFT along x1 (two real rows per
+//                  complex transform)
 //   k_fft_y        forward FFT along x2 of the three components
 //   k_poisson_z    forward FFT along x3, u_hat = b_hat / (|K|^2 V) (zero on
 //                  the eight modes where every K_j vanishes), inverse along x3
@@ -204,11 +207,12 @@ enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry 
 static_assert(kThreads / 32 == 8, "the retry pass reads a workgroup's bits as two uint4");
 template <typename T, int LK, int MODE>
 constexpr bool kClosedOnly = MODE == kLocalExact && kDefect<T> && LK == 0;
-// the passes over every voxel in the float form without LCE phases: they
-// read Step 1's data where the update formed it at this penalty, and their
-// F - A (RveDesc::Q, written by every pass) is what Step 2 then reads
+// the passes over every voxel in the float form without the full LCE
+// model's terms: their F - A (RveDesc::Q, written by every pass) is what
+// Step 2 then reads; without LCE phases they read Step 1's data where the
+// update formed it at this penalty (RveDesc::At)
 template <typename T, int LK, int MODE>
-constexpr bool kFullPass = kDefect<T> && LK == 0 && (MODE == kLocalExact || MODE == kLocalFirst);
+constexpr bool kFullPass = kDefect<T> && LK <= 1 && (MODE == kLocalExact || MODE == kLocalFirst);
 
 // LK: 0 no LCE phase, 1 the ideal LCE, 2 some term of the full LCE model
 // (non-ideality, Frank, dissipation) or the dissipation of F
@@ -245,7 +249,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     const Stencil sn = stencil(n1, n2, n3, x1, x2, x3);
     T E[9], At[9];
     float jw = 0.0f;  // warm_code of the warm start's det F - 1 (closed form)
-    if (kFullPass<T, LK, MODE> && D.At && st->at_rho == rho0) {
+    if (kFullPass<T, LK, MODE> && LK == 0 && D.At && st->at_rho == rho0) {
       // the update formed this data at this penalty, from the same values,
       // and the warm start's det F - 1 beside it: the closed form does not
       // read F itself
@@ -413,7 +417,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
     }
     // Step 2's field F - A of every voxel this pass settled (the retry pass
     // writes those it takes over)
-    if (kDefect<T> && LK == 0 && D.Q && !deferred) {
+    if (kDefect<T> && LK <= 1 && D.Q && !deferred) {
       const auto Qg = global_view(static_cast<T *>(D.Q));
 #pragma unroll
       for (int c = 0; c < 9; ++c) Qg[c * V + idx] = (T)((double)E[c] - (double)At[c]);
