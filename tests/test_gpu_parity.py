@@ -159,10 +159,11 @@ def test_fields_written_between_calls_are_read():
 
 def test_projection_after_iterations_reads_the_fields():
     """Within a call the float form's Step 2 forms its right-hand side from
-    Step 1's data A - I as the local step left it; a projection called on
-    its own must form it from the fields the caller holds. Four iterations,
-    new u, F and Lambda written, one projection: bit for bit the projection
-    of a fresh context started from those fields."""
+    the field F - A that the local step of the iteration left; a projection
+    called on its own must form it from the fields the caller holds. Four
+    iterations, new u, F and Lambda written, one projection: bit for bit
+    the projection of a fresh context started from those fields, and the
+    oracle's projection of them."""
     shape = (16, 12, 24)
     say("projection after iterations")
     phase = M.random_two_phase(shape, 0.5, seed=35)
