@@ -270,7 +270,7 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         E[c] = Eg[c * V + idx];
         At[c] = (T)(A[c] + st->Ebar[c] + (double)Lg[c * V + idx] * irho);
       }
-      if (MODE == kLocalExact && kDefect<T>) jw = warm_code(warm_jm1(E));
+      if (MODE == kLocalExact) jw = warm_code(warm_jm1(E));
     }
     const auto phg = global_view(D.phase);
     const int ph = phg[idx];
@@ -378,11 +378,14 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
         NeoHooke<T> M;
         M.mu = (T)m.mu;
         M.lam = (T)m.lam;
-        // float form, exact mode: the minimiser up to one scalar; the
-        // nine-component Newton where that form does not apply, in the
-        // retry pass when the closed form is compiled alone
+        // exact mode: the minimiser up to one scalar; the nine-component
+        // Newton where that form does not apply (in the retry pass when the
+        // closed form is compiled alone). In the double form the closed
+        // form's point (about 1e-12 relative, least accurate along
+        // rotations, where the objective is only rho-stiff and Newton's
+        // stopping test would accept it) is finished by one full Newton step.
         rc = -3;
-        if (MODE == kLocalExact && kDefect<T>)
+        if (MODE == kLocalExact)
           rc = neo_closed<T>(E, At, jw, m.mu, m.lam, rho, cap, 1e-5);
         if (kClosedOnly<T, LK, MODE>) {
           if (rc == -3) {
@@ -391,9 +394,11 @@ __device__ __forceinline__ void local_tile(KernelArgs a, IterParams ip, int pass
             deferred = true;
             rc = 0;
           }
-        } else if (rc == -3) {
-          rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol,
-                             MODE == kLocalExact || MODE == kLocalRetry ? nullptr : &lsum[0]);
+        } else {
+          if (!kDefect<T> && rc >= 0) rc = newton_polish<T, T>(E, At, M, (T)rho) ? rc + 1 : -3;
+          if (rc == -3)
+            rc = newton<T, T>(E, At, M, (T)rho, cap, ip.gtol, ip.step_tol,
+                               MODE == kLocalExact || MODE == kLocalRetry ? nullptr : &lsum[0]);
         }
         n_its = rc >= 0 ? rc : cap;
       }

@@ -288,8 +288,10 @@ template <typename TG> __device__ __forceinline__ bool admissible(const TG *E) {
 }
 
 // The iterations of newton() from the point s at E; on exit s is the point
-// of the returned iterate when KEEP is set (otherwise it may be stale).
-template <typename TG, typename TH, bool KEEP, typename M>
+// of the returned iterate when KEEP is set (otherwise it may be stale). ONE:
+// a single full Newton step, no stopping test and no line search (returns 1,
+// or -1 with E unchanged where the tangent is not positive definite).
+template <typename TG, typename TH, bool KEEP, typename M, bool ONE = false>
 __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
                            double step_tol, Point<TG> &s) {
   const double smod = m.smod() + (double)rho;
@@ -302,7 +304,7 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
   for (int it = 0; it < maxit; ++it) {
     const double nF2 = (double)norm2_ipx(E);
     const double thr = gtol * smod * (1.0 + sqrt(nF2) + nA);
-    if ((double)s.gn2 <= thr * thr) return it;
+    if (!ONE && (double)s.gn2 <= thr * thr) return it;
 
     // prox tangent, lower triangle packed, assembled in TH
     TH L[45], Gh[9], id[9];
@@ -358,6 +360,12 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) d[i] = -s.g[i];
+    }
+    if (ONE) {
+      if (!pd) return -1;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) E[k] += d[k];
+      return 1;
     }
 
     TG slope_t = (TG)0, nd2_t = (TG)0;
@@ -434,6 +442,16 @@ __device__ int newton_loop(TG *E, const TG *A, const M &m, TG rho, int maxit, do
 // up (E keeps the last accepted iterate; a second call with the remaining
 // budget continues the same iterates), -2 when det F <= 0 at the start.
 // g2 (optional) receives |grad phi|^2 at the returned iterate.
+// One full Newton step from E, for a point inside the region of quadratic
+// convergence (the closed form's): no line search. False (E unchanged) when
+// det F <= 0 at E or the tangent is not positive definite there.
+template <typename TG, typename TH, typename M>
+__device__ bool newton_polish(TG *E, const TG *A, const M &m, TG rho) {
+  Point<TG> s;
+  if (!m.point(E, A, rho, s)) return false;
+  return newton_loop<TG, TH, false, M, true>(E, A, m, rho, 1, 0.0, 0.0, s) == 1;
+}
+
 template <typename TG, typename TH, typename M>
 __device__ int newton(TG *E, const TG *A, const M &m, TG rho, int maxit, double gtol,
                       double step_tol, double *g2 = nullptr) {
