@@ -45,6 +45,22 @@ def rel(a, b):
 NEWTON64 = dict(gtol=1e-14, step_tol=1e-10)
 
 
+def prox_minimiser(mat, rho, A, Fw):
+    """The oracle's local-step minimiser (Sec. 2.1, Step 1) to rounding: its
+    Newton solve from the warm start Fw, continued from that point with a
+    gradient test of 1e-16 (the default 1e-14 test, scaled by the moduli
+    plus rho, accepts points up to about 1e-12 away along rotations, where
+    the objective is only rho-stiff). Where rounding keeps the continued
+    solve from meeting that test it still ends at its last accepted iterate,
+    which its line search keeps no worse than its start. Returns (F, rc) with
+    the status of the first solve."""
+    F, _, _, rc = O.prox(mat, rho, A, Fw, opts=O.newton_opts(**NEWTON64))
+    if rc != O.OK:
+        return F, rc
+    Fp, _, _, rc2 = O.prox(mat, rho, A, F, opts=O.newton_opts(gtol=1e-16, step_tol=1e-12))
+    return (Fp if rc2 in (O.OK, O.NOT_CONVERGED) else F), rc
+
+
 def oracle_iterations(phase, mats, Fbar, n_iter, rho, mu_ref, adapt=False, state=None,
                       rho_min=1.0, rho_max=50.0, **local):
     """n_iter fixed iterations of the oracle from `state` (default: the

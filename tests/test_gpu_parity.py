@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from paper_2010_06697_amd import admm, microstructure as M
-from parity_util import NEWTON64, gpu_solver, omats, oracle_iterations, random_state, rel
+from parity_util import NEWTON64, gpu_solver, omats, oracle_iterations, prox_minimiser, random_state, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -75,8 +75,7 @@ def test_local_step_matches_oracle(shape, precision):
     ref = np.empty_like(got)
     n3, n2, n1 = shape
     for x in np.ndindex(shape):
-        Fx, _, _, rc = O.prox(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x],
-                              opts=O.newton_opts(**NEWTON64))
+        Fx, rc = prox_minimiser(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x])
         assert rc == O.OK
         ref[(slice(None),) + x] = Fx
     err = np.max(np.abs(got - ref))
@@ -116,8 +115,7 @@ def test_local_step_with_negative_det_data(precision):
     om = omats(MATS)
     ref = np.empty_like(got)
     for x in np.ndindex(shape):
-        Fx, _, _, rc = O.prox(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x],
-                              opts=O.newton_opts(**NEWTON64))
+        Fx, rc = prox_minimiser(om[phase[x]], rho, A[(slice(None),) + x], st0["F"][(slice(None),) + x])
         assert rc == O.OK
         ref[(slice(None),) + x] = Fx
     detF = np.linalg.det(np.moveaxis(got.reshape((3, 3) + shape), (0, 1), (-2, -1)))
