@@ -201,8 +201,8 @@ __device__ __forceinline__ bool local_inexact(const IterParams &ip, const RveSta
 // the exact step's second pass over the problems its first pass left to the
 // nine-component Newton method (float form without LCE phases: the first
 // pass then compiles only the neo-Hookean closed form, at the registers
-// that need). The double form keeps the Newton solve, whose stopping rule
-// its parity bounds are set against.
+// that need). The double form finishes the closed form's point with one
+// full Newton step and runs the Newton solve where the closed form fails.
 enum LocalMode { kLocalExact = 0, kLocalFirst = 1, kLocalLater = 2, kLocalRetry = 3 };
 static_assert(kThreads / 32 == 8, "the retry pass reads a workgroup's bits as two uint4");
 template <typename T, int LK, int MODE>
